@@ -1,0 +1,211 @@
+"""Seeded synthetic inputs shared by the GPU library's callers and the oracle.
+
+This module holds grids, initial states and run parameters only: node
+coordinates, primitive fields turned into conserved variables, and the numbers
+a run needs (sizes, Reynolds and Mach numbers, time step).  It contains none of
+the numerical method, so both the GPU path and the CPU oracle can take their
+inputs from it without sharing any of the scheme.
+
+Workloads (paper: Dang et al., arXiv:2209.15333; the problems stand in for the
+paper's own flows, whose data are not public):
+  * Taylor-Green vortex on a uniform or sinusoidally distorted periodic grid;
+  * isentropic vortex advection (exact translated solution);
+  * Sod shock tube laid along any of the three directions;
+  * uniform flow on a distorted grid (free-stream preservation).
+Random numbers come from numpy's PCG64 with the stated seeds.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Tuple
+
+import numpy as np
+
+TWO_PI = 2.0 * math.pi
+
+
+@dataclasses.dataclass
+class Case:
+    """One run: grid, initial state and the physical / scheme parameters."""
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    xyz: np.ndarray                      # [3, nz, ny, nx] node coordinates
+    U0: np.ndarray                       # [5, nz, ny, nx] conserved rho, rho u, rho v, rho w, E
+    period: Tuple[float, float, float]   # coordinate d shifts by period[d] across the seam of direction d
+    h: Tuple[float, float, float]        # computational spacing per direction
+    dt: float
+    nsteps: int
+    periodic: Tuple[int, int, int] = (1, 1, 1)
+    bc: Tuple[int, int, int, int, int, int] = (0, 0, 0, 0, 0, 0)
+    gamma: float = 1.4
+    Re: float = 1600.0
+    Ma: float = 0.1
+    Pr: float = 0.72
+    Tref: float = 288.15
+    suth: float = 110.4
+    Tw: float = 1.0
+    theta1: float = 0.02
+    theta2: float = 0.1
+    eps: float = 1e-6
+    viscous: int = 6
+    scheme: str = "weno7"                # "weno7" | "hybrid"
+    lowdiss: str = "c8"                  # "ud7" | "c8"
+    three_way: bool = False
+    inflow: Optional[np.ndarray] = None
+
+    @property
+    def N(self) -> int:
+        return self.nx * self.ny * self.nz
+
+
+def conserved(gamma: float, rho, u, v, w, p) -> np.ndarray:
+    """Conserved variables from primitive fields (rho, velocity, pressure)."""
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v + w * w)
+    return np.ascontiguousarray(np.stack([rho, rho * u, rho * v, rho * w, E]).astype(np.float64))
+
+
+def _lattice(n: Tuple[int, int, int], L: Tuple[float, float, float]):
+    nx, ny, nz = n
+    X = np.arange(nx) * (L[0] / nx)
+    Y = np.arange(ny) * (L[1] / ny)
+    Z = np.arange(nz) * (L[2] / nz)
+    Zg, Yg, Xg = np.meshgrid(Z, Y, X, indexing="ij")
+    return Xg, Yg, Zg
+
+
+def distortion_phases(seed: int) -> np.ndarray:
+    """The nine phases of the sinusoidal grid distortion, uniform on [0, 2 pi)."""
+    return np.random.Generator(np.random.PCG64(seed)).uniform(0.0, TWO_PI, size=9)
+
+
+def periodic_grid(n: Tuple[int, int, int], L: Tuple[float, float, float],
+                  amplitude: float = 0.0, seed: int = 0) -> np.ndarray:
+    """Nodes of a periodic box, optionally with a smooth sinusoidal distortion.
+
+    x = X + A sin(2 pi X/Lx + p1) sin(2 pi Y/Ly + p2) sin(2 pi Z/Lz + p3), and
+    likewise for y (phases p4..p6) and z (p7..p9), with the nine phases drawn
+    uniformly from [0, 2 pi) by PCG64(seed).  The distortion is periodic, so
+    coordinate d still grows by exactly L[d] across the seam of direction d.
+    """
+    Xg, Yg, Zg = _lattice(n, L)
+    xyz = np.stack([Xg, Yg, Zg]).astype(np.float64)
+    if amplitude != 0.0:
+        ph = distortion_phases(seed)
+        sx = TWO_PI * Xg / L[0]
+        sy = TWO_PI * Yg / L[1]
+        sz = TWO_PI * Zg / L[2]
+        for c in range(3):
+            xyz[c] += amplitude * np.sin(sx + ph[3 * c]) * np.sin(sy + ph[3 * c + 1]) * np.sin(sz + ph[3 * c + 2])
+    return np.ascontiguousarray(xyz)
+
+
+def taylor_green(n: int = 32, distorted: bool = False, seed: int = 22092, Ma: float = 0.1,
+                 Re: float = 1600.0, dt: Optional[float] = None, nsteps: int = 20,
+                 shape: Optional[Tuple[int, int, int]] = None) -> Case:
+    """Taylor-Green vortex on [0, 2 pi)^3 (rho = 1, M = 0.1, Re = 1600, Pr = 0.72).
+
+    u = sin x cos y cos z, v = -cos x sin y cos z, w = 0,
+    p = 1/(gamma M^2) + (cos 2x + cos 2y)(cos 2z + 2)/16, evaluated at the
+    (possibly distorted) node positions.  Distortion amplitude 0.1 h.
+    """
+    nx, ny, nz = shape if shape is not None else (n, n, n)
+    L = (TWO_PI, TWO_PI, TWO_PI)
+    h = (L[0] / nx, L[1] / ny, L[2] / nz)
+    xyz = periodic_grid((nx, ny, nz), L, 0.1 * h[0] if distorted else 0.0, seed)
+    x, y, z = xyz
+    g = 1.4
+    rho = np.ones_like(x)
+    u = np.sin(x) * np.cos(y) * np.cos(z)
+    v = -np.cos(x) * np.sin(y) * np.cos(z)
+    w = np.zeros_like(x)
+    p = 1.0 / (g * Ma * Ma) + (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0) / 16.0
+    if dt is None:
+        dt = 1e-3 if nx <= 32 else 2.5e-4 * 256.0 / max(nx, ny, nz)
+    return Case(name=f"tgv{nx}x{ny}x{nz}{'-distorted' if distorted else ''}", nx=nx, ny=ny, nz=nz,
+                xyz=xyz, U0=conserved(g, rho, u, v, w, p), period=L, h=h, dt=dt, nsteps=nsteps,
+                gamma=g, Re=Re, Ma=Ma, viscous=6)
+
+
+def vortex_primitive(x, y, t: float, L: float = 20.0, strength: float = 5.0, Ma: float = 0.5,
+                     gamma: float = 1.4, center=(10.0, 10.0), advect=(1.0, 1.0)):
+    """Isentropic vortex in the paper's units (rho_inf = T_inf = 1, p_inf = 1/(gamma Ma^2)),
+    translated by advect*t, nearest periodic image of the centre."""
+    dx = x - center[0] - advect[0] * t
+    dy = y - center[1] - advect[1] * t
+    dx = dx - L * np.round(dx / L)
+    dy = dy - L * np.round(dy / L)
+    r2 = dx * dx + dy * dy
+    e = strength / TWO_PI * np.exp(0.5 * (1.0 - r2))
+    u = advect[0] - e * dy
+    v = advect[1] + e * dx
+    th_inf = 1.0 / (gamma * Ma * Ma)
+    th = th_inf - (gamma - 1.0) * strength ** 2 / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
+    rho = (th / th_inf) ** (1.0 / (gamma - 1.0))
+    p = rho * th
+    return rho, u, v, np.zeros_like(u), p
+
+
+def isentropic_vortex(n: int = 256, distorted: bool = True, seed: int = 22091, nsteps: int = 200,
+                      shape: Optional[Tuple[int, int, int]] = None, dt: Optional[float] = None) -> Case:
+    """Isentropic vortex (strength 5, advection (1,1,0), Ma 0.5) on [0,20)^3, Euler.
+
+    Distortion amplitude 0.1 h with seeded phases.  The box is 20 wide so the
+    Gaussian tail at the periodic images is far below roundoff."""
+    nx, ny, nz = shape if shape is not None else (n, n, n)
+    Lb = 20.0
+    L = (Lb, Lb, Lb)
+    h = (Lb / nx, Lb / ny, Lb / nz)
+    xyz = periodic_grid((nx, ny, nz), L, 0.1 * h[0] if distorted else 0.0, seed)
+    g = 1.4
+    rho, u, v, w, p = vortex_primitive(xyz[0], xyz[1], 0.0, L=Lb, gamma=g)
+    if dt is None:
+        dt = 2e-3 * 256.0 / max(nx, ny)
+    return Case(name=f"vortex{nx}x{ny}x{nz}{'-distorted' if distorted else ''}", nx=nx, ny=ny, nz=nz,
+                xyz=xyz, U0=conserved(g, rho, u, v, w, p), period=L, h=h, dt=dt, nsteps=nsteps,
+                gamma=g, Re=1.0, Ma=0.5, viscous=0)
+
+
+def uniform_flow(n: Tuple[int, int, int] = (16, 16, 16), amplitude_frac: float = 0.1, seed: int = 7,
+                 vel=(0.5, 0.3, 0.2), Ma: float = 0.5, viscous: int = 6, L: float = 2 * math.pi) -> Case:
+    """Uniform flow (rho = 1, T = 1) on a distorted periodic grid."""
+    nx, ny, nz = n
+    Ls = (L, L, L)
+    h = (L / nx, L / ny, L / nz)
+    xyz = periodic_grid(n, Ls, amplitude_frac * h[0], seed)
+    g = 1.4
+    shp = xyz[0].shape
+    rho = np.ones(shp)
+    p = np.full(shp, 1.0 / (g * Ma * Ma))
+    U0 = conserved(g, rho, np.full(shp, vel[0]), np.full(shp, vel[1]), np.full(shp, vel[2]), p)
+    return Case(name="uniform-flow", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=U0, period=Ls, h=h, dt=1e-3,
+                nsteps=3, gamma=g, Re=100.0, Ma=Ma, viscous=viscous)
+
+
+def sod(n: int = 200, axis: int = 0, width: int = 4) -> Case:
+    """Sod tube (rho, u, p) = (1, 0, 1) | (0.125, 0, 0.1) on a periodic box [0, 2)
+    along `axis`: the high state fills 0.5 < x < 1.5, so the box holds two
+    mirrored tubes whose waves do not meet before t = 0.2.  Nodes sit at cell
+    centres (i + 1/2) h so no node lies on a discontinuity.  The other two
+    directions carry `width` identical nodes.  Euler, gamma = 1.4; time step
+    0.4/n, 0.2/dt steps of three substeps each."""
+    shape = [width, width, width]
+    shape[axis] = n
+    nx, ny, nz = shape
+    Ls = [0.1 * width, 0.1 * width, 0.1 * width]
+    Ls[axis] = 2.0
+    xyz = periodic_grid((nx, ny, nz), tuple(Ls))
+    h = tuple(Ls[d] / shape[d] for d in range(3))
+    xyz[axis] += 0.5 * h[axis]
+    s = xyz[axis]
+    inside = (s > 0.5) & (s < 1.5)
+    rho = np.where(inside, 1.0, 0.125)
+    p = np.where(inside, 1.0, 0.1)
+    zero = np.zeros_like(rho)
+    g = 1.4
+    dt = 0.4 / n
+    steps = int(round(0.2 / dt))
+    return Case(name=f"sod{n}-axis{axis}", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=conserved(g, rho, zero, zero, zero, p),
+                period=tuple(Ls), h=h, dt=dt, nsteps=3 * steps, gamma=g, Re=1.0, Ma=1.0 / math.sqrt(1.4), viscous=0)
