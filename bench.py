@@ -1,0 +1,170 @@
+"""Throughput of the FP64 path on one MI355X, in grid-point substeps per second.
+
+Workload: the plain FP64 method on two 256^3 periodic grids distorted by a
+sinusoidal mapping (amplitude 0.1 h, seeded phases): the Taylor-Green vortex
+(Re 1600, M 0.1, WENO7 + sixth-order viscous terms) and the isentropic
+vortex (strength 5, advection (1,1,0), M 0.5, Euler).  One benchmark step is
+one Runge-Kutta substep of each of the two runs.  Inputs are synthetic and
+already resident in HBM when the timed region starts.
+
+Prints one JSON line.  The dominant kernel's duration comes from HIP events
+the library records around every launch on its stream during the timed
+region; the CPU baseline is the oracle on a bounded sample (one substep of
+each 256^3 run on the host cores).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# FP64 flops per grid point of one launch, counted from the formulas of the
+# method (add, multiply, divide and square root count one each).
+FLOPS_PRIM = 15          # rho, u, v, w, p and c of a node
+FLOPS_SW = 92            # Steger-Warming split of a node, both signs
+FLOPS_WENO7 = 143        # one seventh-order WENO reconstruction
+FLOPS_IFACE = 10 * FLOPS_WENO7 + 5
+FLOPS_DIFF = 10          # flux difference of the five components
+FLOPS_VDIV = 40          # sixth-order derivative of the four viscous fluxes, added
+FLOPS_MODE = {"set": 0, "add": 5, "rk": 30}
+FLOPS_VISC_FLUX = 300    # gradients, chain rule, Sutherland, stresses, heat flux, fluxes
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
+HBM_PEAK_GBS = 8000.0
+
+
+def sweep_flops(mode: str, viscous: bool) -> int:
+    return FLOPS_PRIM + FLOPS_SW + FLOPS_IFACE + FLOPS_DIFF + (FLOPS_VDIV if viscous else 0) + FLOPS_MODE[mode]
+
+
+def make_cases(n: int):
+    import workloads
+    return [workloads.taylor_green(n, distorted=True), workloads.isentropic_vortex(n, distorted=True)]
+
+
+def cpu_baseline(cases, threads: int):
+    """The oracle, unchanged, on one substep of each run (metrics excluded)."""
+    import oracle
+    total_pts, total_t = 0, 0.0
+    for c in cases:
+        P = oracle.params_from_case(c, nthreads=threads)
+        met = oracle.metrics(P, c.xyz)
+        t0 = time.perf_counter()
+        oracle.advance(P, met, c.U0, 1, c.dt)
+        total_t += time.perf_counter() - t0
+        total_pts += c.N
+        del met
+    return {"value": total_pts / total_t / 1e9, "unit": "Gpt-substeps/s", "cores": threads, "kind": "oracle",
+            "sample": f"one substep of each of the {len(cases)} runs at full size ({total_pts} point-substeps), "
+                      f"{total_t:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256, help="grid points per direction")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the solver keeps the whole domain on a single device; "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2209_15333_amd as pk
+
+    cases = make_cases(args.n)
+    solvers = []
+    for c in cases:
+        s = pk.Solver(pk.params_from(c))
+        s.set_grid(torch.from_numpy(c.xyz).cuda())
+        s.set_state(torch.from_numpy(c.U0).cuda())
+        solvers.append(s)
+    torch.cuda.synchronize()
+    print(f"[bench] {len(cases)} runs of {args.n}^3 ready", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        for s, c in zip(solvers, cases):
+            s.advance(1, c.dt)
+    torch.cuda.synchronize()
+    for s in solvers:
+        pk.ocfd_profile(s.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for s, c in zip(solvers, cases):
+            s.advance(1, c.dt)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = [pk.ocfd_profile_read(s.h) for s in solvers]
+    for s in solvers:
+        pk.ocfd_profile(s.h, False)
+    elapsed = t1 - t0
+    pts = sum(c.N for c in cases) * args.steps
+    value = pts / elapsed / 1e9
+    print(f"[bench] {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    # Dominant kernel class over both runs.
+    tot = {}
+    for p in prof:
+        for k, (ms, cnt) in p.items():
+            a = tot.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += cnt
+    for k, (ms, cnt) in sorted(tot.items(), key=lambda kv: -kv[1][0]):
+        if cnt:
+            print(f"[bench] {k:14s} {ms / cnt * 1e3:9.1f} us/launch  {cnt:6d} launches  {ms:9.2f} ms",
+                  file=sys.stderr, flush=True)
+    dom = max((k for k in tot if k.startswith("sweep")), key=lambda k: tot[k][0])
+    # The zeta sweep applies the Runge-Kutta update; xi stores, eta accumulates.
+    mode = {"sweep_xi": "set", "sweep_eta": "add", "sweep_zeta": "rk"}[dom]
+    flops_launch = {}
+    for c, p in zip(cases, prof):
+        ms, cnt = p[dom]
+        flops_launch[c.name] = (sweep_flops(mode, c.viscous > 0) * c.N, ms / cnt)
+    total_flops = sum(f * 1 for f, _ in flops_launch.values())
+    total_ms = sum(t for _, t in flops_launch.values())
+    achieved = total_flops / (total_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+            "avg_launch_us": {k: round(v[1] * 1e3, 1) for k, v in flops_launch.items()},
+            "flops_per_launch": {k: v[0] for k, v in flops_launch.items()}}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print(f"[bench] oracle baseline on {args.cpu_threads} threads", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(cases, args.cpu_threads)
+
+    out = {
+        "metric": "Gpt-substeps/s (FP64 path)",
+        "value": round(value, 4),
+        "unit": "Gpt-substeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"isentropic vortex + Taylor-Green on {args.n}^3 distorted periodic grids, "
+                               "SW + WENO7 + C6 viscous (TGV), RK3; one step = one substep of each",
+                   "points_per_step": sum(c.N for c in cases), "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

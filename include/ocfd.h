@@ -1,0 +1,171 @@
+/*
+ * ocfd — MI355X (gfx950) library for the right-hand side and time march of
+ * the finite-difference compressible Navier-Stokes solver described by Dang,
+ * Liu, Guo, Duan & Li, "Direct numerical simulation of compressible turbulence
+ * accelerated by GPU. Part 1: OpenCFD-SCU", arXiv:2209.15333.
+ *
+ * One GPU holds the whole single-block curvilinear grid.  Each substep (one
+ * stage of the third-order Runge-Kutta scheme, eq 45) evaluates
+ *   dU/dt = J * [ -d(F - Fv)/dxi - d(G - Gv)/deta - d(H - Hv)/dzeta ]   (eq 1)
+ * with Steger-Warming splitting of the inviscid fluxes (eq 19-30), seventh-order
+ * WENO or hybrid reconstruction along each grid direction (Sec. 2.2.3), and
+ * sixth-order central viscous and heat-flux terms (eq 9-16, Sec. 2.3).
+ *
+ * Conventions shared by every entry point
+ *  - Arrays are structure-of-arrays, field-major, x fastest: field f of node
+ *    (i,j,k) is at  f*N + i + nx*(j + ny*k),  N = nx*ny*nz.
+ *  - Pointers named *_dev are device pointers; the library never frees them.
+ *    Host pointers are named *_host.
+ *  - All device work is enqueued on the solver's HIP stream and returns
+ *    before it finishes, except where an entry point says it synchronises.
+ *  - Every int-returning entry point returns OCFD_OK (0) on success or a
+ *    negative OCFD_ERR_* code; the text of the last error of a solver is
+ *    available from ocfd_last_error.  No C++ exception crosses this interface.
+ *  - One solver must not be used from two host threads at the same time.
+ */
+#ifndef OCFD_H
+#define OCFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OCFD_OK 0
+#define OCFD_ERR_BADARG (-1)      /* null pointer, out-of-range parameter */
+#define OCFD_ERR_BADSIZE (-2)     /* grid size or workspace size not accepted */
+#define OCFD_ERR_HIP (-3)         /* a HIP runtime call failed */
+#define OCFD_ERR_UNSUPPORTED (-4) /* option combination not built */
+#define OCFD_ERR_STATE (-5)       /* call out of order (e.g. advance before set_state) */
+
+/* Inviscid schemes (Sec. 2.2.3, Table 2). */
+#define OCFD_SCHEME_WENO7 0   /* seventh-order WENO at every interface */
+#define OCFD_SCHEME_HYBRID 1  /* sensor-selected low-dissipation / WENO7 (eq 41-43) */
+/* Low-dissipation stencil of the hybrid scheme. */
+#define OCFD_LOWDISS_UD7 0    /* seventh-order upwind, eq 41 */
+#define OCFD_LOWDISS_C8 1     /* eighth-order central */
+
+/* Parts of the right-hand side for ocfd_dudt (bit mask). */
+#define OCFD_PART_XI 1
+#define OCFD_PART_ETA 2
+#define OCFD_PART_ZETA 4
+#define OCFD_PART_VISC 8
+#define OCFD_PART_ALL 15
+
+/* Entries of ocfd_reduce's output. */
+#define OCFD_RED_SUM0 0     /* 0..4: sum over nodes of U_m / J (conserved totals, eq 5) */
+#define OCFD_RED_CFL 5      /* max over nodes of dt * sum_d (|u~_d| + c |grad xi_d|) / h_d */
+#define OCFD_RED_PMIN 6     /* min pressure */
+#define OCFD_RED_RHOMIN 7   /* min density */
+#define OCFD_RED_NONFINITE 8 /* number of non-finite conserved values */
+#define OCFD_RED_COUNT 9
+
+/* Kernel classes timed by the profiling counters. */
+#define OCFD_K_SWEEP_XI 0
+#define OCFD_K_SWEEP_ETA 1
+#define OCFD_K_SWEEP_ZETA 2
+#define OCFD_K_VISC 3
+#define OCFD_K_PRIM 4
+#define OCFD_K_OTHER 5
+#define OCFD_K_COUNT 6
+
+/* Run parameters.  The physical inputs are those the paper names in Sec. 2.1
+   (eq 17-18): gamma, Re, Ma, Pr and the Sutherland reference temperature. */
+typedef struct ocfd_params {
+  int32_t nx, ny, nz;      /* nodes per direction; each >= 1 */
+  int32_t periodic[3];     /* 1: direction xi/eta/zeta is periodic (only periodic grids are built) */
+  double period[3];        /* coordinate d grows by period[d] across the seam of direction d */
+  double h[3];             /* computational spacing of xi, eta, zeta (> 0) */
+  double gamma, Re, Ma, Pr;
+  double Tref, suth;       /* Sutherland law mu = T^1.5 (1 + S)/(T + S), S = suth/Tref (eq 15) */
+  double theta1, theta2;   /* sensor thresholds of eq 43 */
+  double weno_eps;         /* epsilon of the WENO nonlinear weights */
+  int32_t viscous;         /* 0: Euler; 6: sixth-order central viscous terms */
+  int32_t scheme;          /* OCFD_SCHEME_* */
+  int32_t lowdiss;         /* OCFD_LOWDISS_* */
+  int32_t reserved[5];     /* must be zero */
+} ocfd_params;
+
+typedef struct ocfd_solver ocfd_solver;
+
+/* Fill *p with defaults: gamma 1.4, Pr 0.72, Tref 288.15 K, suth 110.4 K,
+   theta 0.02/0.1, eps 1e-6, periodic, WENO7, viscous order 6. */
+int ocfd_params_default(ocfd_params* p);
+
+/* Bytes of device workspace a solver with these parameters needs (0 if the
+   parameters are invalid).  The workspace holds the metrics [10][N], three
+   state buffers [5][N], the right-hand side [5][N], the primitive variables
+   [4][N] and the viscous fluxes [12][N], all FP64, plus small reduction
+   buffers. */
+size_t ocfd_workspace_bytes(const ocfd_params* p);
+
+/* Create a solver.  stream: a hipStream_t (NULL: the default stream).  The
+   solver copies *p.  Errors: BADARG (null pointer / invalid parameter),
+   BADSIZE, UNSUPPORTED (a non-periodic direction). */
+int ocfd_create(const ocfd_params* p, void* stream, ocfd_solver** out);
+
+/* Hand the solver caller-owned device memory of at least
+   ocfd_workspace_bytes bytes, aligned to 256 bytes.  The caller keeps
+   ownership and must keep it alive until ocfd_destroy.  Errors: BADARG,
+   BADSIZE (too small). */
+int ocfd_bind_workspace(ocfd_solver* s, void* workspace_dev, size_t bytes);
+
+/* Compute the metrics from node coordinates xyz_dev [3][N] (x, y, z) with the
+   conservative form of eq 3 evaluated by eighth-order central differences;
+   1/J = det d(x,y,z)/d(xi,eta,zeta) (eq 4).  Errors: BADARG, STATE (no
+   workspace). */
+int ocfd_set_grid(ocfd_solver* s, const double* xyz_dev);
+
+/* Copy metrics [10][N] = xi_x/J, xi_y/J, xi_z/J, eta_x/J, ..., zeta_z/J, 1/J
+   in or out of the solver. */
+int ocfd_set_metrics(ocfd_solver* s, const double* met_dev);
+int ocfd_get_metrics(ocfd_solver* s, double* met_dev);
+
+/* Set the conserved state U_dev [5][N] = rho, rho u, rho v, rho w, E (eq 5)
+   and restart the Runge-Kutta cycle at stage 0. */
+int ocfd_set_state(ocfd_solver* s, const double* U_dev);
+/* Copy out the current state (the value the next substep starts from). */
+int ocfd_get_state(ocfd_solver* s, double* U_dev);
+/* Mid-step restart: the state at the start of the current step and the stage
+   (0, 1, 2).  set_step_state takes the current state, the step-start state
+   and the stage. */
+int ocfd_get_step_state(ocfd_solver* s, double* Un_dev, int32_t* stage_host);
+int ocfd_set_step_state(ocfd_solver* s, const double* U_dev, const double* Un_dev, int32_t stage);
+
+/* Advance n substeps of eq 45 with time step dt: substep k of a step sets
+   U(k) = a_k U^n + b_k (U(k-1) + dt L(U(k-1))), (a,b) = (0,1), (3/4,1/4),
+   (1/3,2/3).  Errors: BADARG (n < 0, dt not finite), STATE. */
+int ocfd_advance(ocfd_solver* s, int32_t n_substeps, double dt);
+
+/* dudt_dev [5][N] = L(U_dev) = dU/dt for the parts selected by the
+   OCFD_PART_* mask, without touching the solver's state.  U_dev must not
+   alias dudt_dev. */
+int ocfd_dudt(ocfd_solver* s, const double* U_dev, double* dudt_dev, int32_t parts);
+
+/* Global sums and extrema of the current state (entries OCFD_RED_*), written
+   to out_host[OCFD_RED_COUNT].  Deterministic order.  Synchronises the
+   stream. */
+int ocfd_reduce(ocfd_solver* s, double dt, double* out_host);
+
+/* Per-interface scheme flags flags_dev [3][N] (byte: 0 low-dissipation,
+   1 WENO7) used by the hybrid scheme instead of the sensor, or NULL to go back
+   to the sensor. */
+int ocfd_set_flags(ocfd_solver* s, const uint8_t* flags_dev);
+
+/* Kernel timing: when enabled, every launch is bracketed by HIP events on the
+   solver's stream.  profile_read synchronises and returns, per kernel class
+   OCFD_K_*, the summed milliseconds and the launch counts since the last
+   enable. */
+int ocfd_profile(ocfd_solver* s, int32_t enable);
+int ocfd_profile_read(ocfd_solver* s, double* ms_host, int64_t* count_host);
+const char* ocfd_kernel_name(int32_t kernel_class);
+
+const char* ocfd_last_error(const ocfd_solver* s);
+void ocfd_destroy(ocfd_solver* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

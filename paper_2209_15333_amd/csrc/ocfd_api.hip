@@ -1,0 +1,488 @@
+// C ABI of the ocfd library (declared in include/ocfd.h).  Host-side
+// bookkeeping only: parameter checks, workspace carving, the order of kernel
+// launches within a Runge-Kutta substep (eq 45) and optional event timing.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "ocfd_internal.h"
+
+using namespace ocfd;
+
+struct ocfd_solver {
+  ocfd_params p;
+  Geo g;
+  Phys ph;
+  hipStream_t st = nullptr;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  double* met = nullptr;
+  double* Ub[3] = {nullptr, nullptr, nullptr};  // [0] = U^n; [1], [2] = stage values
+  double* rhs = nullptr;
+  double* W = nullptr;
+  double* Fv = nullptr;
+  double* theta = nullptr;
+  double* partial = nullptr;
+  double* red = nullptr;
+  const uint8_t* flags = nullptr;
+  int stage = 0;
+  bool have_grid = false;
+  bool have_state = false;
+  bool prof = false;
+  struct Rec {
+    int cls;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  std::string err;
+};
+
+namespace {
+
+int fail(ocfd_solver* s, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(ocfd_solver* s, int code, const char* fmt, ...) {
+  if (s) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    s->err = buf;
+  }
+  return code;
+}
+
+int hip_fail(ocfd_solver* s, hipError_t e, const char* what) {
+  return fail(s, OCFD_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Field-region sizes of the workspace, in doubles per node.
+constexpr int WS_MET = 10, WS_STATE = 5, WS_RHS = 5, WS_PRIM = 4, WS_FV = 12, WS_THETA = 1;
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+bool valid_params(const ocfd_params* p, std::string* why) {
+  char buf[256];
+  if (!p) { *why = "null params"; return false; }
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->nx > 65535 || p->ny > 65535 || p->nz > 65535) {
+    snprintf(buf, sizeof(buf), "grid %d x %d x %d outside [1, 65535]", p->nx, p->ny, p->nz);
+    *why = buf;
+    return false;
+  }
+  for (int d = 0; d < 3; ++d)
+    if (!(p->h[d] > 0.0) || !std::isfinite(p->h[d])) { *why = "h must be positive and finite"; return false; }
+  if (!(p->gamma > 1.0)) { *why = "gamma must exceed 1"; return false; }
+  if (!(p->Ma > 0.0)) { *why = "Ma must be positive"; return false; }
+  if (p->viscous != 0 && p->viscous != 6) { *why = "viscous must be 0 or 6"; return false; }
+  if (p->viscous && !(p->Re > 0.0 && p->Pr > 0.0 && p->Tref > 0.0 && p->suth >= 0.0)) {
+    *why = "Re, Pr, Tref must be positive and suth non-negative";
+    return false;
+  }
+  if (p->scheme != OCFD_SCHEME_WENO7 && p->scheme != OCFD_SCHEME_HYBRID) { *why = "unknown scheme"; return false; }
+  if (p->lowdiss != OCFD_LOWDISS_UD7 && p->lowdiss != OCFD_LOWDISS_C8) { *why = "unknown lowdiss"; return false; }
+  if (!(p->weno_eps > 0.0)) { *why = "weno_eps must be positive"; return false; }
+  for (int i = 0; i < 5; ++i)
+    if (p->reserved[i] != 0) { *why = "reserved fields must be zero"; return false; }
+  return true;
+}
+
+void setup_geo_phys(ocfd_solver* s) {
+  const ocfd_params& p = s->p;
+  s->g.n[0] = p.nx;
+  s->g.n[1] = p.ny;
+  s->g.n[2] = p.nz;
+  s->g.s[0] = 1;
+  s->g.s[1] = p.nx;
+  s->g.s[2] = (long long)p.nx * p.ny;
+  s->g.N = (long long)p.nx * p.ny * p.nz;
+  for (int d = 0; d < 3; ++d) s->g.periodic[d] = p.periodic[d];
+  Phys& ph = s->ph;
+  ph.gamma = p.gamma;
+  ph.gm1 = p.gamma - 1.0;
+  ph.Ma2 = p.Ma * p.Ma;
+  ph.inv_Re = p.viscous ? 1.0 / p.Re : 0.0;
+  ph.kcoef = p.viscous ? 1.0 / ((p.gamma - 1.0) * p.Ma * p.Ma * p.Pr * p.Re) : 0.0;
+  ph.suth = p.viscous ? p.suth / p.Tref : 0.0;
+  ph.eps = p.weno_eps;
+  ph.theta1 = p.theta1;
+  for (int d = 0; d < 3; ++d) {
+    ph.h[d] = p.h[d];
+    ph.ih[d] = 1.0 / p.h[d];
+    ph.period[d] = p.period[d];
+  }
+}
+
+size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver* s, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* ptr = base ? base + off : nullptr;
+    off += align256(bytes);
+    return (double*)ptr;
+  };
+  const size_t fb = (size_t)N * sizeof(double);
+  double* met = take(WS_MET * fb);
+  double* u0 = take(WS_STATE * fb);
+  double* u1 = take(WS_STATE * fb);
+  double* u2 = take(WS_STATE * fb);
+  double* rhs = take(WS_RHS * fb);
+  double* W = take(WS_PRIM * fb);
+  double* Fv = take(WS_FV * fb);
+  double* th = take(WS_THETA * fb);
+  double* partial = take((size_t)nred * OCFD_RED_COUNT * sizeof(double));
+  double* red = take(16 * sizeof(double));
+  (void)p;
+  if (s) {
+    s->met = met;
+    s->Ub[0] = u0;
+    s->Ub[1] = u1;
+    s->Ub[2] = u2;
+    s->rhs = rhs;
+    s->W = W;
+    s->Fv = Fv;
+    s->theta = th;
+    s->partial = partial;
+    s->red = red;
+  }
+  return off;
+}
+
+// Launch bracket for the optional timing.
+struct Timed {
+  ocfd_solver* s;
+  int cls;
+  hipEvent_t a = nullptr, b = nullptr;
+  hipEvent_t get() {
+    if (!s->pool.empty()) {
+      hipEvent_t e = s->pool.back();
+      s->pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  Timed(ocfd_solver* s_, int c) : s(s_), cls(c) {
+    if (s->prof) {
+      a = get();
+      b = get();
+      if (a) (void)hipEventRecord(a, s->st);
+    }
+  }
+  ~Timed() {
+    if (s->prof && a && b) {
+      (void)hipEventRecord(b, s->st);
+      s->recs.push_back({cls, a, b});
+    }
+  }
+};
+
+bool ready(ocfd_solver* s, int* rc) {
+  if (!s) { *rc = OCFD_ERR_BADARG; return false; }
+  if (!s->ws) { *rc = fail(s, OCFD_ERR_STATE, "no workspace bound"); return false; }
+  return true;
+}
+
+// Evaluate the right-hand side of U_cur.  mode MODE_RK writes the next stage
+// into out; MODE_DUDT writes dU/dt into out.
+int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const double* Un, double a, double b,
+            double dt, int parts) {
+  hipError_t e;
+  const bool visc = s->p.viscous && (parts & OCFD_PART_VISC);
+  const bool hyb = s->p.scheme == OCFD_SCHEME_HYBRID;
+  if (visc) {
+    {
+      Timed tm(s, OCFD_K_PRIM);
+      e = launch_prim(s->g, s->ph, Ucur, s->W, s->st);
+    }
+    if (e != hipSuccess) return hip_fail(s, e, "prim kernel");
+    {
+      Timed tm(s, OCFD_K_VISC);
+      e = launch_visc_flux(s->g, s->ph, s->W, s->met, s->Fv, s->st);
+    }
+    if (e != hipSuccess) return hip_fail(s, e, "viscous flux kernel");
+  }
+  if (hyb && !s->flags) {
+    Timed tm(s, OCFD_K_OTHER);
+    e = launch_sensor(s->g, s->ph, Ucur, s->theta, s->st);
+    if (e != hipSuccess) return hip_fail(s, e, "sensor kernel");
+  }
+  SweepArgs A;
+  memset(&A, 0, sizeof(A));
+  A.g = s->g;
+  A.ph = s->ph;
+  A.U = Ucur;
+  A.met = s->met;
+  A.Fv = visc ? s->Fv : nullptr;
+  A.theta = s->theta;
+  A.flags = s->flags;
+  A.rhs = s->rhs;
+  A.Un = Un;
+  A.out = out;
+  A.a = a;
+  A.b = b;
+  A.dt = dt;
+  A.hybrid = hyb ? 1 : 0;
+  A.lowdiss = s->p.lowdiss;
+  for (int d = 0; d < 3; ++d) {
+    A.inviscid = (parts >> d) & 1;
+    A.viscous = visc ? 1 : 0;
+    const int m = d == 0 ? MODE_SET : (d == 1 ? MODE_ADD : mode);
+    Timed tm(s, OCFD_K_SWEEP_XI + d);
+    e = launch_sweep(d, m, A, s->st);
+    if (e != hipSuccess) return hip_fail(s, e, "sweep kernel");
+  }
+  return OCFD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ocfd_params_default(ocfd_params* p) {
+  if (!p) return OCFD_ERR_BADARG;
+  memset(p, 0, sizeof(*p));
+  p->nx = p->ny = p->nz = 1;
+  for (int d = 0; d < 3; ++d) {
+    p->periodic[d] = 1;
+    p->period[d] = 1.0;
+    p->h[d] = 1.0;
+  }
+  p->gamma = 1.4;
+  p->Re = 1600.0;
+  p->Ma = 0.1;
+  p->Pr = 0.72;
+  p->Tref = 288.15;
+  p->suth = 110.4;
+  p->theta1 = 0.02;
+  p->theta2 = 0.1;
+  p->weno_eps = 1e-6;
+  p->viscous = 6;
+  p->scheme = OCFD_SCHEME_WENO7;
+  p->lowdiss = OCFD_LOWDISS_C8;
+  return OCFD_OK;
+}
+
+size_t ocfd_workspace_bytes(const ocfd_params* p) {
+  std::string why;
+  if (!valid_params(p, &why)) return 0;
+  ocfd_solver tmp;
+  tmp.p = *p;
+  setup_geo_phys(&tmp);
+  return workspace_layout(p, tmp.g.N, reduce_blocks(tmp.g), nullptr, nullptr);
+}
+
+int ocfd_create(const ocfd_params* p, void* stream, ocfd_solver** out) {
+  if (!out) return OCFD_ERR_BADARG;
+  *out = nullptr;
+  std::string why;
+  if (!valid_params(p, &why)) {
+    fprintf(stderr, "ocfd_create: %s\n", why.c_str());
+    return OCFD_ERR_BADARG;
+  }
+  for (int d = 0; d < 3; ++d)
+    if (!p->periodic[d]) {
+      fprintf(stderr, "ocfd_create: non-periodic directions are not built\n");
+      return OCFD_ERR_UNSUPPORTED;
+    }
+  ocfd_solver* s = new (std::nothrow) ocfd_solver();
+  if (!s) return OCFD_ERR_BADARG;
+  s->p = *p;
+  s->st = (hipStream_t)stream;
+  setup_geo_phys(s);
+  *out = s;
+  return OCFD_OK;
+}
+
+int ocfd_bind_workspace(ocfd_solver* s, void* ws, size_t bytes) {
+  if (!s) return OCFD_ERR_BADARG;
+  if (!ws) return fail(s, OCFD_ERR_BADARG, "null workspace");
+  if (((uintptr_t)ws) & 255) return fail(s, OCFD_ERR_BADARG, "workspace not 256-byte aligned");
+  const size_t need = workspace_layout(&s->p, s->g.N, reduce_blocks(s->g), nullptr, nullptr);
+  if (bytes < need) return fail(s, OCFD_ERR_BADSIZE, "workspace of %zu bytes, %zu needed", bytes, need);
+  s->ws = (char*)ws;
+  s->ws_bytes = bytes;
+  workspace_layout(&s->p, s->g.N, reduce_blocks(s->g), s, s->ws);
+  s->have_grid = false;
+  s->have_state = false;
+  return OCFD_OK;
+}
+
+int ocfd_set_grid(ocfd_solver* s, const double* xyz) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!xyz) return fail(s, OCFD_ERR_BADARG, "null coordinates");
+  // The viscous-flux region (12 N) is scratch for the 9 inner derivatives.
+  Timed tm(s, OCFD_K_OTHER);
+  hipError_t e = launch_metric_inner(s->g, s->ph, xyz, s->Fv, s->st);
+  if (e == hipSuccess) e = launch_metric_outer(s->g, s->ph, xyz, s->Fv, s->met, s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "metric kernels");
+  s->have_grid = true;
+  return OCFD_OK;
+}
+
+int ocfd_set_metrics(ocfd_solver* s, const double* met) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!met) return fail(s, OCFD_ERR_BADARG, "null metrics");
+  hipError_t e = hipMemcpyAsync(s->met, met, 10 * s->g.N * sizeof(double), hipMemcpyDeviceToDevice, s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "metrics copy");
+  s->have_grid = true;
+  return OCFD_OK;
+}
+
+int ocfd_get_metrics(ocfd_solver* s, double* met) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!met) return fail(s, OCFD_ERR_BADARG, "null metrics");
+  if (!s->have_grid) return fail(s, OCFD_ERR_STATE, "no grid set");
+  hipError_t e = hipMemcpyAsync(met, s->met, 10 * s->g.N * sizeof(double), hipMemcpyDeviceToDevice, s->st);
+  return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "metrics copy");
+}
+
+int ocfd_set_state(ocfd_solver* s, const double* U) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!U) return fail(s, OCFD_ERR_BADARG, "null state");
+  hipError_t e = hipMemcpyAsync(s->Ub[0], U, 5 * s->g.N * sizeof(double), hipMemcpyDeviceToDevice, s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "state copy");
+  s->stage = 0;
+  s->have_state = true;
+  return OCFD_OK;
+}
+
+int ocfd_get_state(ocfd_solver* s, double* U) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!U) return fail(s, OCFD_ERR_BADARG, "null state");
+  if (!s->have_state) return fail(s, OCFD_ERR_STATE, "no state set");
+  hipError_t e = hipMemcpyAsync(U, s->Ub[s->stage], 5 * s->g.N * sizeof(double), hipMemcpyDeviceToDevice, s->st);
+  return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "state copy");
+}
+
+int ocfd_get_step_state(ocfd_solver* s, double* Un, int32_t* stage) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!Un || !stage) return fail(s, OCFD_ERR_BADARG, "null argument");
+  if (!s->have_state) return fail(s, OCFD_ERR_STATE, "no state set");
+  hipError_t e = hipMemcpyAsync(Un, s->Ub[0], 5 * s->g.N * sizeof(double), hipMemcpyDeviceToDevice, s->st);
+  *stage = s->stage;
+  return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "state copy");
+}
+
+int ocfd_set_step_state(ocfd_solver* s, const double* U, const double* Un, int32_t stage) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!U || !Un) return fail(s, OCFD_ERR_BADARG, "null state");
+  if (stage < 0 || stage > 2) return fail(s, OCFD_ERR_BADARG, "stage %d not in 0..2", stage);
+  const size_t b = 5 * s->g.N * sizeof(double);
+  hipError_t e = hipMemcpyAsync(s->Ub[0], Un, b, hipMemcpyDeviceToDevice, s->st);
+  if (e == hipSuccess && stage > 0) e = hipMemcpyAsync(s->Ub[stage], U, b, hipMemcpyDeviceToDevice, s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "state copy");
+  s->stage = stage;
+  s->have_state = true;
+  return OCFD_OK;
+}
+
+int ocfd_advance(ocfd_solver* s, int32_t n, double dt) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (n < 0 || !std::isfinite(dt)) return fail(s, OCFD_ERR_BADARG, "bad substep count or dt");
+  if (!s->have_grid || !s->have_state) return fail(s, OCFD_ERR_STATE, "grid and state must be set first");
+  static const double A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
+  static const double B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
+  for (int i = 0; i < n; ++i) {
+    const int k = s->stage;
+    const double* cur = s->Ub[k];
+    double* nxt = s->Ub[(k + 1) % 3];
+    rc = run_rhs(s, cur, MODE_RK, nxt, s->Ub[0], A[k], B[k], dt, OCFD_PART_ALL);
+    if (rc) return rc;
+    s->stage = (k + 1) % 3;
+  }
+  return OCFD_OK;
+}
+
+int ocfd_dudt(ocfd_solver* s, const double* U, double* out, int32_t parts) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!U || !out) return fail(s, OCFD_ERR_BADARG, "null argument");
+  if (U == out) return fail(s, OCFD_ERR_BADARG, "U and dudt alias");
+  if (parts < 0 || parts > OCFD_PART_ALL) return fail(s, OCFD_ERR_BADARG, "bad parts mask");
+  if (!s->have_grid) return fail(s, OCFD_ERR_STATE, "no grid set");
+  return run_rhs(s, U, MODE_DUDT, out, nullptr, 0.0, 0.0, 0.0, parts);
+}
+
+int ocfd_reduce(ocfd_solver* s, double dt, double* out) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!out) return fail(s, OCFD_ERR_BADARG, "null output");
+  if (!s->have_grid || !s->have_state) return fail(s, OCFD_ERR_STATE, "grid and state must be set first");
+  hipError_t e = launch_reduce(s->g, s->ph, s->Ub[s->stage], s->met, dt, s->partial, reduce_blocks(s->g), s->red,
+                               s->st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(out, s->red, OCFD_RED_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "reduction");
+}
+
+int ocfd_set_flags(ocfd_solver* s, const uint8_t* flags) {
+  if (!s) return OCFD_ERR_BADARG;
+  s->flags = flags;
+  return OCFD_OK;
+}
+
+int ocfd_profile(ocfd_solver* s, int32_t enable) {
+  if (!s) return OCFD_ERR_BADARG;
+  hipError_t e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "stream sync");
+  for (auto& r : s->recs) {
+    s->pool.push_back(r.a);
+    s->pool.push_back(r.b);
+  }
+  s->recs.clear();
+  s->prof = enable != 0;
+  return OCFD_OK;
+}
+
+int ocfd_profile_read(ocfd_solver* s, double* ms, int64_t* count) {
+  if (!s || !ms || !count) return OCFD_ERR_BADARG;
+  hipError_t e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "stream sync");
+  for (int k = 0; k < OCFD_K_COUNT; ++k) {
+    ms[k] = 0.0;
+    count[k] = 0;
+  }
+  for (auto& r : s->recs) {
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, r.a, r.b);
+    if (e != hipSuccess) return hip_fail(s, e, "event timing");
+    ms[r.cls] += t;
+    count[r.cls] += 1;
+  }
+  return OCFD_OK;
+}
+
+const char* ocfd_kernel_name(int32_t k) {
+  static const char* names[OCFD_K_COUNT] = {"sweep_xi", "sweep_eta", "sweep_zeta", "viscous_flux", "primitives",
+                                            "other"};
+  return (k >= 0 && k < OCFD_K_COUNT) ? names[k] : "unknown";
+}
+
+const char* ocfd_last_error(const ocfd_solver* s) { return s ? s->err.c_str() : "null solver"; }
+
+void ocfd_destroy(ocfd_solver* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->st);
+  for (auto& r : s->recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : s->pool) (void)hipEventDestroy(e);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,71 @@
+// Private declarations of the ocfd HIP library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/ocfd.h"
+
+namespace ocfd {
+
+// Grid geometry: node counts and element strides of xi, eta, zeta.
+struct Geo {
+  int n[3];
+  long long s[3];
+  long long N;
+  int periodic[3];
+};
+
+// Physical constants as the kernels use them.
+struct Phys {
+  double gamma, gm1;        // gamma, gamma - 1
+  double Ma2;               // Ma^2
+  double inv_Re;            // 1 / Re
+  double kcoef;             // 1 / ((gamma-1) Ma^2 Pr Re): heat conductivity per unit mu (eq 14)
+  double suth;              // Sutherland constant / Tref (eq 15)
+  double eps;               // WENO epsilon
+  double theta1;            // sensor threshold (eq 43)
+  double h[3], ih[3];       // computational spacing and its inverse
+  double period[3];
+};
+
+// What the last sweep of a substep does with the summed right-hand side.
+enum SweepMode : int {
+  MODE_SET = 0,    // rhs = this direction's contribution
+  MODE_ADD = 1,    // rhs += contribution
+  MODE_RK = 2,     // U_out = a U_n + b (U + dt (rhs + contribution) / (1/J))
+  MODE_DUDT = 3,   // out = (rhs + contribution) / (1/J)
+};
+
+struct SweepArgs {
+  Geo g;
+  Phys ph;
+  const double* U;       // state the right-hand side is evaluated from
+  const double* met;     // [10][N]
+  const double* Fv;      // [12][N] viscous fluxes (or null when inviscid-only / Euler)
+  const double* theta;   // [N] node sensor (hybrid, no forced flags)
+  const uint8_t* flags;  // [3][N] forced interface flags (hybrid) or null
+  double* rhs;           // [5][N]
+  const double* Un;      // RK: state at the start of the step
+  double* out;           // RK: new state; DUDT: dU/dt
+  double a, b, dt;       // RK coefficients
+  int inviscid;          // add the inviscid flux difference of this direction
+  int viscous;           // add the viscous flux derivative of this direction
+  int hybrid;            // 0: WENO7 everywhere; 1: sensor / flags select the stencil
+  int lowdiss;           // OCFD_LOWDISS_*
+};
+
+// Kernel launch entry points (ocfd_kernels.hip).  All return hipError_t of the launch.
+hipError_t launch_sweep(int dir, int mode, const SweepArgs& a, hipStream_t st);
+hipError_t launch_prim(const Geo& g, const Phys& ph, const double* U, double* W, hipStream_t st);
+hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const double* met, double* Fv,
+                            hipStream_t st);
+hipError_t launch_sensor(const Geo& g, const Phys& ph, const double* U, double* theta, hipStream_t st);
+hipError_t launch_metric_inner(const Geo& g, const Phys& ph, const double* xyz, double* inner, hipStream_t st);
+hipError_t launch_metric_outer(const Geo& g, const Phys& ph, const double* xyz, const double* inner, double* met,
+                               hipStream_t st);
+hipError_t launch_reduce(const Geo& g, const Phys& ph, const double* U, const double* met, double dt,
+                         double* partial, int nblocks, double* out, hipStream_t st);
+int reduce_blocks(const Geo& g);
+
+}  // namespace ocfd

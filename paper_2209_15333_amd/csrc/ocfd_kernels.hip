@@ -1,0 +1,628 @@
+// HIP kernels (gfx950) of the ocfd library: one Runge-Kutta substep of the
+// curvilinear compressible Navier-Stokes solver of Dang et al.,
+// arXiv:2209.15333, Section 2.
+//
+// Data layout: structure-of-arrays, field-major, x fastest (see ocfd.h).
+// Every kernel keeps FP64 arithmetic.
+#include "ocfd_internal.h"
+
+namespace ocfd {
+
+// ---------------------------------------------------------------------------
+// Small helpers
+// ---------------------------------------------------------------------------
+
+// Position p (possibly outside [0, n)) wrapped into a periodic line of n nodes.
+__device__ __forceinline__ int wrap(int p, int n) {
+  while (p < 0) p += n;
+  while (p >= n) p -= n;
+  return p;
+}
+
+// Steger-Warming split of one node (eq 19-30).  The vector of eq 23, with the
+// three momentum rows using k1, k2, k3 and the energy row
+// (g-1) l1 |u|^2 + W + l4 |u - c k|^2 / 2 + l5 |u + c k|^2 / 2, is rearranged
+// with B = l4 + l5 and D = c (l5 - l4) into
+//   f0 = s (2(g-1) l1 + B)
+//   f_i = s ((2(g-1) l1 + B) u_i + D k_i)
+//   f4 = s (|u|^2 ((g-1) l1 + B/2) + B c^2 / (g-1) + D (u.k)),  s = rho / (2 g),
+// evaluated once with the positive and once with the negative eigenvalue
+// parts of eq 29.
+__device__ __forceinline__ void sw_split(const Phys& ph, double rho, double u, double v, double w, double p,
+                                         double a0, double a1, double a2, double* fp, double* fm) {
+  const double c2 = ph.gamma * p / rho;
+  const double c = sqrt(c2);
+  const double sig = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+  const double isig = 1.0 / sig;
+  const double k0 = a0 * isig, k1 = a1 * isig, k2 = a2 * isig;
+  const double V = a0 * u + a1 * v + a2 * w;
+  const double cs = c * sig;
+  const double l4 = V - cs, l5 = V + cs;
+  const double q2 = u * u + v * v + w * w;
+  const double uk = V * isig;
+  const double s = rho / (2.0 * ph.gamma);
+  const double c2g = c2 / ph.gm1;
+#pragma unroll
+  for (int sgn = 0; sgn < 2; ++sgn) {
+    const double L1 = sgn == 0 ? 0.5 * (V + fabs(V)) : 0.5 * (V - fabs(V));
+    const double L4 = sgn == 0 ? 0.5 * (l4 + fabs(l4)) : 0.5 * (l4 - fabs(l4));
+    const double L5 = sgn == 0 ? 0.5 * (l5 + fabs(l5)) : 0.5 * (l5 - fabs(l5));
+    const double A = 2.0 * ph.gm1 * L1;
+    const double B = L4 + L5;
+    const double D = c * (L5 - L4);
+    const double AB = A + B;
+    double* f = sgn == 0 ? fp : fm;
+    f[0] = s * AB;
+    f[1] = s * (AB * u + D * k0);
+    f[2] = s * (AB * v + D * k1);
+    f[3] = s * (AB * w + D * k2);
+    f[4] = s * (q2 * (ph.gm1 * L1 + 0.5 * B) + B * c2g + D * uk);
+  }
+}
+
+// Seventh-order WENO value at j+1/2 from a0..a6 = f_{j-3..j+3} (left-biased;
+// Table 2 scheme 4 with the Jiang-Shu smoothness indicators).  The candidates
+// and indicators are kept at 12x and 240x scale, which cancels in the
+// normalised weights, and the four divisions of the weights are folded into
+// one: w_r = d_r prod_{s != r} (eps + beta_s)^2.
+__device__ __forceinline__ double weno7(double a0, double a1, double a2, double a3, double a4, double a5, double a6,
+                                        double eps240) {
+  const double q0 = -3.0 * a0 + 13.0 * a1 - 23.0 * a2 + 25.0 * a3;
+  const double q1 = a1 - 5.0 * a2 + 13.0 * a3 + 3.0 * a4;
+  const double q2 = -a2 + 7.0 * a3 + 7.0 * a4 - a5;
+  const double q3 = 3.0 * a3 + 13.0 * a4 - 5.0 * a5 + a6;
+  const double b0 = a0 * (547.0 * a0 - 3882.0 * a1 + 4642.0 * a2 - 1854.0 * a3) +
+                    a1 * (7043.0 * a1 - 17246.0 * a2 + 7042.0 * a3) + a2 * (11003.0 * a2 - 9402.0 * a3) +
+                    2107.0 * a3 * a3;
+  const double b1 = a1 * (267.0 * a1 - 1642.0 * a2 + 1602.0 * a3 - 494.0 * a4) +
+                    a2 * (2843.0 * a2 - 5966.0 * a3 + 1922.0 * a4) + a3 * (3443.0 * a3 - 2522.0 * a4) +
+                    547.0 * a4 * a4;
+  const double b2 = a2 * (547.0 * a2 - 2522.0 * a3 + 1922.0 * a4 - 494.0 * a5) +
+                    a3 * (3443.0 * a3 - 5966.0 * a4 + 1602.0 * a5) + a4 * (2843.0 * a4 - 1642.0 * a5) +
+                    267.0 * a5 * a5;
+  const double b3 = a3 * (2107.0 * a3 - 9402.0 * a4 + 7042.0 * a5 - 1854.0 * a6) +
+                    a4 * (11003.0 * a4 - 17246.0 * a5 + 4642.0 * a6) + a5 * (7043.0 * a5 - 3882.0 * a6) +
+                    547.0 * a6 * a6;
+  double e0 = eps240 + b0, e1 = eps240 + b1, e2 = eps240 + b2, e3 = eps240 + b3;
+  e0 *= e0;
+  e1 *= e1;
+  e2 *= e2;
+  e3 *= e3;
+  const double e01 = e0 * e1, e23 = e2 * e3;
+  const double w0 = e1 * e23;
+  const double w1 = 12.0 * e0 * e23;
+  const double w2 = 18.0 * e3 * e01;
+  const double w3 = 4.0 * e2 * e01;
+  return (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) / (12.0 * (w0 + w1 + w2 + w3));
+}
+
+// Seventh-order upwind value at j+1/2 (eq 41).
+__device__ __forceinline__ double ud7(double a0, double a1, double a2, double a3, double a4, double a5, double a6) {
+  return (-3.0 * a0 + 25.0 * a1 - 101.0 * a2 + 319.0 * a3 + 214.0 * a4 - 38.0 * a5 + 4.0 * a6) * (1.0 / 420.0);
+}
+
+// Eighth-order central value at j+1/2 over g_{j-3..j+4}.
+__device__ __forceinline__ double c8(double g0, double g1, double g2, double g3, double g4, double g5, double g6,
+                                     double g7) {
+  return (-3.0 * (g0 + g7) + 29.0 * (g1 + g6) - 139.0 * (g2 + g5) + 533.0 * (g3 + g4)) * (1.0 / 840.0);
+}
+
+// ---------------------------------------------------------------------------
+// Directional sweep
+// ---------------------------------------------------------------------------
+//
+// A workgroup owns SW_W neighbouring grid lines along direction DIR and
+// marches along them in chunks of SW_S nodes.  Per chunk:
+//   1. each thread loads one node, recovers the primitives and splits the
+//      flux (eq 19-30) into an LDS ring of split fluxes (node m -> slot m%32);
+//   2. each thread reconstructs one interface j+1/2 (WENO7, or the hybrid's
+//      low-dissipation stencil) from the ring;
+//   3. each thread forms one node's flux difference (F(j+1/2) - F(j-1/2))/h,
+//      adds the sixth-order derivative of the viscous flux of this direction
+//      and applies the mode (store, accumulate, Runge-Kutta update, dU/dt).
+// The flux of the chunk's last interface is carried to the next chunk, so
+// every interface is reconstructed exactly once, and the first node of a
+// periodic line is finished after the last chunk with the wrapped flux.
+// Lines are periodic (the wrap of node positions happens at load time).
+
+constexpr int SW_W = 16;
+constexpr int SW_S = 16;
+constexpr int SW_T = SW_W * SW_S;
+constexpr int RING = 32;
+
+template <int DIR, int MODE, bool HYB>
+__global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
+  constexpr int CD = (DIR == 0) ? 1 : 0;  // direction across the lines of the group
+  constexpr int OD = (DIR == 2) ? 1 : 2;  // remaining direction
+  constexpr int NVAL = HYB ? 11 : 10;     // f+ (5), f- (5), node sensor
+  constexpr int SLOT = NVAL * SW_W + 1;   // padded against bank conflicts
+  constexpr int FHS = 5 * SW_W + 1;
+  __shared__ double ring[RING * SLOT];
+  __shared__ double fh[(SW_S + 1) * FHS];  // fh[0]: carried flux; fh[s+1]: interface j0+s
+  __shared__ double fh0[FHS];             // flux at 1/2, for node 0 of a periodic line
+
+  const int n = A.g.n[DIR];
+  const int ncol = A.g.n[CD];
+  const long long sd = A.g.s[DIR];
+  const long long sc = A.g.s[CD];
+  const long long N = A.g.N;
+  const int col0 = blockIdx.x * SW_W;
+  const long long base = (long long)blockIdx.y * A.g.s[OD] + (long long)col0 * sc;
+  const int t = threadIdx.x;
+  // Global-facing mapping: consecutive threads walk the contiguous index.
+  const int gs = (DIR == 0) ? (t & (SW_S - 1)) : (t / SW_W);
+  const int gc = (DIR == 0) ? (t / SW_S) : (t & (SW_W - 1));
+  // LDS-facing mapping for the reconstruction: lines fastest.
+  const int rs = t / SW_W;
+  const int rc = t & (SW_W - 1);
+  const bool gcol_ok = col0 + gc < ncol;
+  const bool rcol_ok = col0 + rc < ncol;
+  const double ih = A.ph.ih[DIR];
+  const double eps240 = 240.0 * A.ph.eps;
+
+  auto load_node = [&](int m, int col) {
+    const int j = wrap(m, n);
+    const long long id = base + (long long)col * sc + (long long)j * sd;
+    const double rho = A.U[id];
+    const double ir = 1.0 / rho;
+    const double u = A.U[N + id] * ir;
+    const double v = A.U[2 * N + id] * ir;
+    const double w = A.U[3 * N + id] * ir;
+    const double p = A.ph.gm1 * (A.U[4 * N + id] - 0.5 * rho * (u * u + v * v + w * w));
+    const double a0 = A.met[(3 * DIR) * N + id];
+    const double a1 = A.met[(3 * DIR + 1) * N + id];
+    const double a2 = A.met[(3 * DIR + 2) * N + id];
+    double fp[5], fm[5];
+    sw_split(A.ph, rho, u, v, w, p, a0, a1, a2, fp, fm);
+    double* slot = ring + (m & (RING - 1)) * SLOT + col;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      slot[q * SW_W] = fp[q];
+      slot[(5 + q) * SW_W] = fm[q];
+    }
+    if (HYB) slot[10 * SW_W] = A.theta ? A.theta[id] : 0.0;
+  };
+
+  // Output of node j of line col from its two interface fluxes.
+  auto emit = [&](int j, int col, const double* Fr, const double* Fl) {
+    const long long id = base + (long long)col * sc + (long long)j * sd;
+    double r[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r[q] = A.inviscid ? -(Fr[q * SW_W] - Fl[q * SW_W]) * ih : 0.0;
+    if (A.viscous) {
+      const long long o1p = (long long)(wrap(j + 1, n) - j) * sd, o1m = (long long)(wrap(j - 1, n) - j) * sd;
+      const long long o2p = (long long)(wrap(j + 2, n) - j) * sd, o2m = (long long)(wrap(j - 2, n) - j) * sd;
+      const long long o3p = (long long)(wrap(j + 3, n) - j) * sd, o3m = (long long)(wrap(j - 3, n) - j) * sd;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double* F = A.Fv + (long long)(4 * DIR + q) * N + id;
+        const double d = 0.75 * (F[o1p] - F[o1m]) - 0.15 * (F[o2p] - F[o2m]) + (1.0 / 60.0) * (F[o3p] - F[o3m]);
+        r[q + 1] += d * ih;
+      }
+    }
+    if (MODE == MODE_SET) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) A.rhs[q * N + id] = r[q];
+    } else if (MODE == MODE_ADD) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) A.rhs[q * N + id] += r[q];
+    } else {
+      const double jinv = A.met[9 * N + id];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const double L = (A.rhs[q * N + id] + r[q]) / jinv;
+        if (MODE == MODE_RK)
+          A.out[q * N + id] = A.a * A.Un[q * N + id] + A.b * (A.U[q * N + id] + A.dt * L);
+        else
+          A.out[q * N + id] = L;
+      }
+    }
+  };
+
+  const int nchunks = (n + SW_S - 1) / SW_S;
+  // Prologue: nodes -3..3 of every line.
+  if (A.inviscid && t < 7 * SW_W) {
+    const int pm = (DIR == 0) ? (t % 7) : (t / SW_W);
+    const int pc = (DIR == 0) ? (t / 7) : (t % SW_W);
+    if (col0 + pc < ncol) load_node(pm - 3, pc);
+  }
+  for (int c = 0; c < nchunks; ++c) {
+    const int j0 = c * SW_S;
+    if (A.inviscid) {
+      const int m = j0 + 4 + gs;
+      if (gcol_ok && m <= n + 3) load_node(m, gc);
+    }
+    __syncthreads();
+    const int j = j0 + rs;
+    if (A.inviscid && rcol_ok && j < n) {
+      double* dst = fh + (rs + 1) * FHS + rc;
+      bool low = false;
+      if (HYB) {
+        if (A.flags) {
+          low = A.flags[DIR * N + base + (long long)rc * sc + (long long)j * sd] == 0;
+        } else {
+          double mx = 0.0;
+#pragma unroll
+          for (int o = -3; o <= 4; ++o) mx = fmax(mx, ring[((j + o) & (RING - 1)) * SLOT + 10 * SW_W + rc]);
+          low = mx <= A.ph.theta1;
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const double* P = ring + rc + q * SW_W;
+        const double* M = ring + rc + (5 + q) * SW_W;
+#define RP(o) P[((j + (o)) & (RING - 1)) * SLOT]
+#define RM(o) M[((j + (o)) & (RING - 1)) * SLOT]
+        double F;
+        if (HYB && low) {
+          if (A.lowdiss == OCFD_LOWDISS_C8)
+            F = c8(RP(-3) + RM(-3), RP(-2) + RM(-2), RP(-1) + RM(-1), RP(0) + RM(0), RP(1) + RM(1), RP(2) + RM(2),
+                   RP(3) + RM(3), RP(4) + RM(4));
+          else
+            F = ud7(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3)) +
+                ud7(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2));
+        } else {
+          F = weno7(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3), eps240) +
+              weno7(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2), eps240);
+        }
+#undef RP
+#undef RM
+        dst[q * SW_W] = F;
+      }
+    }
+    __syncthreads();
+    if (c == 0 && t < 5 * SW_W) fh0[(t / SW_W) * SW_W + (t % SW_W)] = fh[FHS + (t / SW_W) * SW_W + (t % SW_W)];
+    const int jo = j0 + gs;
+    if (gcol_ok && jo < n && (c > 0 || gs > 0))
+      emit(jo, gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc);
+    __syncthreads();
+    if (t < 5 * SW_W) {
+      const int last = min(SW_S, n - j0);
+      fh[(t / SW_W) * SW_W + (t % SW_W)] = fh[last * FHS + (t / SW_W) * SW_W + (t % SW_W)];
+    }
+  }
+  __syncthreads();
+  if (gs == 0 && gcol_ok) emit(0, gc, fh0 + gc, fh + gc);
+}
+
+template <int DIR, int MODE>
+static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
+  constexpr int CD = (DIR == 0) ? 1 : 0;
+  constexpr int OD = (DIR == 2) ? 1 : 2;
+  dim3 grid((a.g.n[CD] + SW_W - 1) / SW_W, a.g.n[OD]);
+  if (a.hybrid)
+    hipLaunchKernelGGL((k_sweep<DIR, MODE, true>), grid, dim3(SW_T), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_sweep<DIR, MODE, false>), grid, dim3(SW_T), 0, st, a);
+  return hipGetLastError();
+}
+
+template <int DIR>
+static hipError_t launch_sweep_d(int mode, const SweepArgs& a, hipStream_t st) {
+  switch (mode) {
+    case MODE_SET: return launch_sweep_t<DIR, MODE_SET>(a, st);
+    case MODE_ADD: return launch_sweep_t<DIR, MODE_ADD>(a, st);
+    case MODE_RK: return launch_sweep_t<DIR, MODE_RK>(a, st);
+    default: return launch_sweep_t<DIR, MODE_DUDT>(a, st);
+  }
+}
+
+hipError_t launch_sweep(int dir, int mode, const SweepArgs& a, hipStream_t st) {
+  if (dir == 0) return launch_sweep_d<0>(mode, a, st);
+  if (dir == 1) return launch_sweep_d<1>(mode, a, st);
+  return launch_sweep_d<2>(mode, a, st);
+}
+
+// ---------------------------------------------------------------------------
+// Primitive variables and viscous fluxes (eq 9-16, Sec. 2.3)
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_prim(const Geo g, const Phys ph, const double* __restrict__ U,
+                                              double* __restrict__ W) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= g.N) return;
+  const long long N = g.N;
+  const double rho = U[id];
+  const double ir = 1.0 / rho;
+  const double u = U[N + id] * ir, v = U[2 * N + id] * ir, w = U[3 * N + id] * ir;
+  const double p = ph.gm1 * (U[4 * N + id] - 0.5 * rho * (u * u + v * v + w * w));
+  W[id] = u;
+  W[N + id] = v;
+  W[2 * N + id] = w;
+  W[3 * N + id] = ph.gamma * ph.Ma2 * p * ir;  // T = gamma Ma^2 p / rho (eq 16-17)
+}
+
+hipError_t launch_prim(const Geo& g, const Phys& ph, const double* U, double* W, hipStream_t st) {
+  hipLaunchKernelGGL(k_prim, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, U, W);
+  return hipGetLastError();
+}
+
+// Sixth-order central derivative (times h) along a line through node pos.
+__device__ __forceinline__ double d6(const double* f, long long id, int pos, int n, long long stride) {
+  const long long p1 = (long long)(wrap(pos + 1, n) - pos) * stride, m1 = (long long)(wrap(pos - 1, n) - pos) * stride;
+  const long long p2 = (long long)(wrap(pos + 2, n) - pos) * stride, m2 = (long long)(wrap(pos - 2, n) - pos) * stride;
+  const long long p3 = (long long)(wrap(pos + 3, n) - pos) * stride, m3 = (long long)(wrap(pos - 3, n) - pos) * stride;
+  return 0.75 * (f[id + p1] - f[id + m1]) - 0.15 * (f[id + p2] - f[id + m2]) +
+         (1.0 / 60.0) * (f[id + p3] - f[id + m3]);
+}
+
+// Viscous flux vectors of the three directions at every node: derivatives of
+// u, v, w, T along xi, eta, zeta; Cartesian gradients by the chain rule with
+// the node metrics; Sutherland viscosity (eq 15), heat conductivity (eq 14),
+// stresses (eq 13) and stress work plus heat flux (eq 12); the flux of
+// direction d is (row d of the metrics / J) applied to tau and Theta (eq 9-11).
+// Output Fv[4*d + q][N], q = momentum x, y, z, energy.
+__global__ __launch_bounds__(256) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ W,
+                                                   const double* __restrict__ met, double* __restrict__ Fv) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= g.N) return;
+  const long long N = g.N;
+  const int i = (int)(id % g.n[0]);
+  const int j = (int)((id / g.n[0]) % g.n[1]);
+  const int k = (int)(id / ((long long)g.n[0] * g.n[1]));
+  const int pos[3] = {i, j, k};
+  double dq[4][3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dq[q][d] = d6(W + q * N, id, pos[d], g.n[d], g.s[d]) * ph.ih[d];
+  const double ij = 1.0 / met[9 * N + id];
+  double m[9];
+#pragma unroll
+  for (int r = 0; r < 9; ++r) m[r] = met[r * N + id];
+  double gr[4][3];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      gr[q][c] = (m[c] * ij) * dq[q][0] + (m[3 + c] * ij) * dq[q][1] + (m[6 + c] * ij) * dq[q][2];
+  const double T = W[3 * N + id];
+  const double mu = T * sqrt(T) * (1.0 + ph.suth) / (T + ph.suth);
+  const double kc = mu * ph.kcoef;
+  const double mr = mu * ph.inv_Re;
+  const double div = gr[0][0] + gr[1][1] + gr[2][2];
+  double tau[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) tau[a][b] = mr * (gr[a][b] + gr[b][a] - (a == b ? (2.0 / 3.0) * div : 0.0));
+  const double u = W[id], v = W[N + id], w = W[2 * N + id];
+  double th[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) th[a] = u * tau[0][a] + v * tau[1][a] + w * tau[2][a] + kc * gr[3][a];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const double m0 = m[3 * d], m1 = m[3 * d + 1], m2 = m[3 * d + 2];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) Fv[(4 * d + b) * N + id] = m0 * tau[0][b] + m1 * tau[1][b] + m2 * tau[2][b];
+    Fv[(4 * d + 3) * N + id] = m0 * th[0] + m1 * th[1] + m2 * th[2];
+  }
+}
+
+hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const double* met, double* Fv,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_visc_flux, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, W, met, Fv);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Shock sensor (eq 42-43): theta = sum_d |-p_- + 2p - p_+| / (p_- + 2p + p_+)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double node_p(const Phys& ph, const double* U, long long N, long long id) {
+  const double rho = U[id];
+  const double u = U[N + id] / rho, v = U[2 * N + id] / rho, w = U[3 * N + id] / rho;
+  return ph.gm1 * (U[4 * N + id] - 0.5 * rho * (u * u + v * v + w * w));
+}
+
+__global__ __launch_bounds__(256) void k_sensor(const Geo g, const Phys ph, const double* __restrict__ U,
+                                                double* __restrict__ theta) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= g.N) return;
+  const int i = (int)(id % g.n[0]);
+  const int j = (int)((id / g.n[0]) % g.n[1]);
+  const int k = (int)(id / ((long long)g.n[0] * g.n[1]));
+  const int pos[3] = {i, j, k};
+  const double p0 = node_p(ph, U, g.N, id);
+  double th = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const long long im = id + (long long)(wrap(pos[d] - 1, g.n[d]) - pos[d]) * g.s[d];
+    const long long ip = id + (long long)(wrap(pos[d] + 1, g.n[d]) - pos[d]) * g.s[d];
+    const double pm = node_p(ph, U, g.N, im), pp = node_p(ph, U, g.N, ip);
+    th += fabs(-pm + 2.0 * p0 - pp) / (pm + 2.0 * p0 + pp);
+  }
+  theta[id] = th;
+}
+
+hipError_t launch_sensor(const Geo& g, const Phys& ph, const double* U, double* theta, hipStream_t st) {
+  hipLaunchKernelGGL(k_sensor, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, U, theta);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Metrics (eq 2-4) in the conservative form, eighth-order central operator
+// ---------------------------------------------------------------------------
+
+// Eighth-order central derivative (times h) of coordinate `co` along d at the
+// node, the seam crossing of direction d adding period[d] to coordinate d.
+__device__ __forceinline__ double d8_coord(const Geo& g, const Phys& ph, const double* xyz, int co, long long id,
+                                           const int* pos, int d) {
+  const double C[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+  const double* x = xyz + co * g.N;
+  double s = 0.0;
+  for (int m = 1; m <= 4; ++m) {
+    const int pp = pos[d] + m, pm = pos[d] - m;
+    const int wp = wrap(pp, g.n[d]), wm = wrap(pm, g.n[d]);
+    double xp = x[id + (long long)(wp - pos[d]) * g.s[d]];
+    double xm = x[id + (long long)(wm - pos[d]) * g.s[d]];
+    if (co == d) {
+      xp += (double)((pp - wp) / g.n[d]) * ph.period[d];
+      xm += (double)((pm - wm) / g.n[d]) * ph.period[d];
+    }
+    s += C[m - 1] * (xp - xm);
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_metric_inner(const Geo g, const Phys ph, const double* __restrict__ xyz,
+                                                      double* __restrict__ inner) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= g.N) return;
+  const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
+  for (int co = 0; co < 3; ++co)
+    for (int d = 0; d < 3; ++d) inner[(3 * co + d) * g.N + id] = d8_coord(g, ph, xyz, co, id, pos, d) * ph.ih[d];
+}
+
+hipError_t launch_metric_inner(const Geo& g, const Phys& ph, const double* xyz, double* inner, hipStream_t st) {
+  hipLaunchKernelGGL(k_metric_inner, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, xyz, inner);
+  return hipGetLastError();
+}
+
+// Row r (xi, eta, zeta), column co (x, y, z):
+//   (r_co)/J = D_t(a_s * b) - D_s(a_t * b)
+// with (s, t) = (r+1, r+2) and (a, b) = (co+1, co+2) cyclic; for example
+// xi_x/J = (y_eta z)_zeta - (y_zeta z)_eta.  The outer derivative uses the
+// same eighth-order operator, and the coordinate b is unwrapped across a seam
+// of the derivative direction.  1/J is the determinant of the inner
+// derivatives (eq 4).
+__global__ __launch_bounds__(256) void k_metric_outer(const Geo g, const Phys ph, const double* __restrict__ xyz,
+                                                      const double* __restrict__ inner, double* __restrict__ met) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= g.N) return;
+  const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
+  const double C[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
+  for (int r = 0; r < 3; ++r)
+    for (int co = 0; co < 3; ++co) {
+      const int s = (r + 1) % 3, t = (r + 2) % 3;
+      const int a = (co + 1) % 3, b = (co + 2) % 3;
+      double term[2];
+      for (int pass = 0; pass < 2; ++pass) {
+        const int dir = pass == 0 ? t : s;
+        const int inn = pass == 0 ? s : t;
+        const double* ia = inner + (3 * a + inn) * g.N;
+        const double* xb = xyz + b * g.N;
+        double acc = 0.0;
+        for (int m = 1; m <= 4; ++m) {
+          const int pp = pos[dir] + m, pm = pos[dir] - m;
+          const int wp = wrap(pp, g.n[dir]), wm = wrap(pm, g.n[dir]);
+          const long long ip = id + (long long)(wp - pos[dir]) * g.s[dir];
+          const long long im = id + (long long)(wm - pos[dir]) * g.s[dir];
+          double bp = xb[ip], bm = xb[im];
+          if (b == dir) {
+            bp += (double)((pp - wp) / g.n[dir]) * ph.period[dir];
+            bm += (double)((pm - wm) / g.n[dir]) * ph.period[dir];
+          }
+          acc += C[m - 1] * (ia[ip] * bp - ia[im] * bm);
+        }
+        term[pass] = acc * ph.ih[dir];
+      }
+      met[(3 * r + co) * g.N + id] = term[0] - term[1];
+    }
+  double q[3][3];
+  for (int co = 0; co < 3; ++co)
+    for (int d = 0; d < 3; ++d) q[co][d] = inner[(3 * co + d) * g.N + id];
+  met[9 * g.N + id] = q[0][0] * (q[1][1] * q[2][2] - q[1][2] * q[2][1]) -
+                      q[0][1] * (q[1][0] * q[2][2] - q[1][2] * q[2][0]) +
+                      q[0][2] * (q[1][0] * q[2][1] - q[1][1] * q[2][0]);
+}
+
+hipError_t launch_metric_outer(const Geo& g, const Phys& ph, const double* xyz, const double* inner, double* met,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_metric_outer, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, xyz, inner, met);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: conserved totals, CFL, extrema, non-finite count
+// ---------------------------------------------------------------------------
+
+constexpr int RED_T = 256;
+constexpr int RED_MAXB = 1024;
+constexpr int NRED = OCFD_RED_COUNT;
+
+int reduce_blocks(const Geo& g) {
+  long long b = (g.N + RED_T * 16 - 1) / (RED_T * 16);
+  if (b < 1) b = 1;
+  if (b > RED_MAXB) b = RED_MAXB;
+  return (int)b;
+}
+
+// Combine two partial records (sums add; CFL max; p, rho min; count add).
+__device__ __forceinline__ void red_combine(double* a, const double* b) {
+  for (int q = 0; q < 5; ++q) a[q] += b[q];
+  a[5] = fmax(a[5], b[5]);
+  a[6] = fmin(a[6], b[6]);
+  a[7] = fmin(a[7], b[7]);
+  a[8] += b[8];
+}
+
+__device__ void block_reduce(double (*sh)[RED_T], double* acc, double* out) {
+  const int t = threadIdx.x;
+  for (int q = 0; q < NRED; ++q) sh[q][t] = acc[q];
+  __syncthreads();
+  for (int w = RED_T / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      double a[NRED], b[NRED];
+      for (int q = 0; q < NRED; ++q) {
+        a[q] = sh[q][t];
+        b[q] = sh[q][t + w];
+      }
+      red_combine(a, b);
+      for (int q = 0; q < NRED; ++q) sh[q][t] = a[q];
+    }
+    __syncthreads();
+  }
+  if (t < NRED) out[t] = sh[t][0];
+}
+
+__global__ __launch_bounds__(RED_T) void k_reduce_partial(const Geo g, const Phys ph, const double* __restrict__ U,
+                                                          const double* __restrict__ met, double dt,
+                                                          double* __restrict__ partial) {
+  __shared__ double sh[NRED][RED_T];
+  const long long N = g.N;
+  double acc[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY, 0.0};
+  for (long long id = (long long)blockIdx.x * RED_T + threadIdx.x; id < N; id += (long long)gridDim.x * RED_T) {
+    const double jinv = met[9 * N + id];
+    double Uq[5];
+    for (int q = 0; q < 5; ++q) {
+      Uq[q] = U[q * N + id];
+      acc[q] += Uq[q] * jinv;
+      if (!isfinite(Uq[q])) acc[8] += 1.0;
+    }
+    const double rho = Uq[0];
+    const double u = Uq[1] / rho, v = Uq[2] / rho, w = Uq[3] / rho;
+    const double p = ph.gm1 * (Uq[4] - 0.5 * rho * (u * u + v * v + w * w));
+    const double c = sqrt(ph.gamma * p / rho);
+    double local = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      const double a0 = met[(3 * d) * N + id], a1 = met[(3 * d + 1) * N + id], a2 = met[(3 * d + 2) * N + id];
+      const double sig = sqrt(a0 * a0 + a1 * a1 + a2 * a2) / jinv;
+      const double V = (a0 * u + a1 * v + a2 * w) / jinv;
+      local += (fabs(V) + c * sig) * ph.ih[d];
+    }
+    acc[5] = fmax(acc[5], local * dt);
+    acc[6] = fmin(acc[6], p);
+    acc[7] = fmin(acc[7], rho);
+  }
+  block_reduce(sh, acc, partial + (long long)blockIdx.x * NRED);
+}
+
+__global__ __launch_bounds__(RED_T) void k_reduce_final(const double* __restrict__ partial, int nb,
+                                                        double* __restrict__ out) {
+  __shared__ double sh[NRED][RED_T];
+  double acc[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY, 0.0};
+  for (int b = threadIdx.x; b < nb; b += RED_T) red_combine(acc, partial + (long long)b * NRED);
+  block_reduce(sh, acc, out);
+}
+
+hipError_t launch_reduce(const Geo& g, const Phys& ph, const double* U, const double* met, double dt,
+                         double* partial, int nblocks, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nblocks), dim3(RED_T), 0, st, g, ph, U, met, dt, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_T), 0, st, partial, nblocks, out);
+  return hipGetLastError();
+}
+
+}  // namespace ocfd

@@ -1,0 +1,79 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function its header declares, and rejects bad arguments before any
+device work."""
+import ctypes
+import os
+
+import pytest
+
+from helpers import ROOT, header_functions
+
+LIB = os.path.join(ROOT, "paper_2209_15333_amd", "libocfd.so")
+
+
+@pytest.fixture(scope="module")
+def ocfd():
+    if not os.path.exists(LIB):
+        pytest.fail("libocfd.so has not been built (run __graft_entry__.build())")
+    import paper_2209_15333_amd as pk
+    return pk
+
+
+def test_exports_every_declared_symbol(ocfd):
+    names = header_functions()
+    assert len(names) >= 20
+    L = ctypes.CDLL(LIB)
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_header_and_binding_agree(ocfd):
+    """The Python binding exposes every C entry point under the same name."""
+    missing = [n for n in header_functions() if n not in ("ocfd_kernel_name", "ocfd_last_error")
+               and not hasattr(ocfd, n)]
+    assert not missing, missing
+
+
+def test_params_struct_layout(ocfd):
+    # 3 + 3 int32, 3 + 3 + 9 double, 3 + 5 int32 with padding to 8 bytes
+    assert ctypes.sizeof(ocfd.ocfd_params) == 176
+
+
+def _params(ocfd, **kw):
+    p = ocfd.ocfd_params_default()
+    p.nx, p.ny, p.nz = 16, 8, 4
+    for d in range(3):
+        p.h[d] = 0.1
+        p.period[d] = 1.6
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_rejects_bad_parameters(ocfd):
+    L = ocfd.lib()
+    h = ctypes.c_void_p()
+    for bad in (dict(nx=0), dict(gamma=1.0), dict(viscous=4), dict(scheme=7), dict(weno_eps=0.0), dict(Ma=-1.0)):
+        p = _params(ocfd, **bad)
+        assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -1, bad
+        assert L.ocfd_workspace_bytes(ctypes.byref(p)) == 0
+    p = _params(ocfd)
+    p.periodic[1] = 0
+    assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -4
+
+
+def test_workspace_and_order_errors(ocfd):
+    L = ocfd.lib()
+    p = _params(ocfd)
+    h = ctypes.c_void_p()
+    assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == 0
+    try:
+        need = L.ocfd_workspace_bytes(ctypes.byref(p))
+        assert need >= 47 * 8 * 16 * 8 * 4
+        assert L.ocfd_advance(h, 1, 1e-3) == -5                  # no workspace yet
+        assert L.ocfd_bind_workspace(h, ctypes.c_void_p(4096 + 8), need) == -1   # misaligned
+        assert L.ocfd_bind_workspace(h, ctypes.c_void_p(4096), need - 1) == -2   # too small
+        assert b"needed" in L.ocfd_last_error(h)
+        assert L.ocfd_bind_workspace(h, None, need) == -1
+    finally:
+        L.ocfd_destroy(h)

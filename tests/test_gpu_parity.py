@@ -1,0 +1,270 @@
+"""Parity of the HIP library with the CPU oracle on identical seeded inputs.
+
+Bar (FP64 path): per-field relative L2 <= 1e-12 (momentum components share
+the norm of the momentum vector).  Sizes span several 16-node chunks with
+ragged tails; the full 256^3 workloads are checked on sampled nodes in the
+same launch configuration the benchmark times, plus conservation.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from helpers import rel_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL_L2 = 1e-12
+TOL_INF = 1e-11
+# dU/dt itself is a difference of interface fluxes, each the sum of two split
+# fluxes that at Mach 0.1 are ~10x the net flux (c >> |u|), and the 2% noise
+# of the test states makes the difference a further ~50x cancellation.  With
+# unit roundoff 1.1e-16 and ~100 dependent operations per interface value the
+# expected relative difference is ~1e-16 * 10 * 50 * 100 / sqrt(ops) ~ 1e-12,
+# so dU/dt is held to 1e-11 (L2) / 1e-10 (Linf); states after substeps, where
+# dt * dU/dt is small against U, keep the 1e-12 bar.
+TOL_DUDT_L2 = 1e-11
+TOL_DUDT_INF = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pk(torch_cuda):
+    import paper_2209_15333_amd as pk
+    pk.lib()
+    return pk
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _solver(pk, torch, case):
+    s = pk.Solver(pk.params_from(case))
+    s.set_grid(_dev(torch, case.xyz))
+    s.set_state(_dev(torch, case.U0))
+    return s
+
+
+def _local_noise(case, amp, seed):
+    """Multiplicative noise confined to a Gaussian ball around the grid centre,
+    so the sensor marks part of the domain and leaves the rest smooth."""
+    rng = np.random.default_rng(seed)
+    k, j, i = np.meshgrid(*[np.arange(n) - n / 2 for n in (case.nz, case.ny, case.nx)], indexing="ij")
+    ball = np.exp(-(i * i + j * j + k * k) / (2.0 * 4.0 ** 2))
+    return case.U0 * (1.0 + amp * ball * rng.standard_normal(case.U0.shape))
+
+
+def _orc(orc, case):
+    P = orc.params_from_case(case)
+    return P, orc.metrics(P, case.xyz)
+
+
+def _assert_close(got, ref, tol2=TOL_L2, tolinf=TOL_INF, what=""):
+    l2, linf = rel_errors(got, ref)
+    print(f"{what}: rel L2 {l2}, rel Linf {linf}", flush=True)
+    assert np.all(l2 <= tol2), (what, l2)
+    assert np.all(linf <= tolinf), (what, linf)
+
+
+# ------------------------------------------------------------------ metrics
+
+@pytest.mark.parametrize("shape", [(20, 12, 18), (33, 17, 5), (16, 16, 1)])
+def test_metrics_parity(pk, torch_cuda, orc, shape):
+    case = workloads.taylor_green(shape=shape, distorted=True)
+    s = _solver(pk, torch_cuda, case)
+    _, met = _orc(orc, case)
+    got = s.metrics().cpu().numpy()
+    assert np.abs(got - met).max() <= 1e-13 * np.abs(met).max()
+
+
+# ---------------------------------------------------------------- dU/dt parts
+
+PARTS = {"xi": 1, "eta": 2, "zeta": 4, "visc": 8, "all": 15}
+
+
+@pytest.mark.parametrize("part", list(PARTS))
+@pytest.mark.parametrize("shape", [(36, 20, 24), (17, 33, 9)])
+def test_dudt_parity(pk, torch_cuda, orc, part, shape):
+    case = workloads.taylor_green(shape=shape, distorted=True)
+    rng = np.random.default_rng(5)
+    case.U0 = case.U0 * (1.0 + 0.02 * rng.standard_normal(case.U0.shape))
+    s = _solver(pk, torch_cuda, case)
+    P, met = _orc(orc, case)
+    ref = orc.dudt(P, met, case.U0, parts=PARTS[part])
+    got = s.dudt(_dev(torch_cuda, case.U0), PARTS[part]).cpu().numpy()
+    _assert_close(got, ref, TOL_DUDT_L2, TOL_DUDT_INF, what=f"dudt {part} {shape}")
+
+
+def test_dudt_tiny_and_flat_grids(pk, torch_cuda, orc):
+    for shape in [(5, 3, 2), (1, 9, 7), (12, 1, 1)]:
+        case = workloads.taylor_green(shape=shape, distorted=False)
+        rng = np.random.default_rng(6)
+        case.U0 = case.U0 * (1.0 + 0.02 * rng.standard_normal(case.U0.shape))
+        s = _solver(pk, torch_cuda, case)
+        P, met = _orc(orc, case)
+        ref = orc.dudt(P, met, case.U0)
+        got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy()
+        _assert_close(got, ref, TOL_DUDT_L2, TOL_DUDT_INF, what=f"dudt {shape}")
+
+
+# ------------------------------------------------------------------ advance
+
+def test_tgv32_twenty_substeps(pk, torch_cuda, orc):
+    """Taylor-Green 32^3, WENO7 + sixth-order viscous, dt = 1e-3, 20 substeps."""
+    case = workloads.taylor_green(32)
+    s = _solver(pk, torch_cuda, case)
+    P, met = _orc(orc, case)
+    ref, _, st = orc.advance(P, met, case.U0, case.nsteps, case.dt)
+    s.advance(case.nsteps, case.dt)
+    got = s.state().cpu().numpy()
+    _assert_close(got, ref, what="tgv32 x20")
+
+
+def test_vortex_distorted_advance(pk, torch_cuda, orc):
+    case = workloads.isentropic_vortex(shape=(40, 36, 8), distorted=True, dt=0.02)
+    s = _solver(pk, torch_cuda, case)
+    P, met = _orc(orc, case)
+    ref, _, _ = orc.advance(P, met, case.U0, 12, case.dt)
+    s.advance(12, case.dt)
+    _assert_close(s.state().cpu().numpy(), ref, what="vortex 40x36x8 x12")
+
+
+def test_tgv_distorted_ragged_advance(pk, torch_cuda, orc):
+    case = workloads.taylor_green(shape=(40, 24, 20), distorted=True, dt=2e-3)
+    s = _solver(pk, torch_cuda, case)
+    P, met = _orc(orc, case)
+    ref, _, _ = orc.advance(P, met, case.U0, 7, case.dt)
+    s.advance(7, case.dt)
+    _assert_close(s.state().cpu().numpy(), ref, what="tgv 40x24x20 x7")
+
+
+def test_restart_bitwise(pk, torch_cuda):
+    import paper_2209_15333_amd as m
+    case = workloads.taylor_green(shape=(24, 20, 16), distorted=True, dt=2e-3)
+    a = _solver(pk, torch_cuda, case)
+    a.advance(5, case.dt)
+    ua = a.state().cpu().numpy()
+    b = _solver(pk, torch_cuda, case)
+    b.advance(2, case.dt)
+    Un = b.field(5)
+    stage = m.ocfd_get_step_state(b.h, Un)
+    U = b.state()
+    c = _solver(pk, torch_cuda, case)
+    m.ocfd_set_step_state(c.h, U, Un, stage)
+    c.advance(3, case.dt)
+    assert stage == 2
+    assert np.array_equal(c.state().cpu().numpy(), ua)
+
+
+def test_deterministic(pk, torch_cuda):
+    case = workloads.taylor_green(shape=(24, 20, 16), distorted=True, dt=2e-3)
+    outs = []
+    for _ in range(2):
+        s = _solver(pk, torch_cuda, case)
+        s.advance(4, case.dt)
+        outs.append(s.state().cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+# ------------------------------------------------------------------- hybrid
+
+def test_hybrid_with_oracle_flags(pk, torch_cuda, orc):
+    """Hybrid scheme on flags from the oracle's sensor (so both sides use the
+    same stencil at every interface), both low-dissipation stencils."""
+    for low in ("c8", "ud7"):
+        case = workloads.taylor_green(shape=(32, 20, 24), distorted=True)
+        case.scheme, case.lowdiss = "hybrid", low
+        case.U0 = _local_noise(case, 0.03, 9)
+        P, met = _orc(orc, case)
+        theta, flags = orc.sensor(P, case.U0)
+        frac = flags.mean()
+        assert 0.05 < frac < 0.95
+        s = _solver(pk, torch_cuda, case)
+        fl = _dev(torch_cuda, flags)
+        pk.ocfd_set_flags(s.h, fl)
+        ref = orc.dudt(P, met, case.U0, flags=flags)
+        got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy()
+        _assert_close(got, ref, TOL_DUDT_L2, TOL_DUDT_INF, what=f"hybrid forced flags {low}")
+
+
+def test_hybrid_own_sensor(pk, torch_cuda, orc):
+    """Hybrid with each side's own sensor.  Flags can differ only at theta
+    within roundoff of theta1; with none of those, the results agree."""
+    case = workloads.taylor_green(shape=(32, 20, 24), distorted=True)
+    case.scheme = "hybrid"
+    case.U0 = _local_noise(case, 0.03, 10)
+    P, met = _orc(orc, case)
+    theta, flags = orc.sensor(P, case.U0)
+    assert 0.05 < flags.mean() < 0.95
+    assert np.abs(theta - case.theta1).min() > 1e-12
+    s = _solver(pk, torch_cuda, case)
+    ref = orc.dudt(P, met, case.U0)
+    got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy()
+    _assert_close(got, ref, TOL_DUDT_L2, TOL_DUDT_INF, what="hybrid own sensor")
+
+
+# --------------------------------------------------------------- reductions
+
+def test_reduce_parity(pk, torch_cuda, orc):
+    case = workloads.taylor_green(shape=(36, 20, 24), distorted=True)
+    s = _solver(pk, torch_cuda, case)
+    P, met = _orc(orc, case)
+    ref = orc.reduce(P, met, case.U0, case.dt)
+    got = np.array(s.reduce(case.dt))
+    assert np.allclose(got[[0, 4, 5, 6, 7]], ref[[0, 4, 5, 6, 7]], rtol=1e-12, atol=0)
+    mom = np.abs(ref[0]) + np.abs(ref[4])
+    assert np.all(np.abs(got[1:4] - ref[1:4]) <= 1e-13 * mom)
+    assert got[8] == 0.0
+
+
+# --------------------------------------------------- full-size configuration
+
+def _sampled_parity(pk, torch, orc, case, nsamp=1500):
+    """One substep at full size on the GPU (the benchmark's launch path:
+    x/y sweeps into the right-hand side, z sweep fused with the first
+    Runge-Kutta stage) against the oracle's dU/dt at sampled nodes."""
+    s = _solver(pk, torch, case)
+    s.advance(1, case.dt)
+    got = s.state().cpu().numpy().reshape(5, -1)
+    P = orc.params_from_case(case)
+    met = orc.metrics(P, case.xyz)
+    rng = np.random.default_rng(11)
+    nodes = np.unique(np.concatenate([rng.integers(0, case.N, nsamp), [0, case.N - 1, case.nx - 1]]))
+    L = orc.dudt_points(P, met, case.U0, nodes)
+    U0 = case.U0.reshape(5, -1)[:, nodes]
+    ref = 0.0 * U0 + 1.0 * (U0 + case.dt * L.T)
+    _assert_close(got[:, nodes], ref, what=f"{case.name} sampled stage 1")
+    # dU/dt itself at full size (same sweeps, final sweep storing dU/dt)
+    dudt = s.dudt(_dev(torch, case.U0)).cpu().numpy().reshape(5, -1)
+    _assert_close(dudt[:, nodes], L.T, TOL_DUDT_L2, TOL_DUDT_INF, what=f"{case.name} sampled dU/dt")
+    del s
+
+
+@pytest.mark.parametrize("which", ["tgv", "vortex"])
+def test_full_size_sampled(pk, torch_cuda, orc, which):
+    case = (workloads.taylor_green(256, distorted=True) if which == "tgv"
+            else workloads.isentropic_vortex(256, distorted=True))
+    _sampled_parity(pk, torch_cuda, orc, case)
+
+
+def test_full_size_conservation(pk, torch_cuda):
+    """Conserved totals after 30 substeps of the 256^3 distorted Taylor-Green
+    run stay at their initial values to FP64 roundoff."""
+    case = workloads.taylor_green(256, distorted=True)
+    s = _solver(pk, torch_cuda, case)
+    r0 = np.array(s.reduce(case.dt))
+    s.advance(30, case.dt)
+    r1 = np.array(s.reduce(case.dt))
+    tot = np.abs(r0[:5]).copy()
+    tot[1:4] = max(tot[0], tot[4]) * 1e-3 + tot[1:4].sum()
+    print("conservation drift", (r1[:5] - r0[:5]) / np.where(tot > 0, tot, 1), flush=True)
+    assert abs(r1[0] - r0[0]) <= 1e-13 * abs(r0[0])
+    assert abs(r1[4] - r0[4]) <= 1e-13 * abs(r0[4])
+    assert r1[8] == 0.0
