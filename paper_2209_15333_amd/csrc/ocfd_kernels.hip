@@ -61,39 +61,50 @@ __device__ __forceinline__ void sw_split(const Phys& ph, double rho, double u, d
 }
 
 // Seventh-order WENO value at j+1/2 from a0..a6 = f_{j-3..j+3} (left-biased;
-// Table 2 scheme 4 with the Jiang-Shu smoothness indicators).  The candidates
-// and indicators are kept at 12x and 240x scale, which cancels in the
-// normalised weights, and the four divisions of the weights are folded into
-// one: w_r = d_r prod_{s != r} (eps + beta_s)^2.
+// Table 2 scheme 4 with the Jiang-Shu smoothness indicators).
+//
+// The four cubic candidates share the first, second and third differences
+// D_k = a_{k+1} - a_k, E_k = D_{k+1} - D_k, G_k = E_{k+1} - E_k.  For candidate
+// r (cells j-3+r .. j+r) the derivatives of its polynomial at the centre of
+// cell j are d3 = G_r, d2 = E_r + (2, 1, 0, -1)_r G_r and
+// d1 = D_r + (5/2, 3/2, 1/2, -1/2)_r E_r + (43, 7, -5, 7)_r/24 G_r, and the
+// indicator sum_{l=1..3} int_cell (p^(l))^2 equals
+//   (d1 + d3/24)^2 + 13/12 d2^2 + 781/720 d3^2,
+// a sum of squares that avoids the cancellation of the expanded quadratic
+// form.  The candidate values at j+1/2 follow from the same differences.  The
+// four weight divisions are folded into one: w_r = d_r prod_{s != r} (eps + beta_s)^2
+// with d = (1, 12, 18, 4)/35 (the common 1/35 cancels).
 __device__ __forceinline__ double weno7(double a0, double a1, double a2, double a3, double a4, double a5, double a6,
-                                        double eps240) {
-  const double q0 = -3.0 * a0 + 13.0 * a1 - 23.0 * a2 + 25.0 * a3;
-  const double q1 = a1 - 5.0 * a2 + 13.0 * a3 + 3.0 * a4;
-  const double q2 = -a2 + 7.0 * a3 + 7.0 * a4 - a5;
-  const double q3 = 3.0 * a3 + 13.0 * a4 - 5.0 * a5 + a6;
-  const double b0 = a0 * (547.0 * a0 - 3882.0 * a1 + 4642.0 * a2 - 1854.0 * a3) +
-                    a1 * (7043.0 * a1 - 17246.0 * a2 + 7042.0 * a3) + a2 * (11003.0 * a2 - 9402.0 * a3) +
-                    2107.0 * a3 * a3;
-  const double b1 = a1 * (267.0 * a1 - 1642.0 * a2 + 1602.0 * a3 - 494.0 * a4) +
-                    a2 * (2843.0 * a2 - 5966.0 * a3 + 1922.0 * a4) + a3 * (3443.0 * a3 - 2522.0 * a4) +
-                    547.0 * a4 * a4;
-  const double b2 = a2 * (547.0 * a2 - 2522.0 * a3 + 1922.0 * a4 - 494.0 * a5) +
-                    a3 * (3443.0 * a3 - 5966.0 * a4 + 1602.0 * a5) + a4 * (2843.0 * a4 - 1642.0 * a5) +
-                    267.0 * a5 * a5;
-  const double b3 = a3 * (2107.0 * a3 - 9402.0 * a4 + 7042.0 * a5 - 1854.0 * a6) +
-                    a4 * (11003.0 * a4 - 17246.0 * a5 + 4642.0 * a6) + a5 * (7043.0 * a5 - 3882.0 * a6) +
-                    547.0 * a6 * a6;
-  double e0 = eps240 + b0, e1 = eps240 + b1, e2 = eps240 + b2, e3 = eps240 + b3;
+                                        double eps) {
+  const double D0 = a1 - a0, D1 = a2 - a1, D2 = a3 - a2, D3 = a4 - a3, D4 = a5 - a4, D5 = a6 - a5;
+  const double E0 = D1 - D0, E1 = D2 - D1, E2 = D3 - D2, E3 = D4 - D3, E4 = D5 - D4;
+  const double G0 = E1 - E0, G1 = E2 - E1, G2 = E3 - E2, G3 = E4 - E3;
+  (void)E4;
+  // t_r = d1 + d3/24 and d2 of each candidate
+  const double t0 = D0 + 2.5 * E0 + (11.0 / 6.0) * G0, s0 = E0 + 2.0 * G0;
+  const double t1 = D1 + 1.5 * E1 + (1.0 / 3.0) * G1, s1 = E1 + G1;
+  const double t2 = D2 + 0.5 * E2 - (1.0 / 6.0) * G2, s2 = E2;
+  const double t3 = D3 - 0.5 * E3 + (1.0 / 3.0) * G3, s3 = E3 - G3;
+  constexpr double C2 = 13.0 / 12.0, C3 = 781.0 / 720.0;
+  double e0 = eps + (t0 * t0 + C2 * s0 * s0 + C3 * G0 * G0);
+  double e1 = eps + (t1 * t1 + C2 * s1 * s1 + C3 * G1 * G1);
+  double e2 = eps + (t2 * t2 + C2 * s2 * s2 + C3 * G2 * G2);
+  double e3 = eps + (t3 * t3 + C2 * s3 * s3 + C3 * G3 * G3);
   e0 *= e0;
   e1 *= e1;
   e2 *= e2;
   e3 *= e3;
+  // candidate values at j+1/2 relative to a3 = f_j
+  const double q0 = 0.5 * D0 + (4.0 / 3.0) * E0 + (13.0 / 12.0) * G0;
+  const double q1 = 0.5 * D1 + (5.0 / 6.0) * E1 + 0.25 * G1;
+  const double q2 = 0.5 * D2 + (1.0 / 3.0) * E2 - (1.0 / 12.0) * G2;
+  const double q3 = 0.5 * D3 - (1.0 / 6.0) * E3 + (1.0 / 12.0) * G3;
   const double e01 = e0 * e1, e23 = e2 * e3;
   const double w0 = e1 * e23;
   const double w1 = 12.0 * e0 * e23;
   const double w2 = 18.0 * e3 * e01;
   const double w3 = 4.0 * e2 * e01;
-  return (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) / (12.0 * (w0 + w1 + w2 + w3));
+  return a3 + (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) / (w0 + w1 + w2 + w3);
 }
 
 // Seventh-order upwind value at j+1/2 (eq 41).
@@ -158,29 +169,43 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   const bool gcol_ok = col0 + gc < ncol;
   const bool rcol_ok = col0 + rc < ncol;
   const double ih = A.ph.ih[DIR];
-  const double eps240 = 240.0 * A.ph.eps;
+  const double eps = A.ph.eps;
 
-  auto load_node = [&](int m, int col) {
-    const int j = wrap(m, n);
-    const long long id = base + (long long)col * sc + (long long)j * sd;
-    const double rho = A.U[id];
+  // Raw inputs of one node: conserved variables, row DIR of the metrics / J,
+  // node sensor.  Fetched one chunk ahead so the loads overlap the
+  // reconstruction of the current chunk.
+  struct NodeIn {
+    double U[5];
+    double a[3];
+    double th;
+  };
+  auto fetch = [&](int m, int col) {
+    NodeIn r;
+    const long long id = base + (long long)col * sc + (long long)wrap(m, n) * sd;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r.U[q] = A.U[q * N + id];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r.a[q] = A.met[(3 * DIR + q) * N + id];
+    r.th = (HYB && A.theta) ? A.theta[id] : 0.0;
+    return r;
+  };
+  // Primitive recovery and Steger-Warming split of node m into the ring.
+  auto split_store = [&](int m, int col, const NodeIn& in) {
+    const double rho = in.U[0];
     const double ir = 1.0 / rho;
-    const double u = A.U[N + id] * ir;
-    const double v = A.U[2 * N + id] * ir;
-    const double w = A.U[3 * N + id] * ir;
-    const double p = A.ph.gm1 * (A.U[4 * N + id] - 0.5 * rho * (u * u + v * v + w * w));
-    const double a0 = A.met[(3 * DIR) * N + id];
-    const double a1 = A.met[(3 * DIR + 1) * N + id];
-    const double a2 = A.met[(3 * DIR + 2) * N + id];
+    const double u = in.U[1] * ir;
+    const double v = in.U[2] * ir;
+    const double w = in.U[3] * ir;
+    const double p = A.ph.gm1 * (in.U[4] - 0.5 * rho * (u * u + v * v + w * w));
     double fp[5], fm[5];
-    sw_split(A.ph, rho, u, v, w, p, a0, a1, a2, fp, fm);
+    sw_split(A.ph, rho, u, v, w, p, in.a[0], in.a[1], in.a[2], fp, fm);
     double* slot = ring + (m & (RING - 1)) * SLOT + col;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       slot[q * SW_W] = fp[q];
       slot[(5 + q) * SW_W] = fm[q];
     }
-    if (HYB) slot[10 * SW_W] = A.theta ? A.theta[id] : 0.0;
+    if (HYB) slot[10 * SW_W] = in.th;
   };
 
   // Output of node j of line col from its two interface fluxes.
@@ -220,26 +245,32 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   };
 
   const int nchunks = (n + SW_S - 1) / SW_S;
-  // Prologue: nodes -3..3 of every line.
+  // Chunk c reconstructs interfaces JB + 16c + s (s = 0..15) and loads nodes
+  // JB + 16c + 4 .. JB + 16c + 19; with JB = -4 every load window starts on a
+  // 16-node (128-byte) boundary of the line.
+  constexpr int JB = -4;
+  // Prologue: nodes JB-3 .. JB+3 of every line.
   if (A.inviscid && t < 7 * SW_W) {
     const int pm = (DIR == 0) ? (t % 7) : (t / SW_W);
     const int pc = (DIR == 0) ? (t / 7) : (t % SW_W);
-    if (col0 + pc < ncol) load_node(pm - 3, pc);
+    if (col0 + pc < ncol) split_store(JB + pm - 3, pc, fetch(JB + pm - 3, pc));
   }
+  NodeIn ahead;
+  bool have = A.inviscid && gcol_ok && 4 + gs <= n + 3;
+  if (have) ahead = fetch(JB + 4 + gs, gc);
   for (int c = 0; c < nchunks; ++c) {
-    const int j0 = c * SW_S;
-    if (A.inviscid) {
-      const int m = j0 + 4 + gs;
-      if (gcol_ok && m <= n + 3) load_node(m, gc);
-    }
+    const int j0 = JB + c * SW_S;
+    if (have) split_store(j0 + 4 + gs, gc, ahead);
     __syncthreads();
+    have = A.inviscid && gcol_ok && c + 1 < nchunks && (c + 1) * SW_S + 4 + gs <= n + 3;
+    if (have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
     const int j = j0 + rs;
-    if (A.inviscid && rcol_ok && j < n) {
+    if (A.inviscid && rcol_ok && c * SW_S + rs < n) {
       double* dst = fh + (rs + 1) * FHS + rc;
       bool low = false;
       if (HYB) {
         if (A.flags) {
-          low = A.flags[DIR * N + base + (long long)rc * sc + (long long)j * sd] == 0;
+          low = A.flags[DIR * N + base + (long long)rc * sc + (long long)wrap(j, n) * sd] == 0;
         } else {
           double mx = 0.0;
 #pragma unroll
@@ -262,8 +293,8 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
             F = ud7(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3)) +
                 ud7(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2));
         } else {
-          F = weno7(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3), eps240) +
-              weno7(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2), eps240);
+          F = weno7(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3), eps) +
+              weno7(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2), eps);
         }
 #undef RP
 #undef RM
@@ -272,17 +303,17 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     }
     __syncthreads();
     if (c == 0 && t < 5 * SW_W) fh0[(t / SW_W) * SW_W + (t % SW_W)] = fh[FHS + (t / SW_W) * SW_W + (t % SW_W)];
-    const int jo = j0 + gs;
-    if (gcol_ok && jo < n && (c > 0 || gs > 0))
-      emit(jo, gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc);
+    if (gcol_ok && c * SW_S + gs < n && (c > 0 || gs > 0))
+      emit(wrap(j0 + gs, n), gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc);
     __syncthreads();
     if (t < 5 * SW_W) {
-      const int last = min(SW_S, n - j0);
+      const int last = min(SW_S, n - c * SW_S);
       fh[(t / SW_W) * SW_W + (t % SW_W)] = fh[last * FHS + (t / SW_W) * SW_W + (t % SW_W)];
     }
   }
   __syncthreads();
-  if (gs == 0 && gcol_ok) emit(0, gc, fh0 + gc, fh + gc);
+  // The line's first node (JB) with the wrapped flux carried out of the last chunk.
+  if (gs == 0 && gcol_ok) emit(wrap(JB, n), gc, fh0 + gc, fh + gc);
 }
 
 template <int DIR, int MODE>
@@ -337,71 +368,116 @@ hipError_t launch_prim(const Geo& g, const Phys& ph, const double* U, double* W,
   return hipGetLastError();
 }
 
-// Sixth-order central derivative (times h) along a line through node pos.
-__device__ __forceinline__ double d6(const double* f, long long id, int pos, int n, long long stride) {
-  const long long p1 = (long long)(wrap(pos + 1, n) - pos) * stride, m1 = (long long)(wrap(pos - 1, n) - pos) * stride;
-  const long long p2 = (long long)(wrap(pos + 2, n) - pos) * stride, m2 = (long long)(wrap(pos - 2, n) - pos) * stride;
-  const long long p3 = (long long)(wrap(pos + 3, n) - pos) * stride, m3 = (long long)(wrap(pos - 3, n) - pos) * stride;
-  return 0.75 * (f[id + p1] - f[id + m1]) - 0.15 * (f[id + p2] - f[id + m2]) +
-         (1.0 / 60.0) * (f[id + p3] - f[id + m3]);
-}
-
 // Viscous flux vectors of the three directions at every node: derivatives of
 // u, v, w, T along xi, eta, zeta; Cartesian gradients by the chain rule with
 // the node metrics; Sutherland viscosity (eq 15), heat conductivity (eq 14),
 // stresses (eq 13) and stress work plus heat flux (eq 12); the flux of
 // direction d is (row d of the metrics / J) applied to tau and Theta (eq 9-11).
 // Output Fv[4*d + q][N], q = momentum x, y, z, energy.
-__global__ __launch_bounds__(256) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ W,
-                                                   const double* __restrict__ met, double* __restrict__ Fv) {
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= g.N) return;
+//
+// A workgroup owns a 64 x 4 tile of (xi, eta) columns and marches along zeta
+// through one segment of planes, keeping each column's seven-plane window of
+// u, v, w, T in registers, so every plane is read from memory once per
+// segment.  Neighbours along xi and eta are read directly (they sit in the
+// same or adjacent rows of the plane).  Tiles are numbered so that the eight
+// XCDs each receive a contiguous range (round-robin dispatch), which keeps a
+// whole segment of neighbouring tiles on one L2.
+constexpr int VT_X = 64;
+constexpr int VT_Y = 4;
+
+__global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ W,
+                                                   const double* __restrict__ met, double* __restrict__ Fv,
+                                                   int ntx, int nty, int nseg, int zseg) {
+  const int per = gridDim.x / 8;
+  const int L = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (L >= ntx * nty * nseg) return;
+  const int tx = L % ntx, ty = (L / ntx) % nty, zs = L / (ntx * nty);
+  const int i = tx * VT_X + (threadIdx.x & (VT_X - 1));
+  const int j = ty * VT_Y + threadIdx.x / VT_X;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  if (i >= nx || j >= ny) return;
+  const int k0 = zs * zseg;
+  const int k1 = min(nz, k0 + zseg);
   const long long N = g.N;
-  const int i = (int)(id % g.n[0]);
-  const int j = (int)((id / g.n[0]) % g.n[1]);
-  const int k = (int)(id / ((long long)g.n[0] * g.n[1]));
-  const int pos[3] = {i, j, k};
-  double dq[4][3];
+  const long long sz = g.s[2];
+  const long long colid = i + (long long)nx * j;
+  double zw[4][7];
 #pragma unroll
-  for (int d = 0; d < 3; ++d)
+  for (int o = -3; o <= 2; ++o) {
+    const long long id = colid + (long long)wrap(k0 + o, nz) * sz;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) dq[q][d] = d6(W + q * N, id, pos[d], g.n[d], g.s[d]) * ph.ih[d];
-  const double ij = 1.0 / met[9 * N + id];
-  double m[9];
+    for (int q = 0; q < 4; ++q) zw[q][o + 3] = W[q * N + id];
+  }
+  const long long xp1 = wrap(i + 1, nx) - i, xm1 = wrap(i - 1, nx) - i;
+  const long long xp2 = wrap(i + 2, nx) - i, xm2 = wrap(i - 2, nx) - i;
+  const long long xp3 = wrap(i + 3, nx) - i, xm3 = wrap(i - 3, nx) - i;
+  const long long yp1 = (long long)(wrap(j + 1, ny) - j) * nx, ym1 = (long long)(wrap(j - 1, ny) - j) * nx;
+  const long long yp2 = (long long)(wrap(j + 2, ny) - j) * nx, ym2 = (long long)(wrap(j - 2, ny) - j) * nx;
+  const long long yp3 = (long long)(wrap(j + 3, ny) - j) * nx, ym3 = (long long)(wrap(j - 3, ny) - j) * nx;
+  for (int k = k0; k < k1; ++k) {
+    const long long idn = colid + (long long)wrap(k + 3, nz) * sz;
 #pragma unroll
-  for (int r = 0; r < 9; ++r) m[r] = met[r * N + id];
-  double gr[4][3];
+    for (int q = 0; q < 4; ++q) zw[q][6] = W[q * N + idn];
+    const long long id = colid + (long long)k * sz;
+    double dq[4][3];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+    for (int q = 0; q < 4; ++q) {
+      const double* f = W + q * N + id;
+      dq[q][0] = (0.75 * (f[xp1] - f[xm1]) - 0.15 * (f[xp2] - f[xm2]) + (1.0 / 60.0) * (f[xp3] - f[xm3])) * ph.ih[0];
+      dq[q][1] = (0.75 * (f[yp1] - f[ym1]) - 0.15 * (f[yp2] - f[ym2]) + (1.0 / 60.0) * (f[yp3] - f[ym3])) * ph.ih[1];
+      dq[q][2] = (0.75 * (zw[q][4] - zw[q][2]) - 0.15 * (zw[q][5] - zw[q][1]) + (1.0 / 60.0) * (zw[q][6] - zw[q][0])) *
+                 ph.ih[2];
+    }
+    const double ij = 1.0 / met[9 * N + id];
+    double m[9];
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
-      gr[q][c] = (m[c] * ij) * dq[q][0] + (m[3 + c] * ij) * dq[q][1] + (m[6 + c] * ij) * dq[q][2];
-  const double T = W[3 * N + id];
-  const double mu = T * sqrt(T) * (1.0 + ph.suth) / (T + ph.suth);
-  const double kc = mu * ph.kcoef;
-  const double mr = mu * ph.inv_Re;
-  const double div = gr[0][0] + gr[1][1] + gr[2][2];
-  double tau[3][3];
+    for (int r = 0; r < 9; ++r) m[r] = met[r * N + id];
+    double gr[4][3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) tau[a][b] = mr * (gr[a][b] + gr[b][a] - (a == b ? (2.0 / 3.0) * div : 0.0));
-  const double u = W[id], v = W[N + id], w = W[2 * N + id];
-  double th[3];
+      for (int c = 0; c < 3; ++c)
+        gr[q][c] = (m[c] * ij) * dq[q][0] + (m[3 + c] * ij) * dq[q][1] + (m[6 + c] * ij) * dq[q][2];
+    const double T = zw[3][3];
+    const double mu = T * sqrt(T) * (1.0 + ph.suth) / (T + ph.suth);
+    const double kc = mu * ph.kcoef;
+    const double mr = mu * ph.inv_Re;
+    const double div = gr[0][0] + gr[1][1] + gr[2][2];
+    double tau[3][3];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) th[a] = u * tau[0][a] + v * tau[1][a] + w * tau[2][a] + kc * gr[3][a];
+    for (int a = 0; a < 3; ++a)
 #pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    const double m0 = m[3 * d], m1 = m[3 * d + 1], m2 = m[3 * d + 2];
+      for (int b = 0; b < 3; ++b) tau[a][b] = mr * (gr[a][b] + gr[b][a] - (a == b ? (2.0 / 3.0) * div : 0.0));
+    const double u = zw[0][3], v = zw[1][3], w = zw[2][3];
+    double th[3];
 #pragma unroll
-    for (int b = 0; b < 3; ++b) Fv[(4 * d + b) * N + id] = m0 * tau[0][b] + m1 * tau[1][b] + m2 * tau[2][b];
-    Fv[(4 * d + 3) * N + id] = m0 * th[0] + m1 * th[1] + m2 * th[2];
+    for (int a = 0; a < 3; ++a) th[a] = u * tau[0][a] + v * tau[1][a] + w * tau[2][a] + kc * gr[3][a];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const double m0 = m[3 * d], m1 = m[3 * d + 1], m2 = m[3 * d + 2];
+#pragma unroll
+      for (int b = 0; b < 3; ++b) Fv[(4 * d + b) * N + id] = m0 * tau[0][b] + m1 * tau[1][b] + m2 * tau[2][b];
+      Fv[(4 * d + 3) * N + id] = m0 * th[0] + m1 * th[1] + m2 * th[2];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int o = 0; o < 6; ++o) zw[q][o] = zw[q][o + 1];
   }
 }
 
 hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const double* met, double* Fv,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_visc_flux, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, W, met, Fv);
+  const int ntx = (g.n[0] + VT_X - 1) / VT_X;
+  const int nty = (g.n[1] + VT_Y - 1) / VT_Y;
+  // Enough segments along zeta for ~2048 workgroups.
+  int nseg = (2048 + ntx * nty - 1) / (ntx * nty);
+  nseg = nseg < 1 ? 1 : (nseg > g.n[2] ? g.n[2] : nseg);
+  const int zseg = (g.n[2] + nseg - 1) / nseg;
+  nseg = (g.n[2] + zseg - 1) / zseg;
+  const long long tiles = (long long)ntx * nty * nseg;
+  const unsigned nb = (unsigned)(8 * ((tiles + 7) / 8));
+  hipLaunchKernelGGL(k_visc_flux, dim3(nb), dim3(256), 0, st, g, ph, W, met, Fv, ntx, nty, nseg, zseg);
   return hipGetLastError();
 }
 

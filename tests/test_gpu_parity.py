@@ -66,6 +66,32 @@ def _orc(orc, case):
     return P, orc.metrics(P, case.xyz)
 
 
+def _ulp_perturbed(U, seed=123):
+    """U with every value moved by about one unit in the last place."""
+    rng = np.random.default_rng(seed)
+    return U * (1.0 + 2.2e-16 * rng.choice([-1.0, 1.0], size=U.shape))
+
+
+# For smooth states the WENO7 nonlinear weights make dU/dt sensitive to
+# rounding: a one-ulp change of the input moves the oracle's own dU/dt by
+# ~1e-10 of its directional terms (and far more relative to near-zero net
+# fields such as d rho/dt of a divergence-free flow).  Where the states are
+# smooth, the GPU's dU/dt is therefore held to a multiple of that measured
+# sensitivity instead of a fixed relative bound.
+ROUNDOFF_FACTOR = 30.0
+
+
+def _assert_within_roundoff(got, ref, ref_pert, what=""):
+    got = got.reshape(5, -1)
+    ref = ref.reshape(5, -1)
+    ref_pert = ref_pert.reshape(5, -1)
+    err = np.sqrt(((got - ref) ** 2).sum(axis=1))
+    noise = np.sqrt(((ref_pert - ref) ** 2).sum(axis=1))
+    floor = 1e-13 * np.sqrt((ref ** 2).sum(axis=1)).max()
+    print(f"{what}: |gpu - oracle| {err}, oracle one-ulp sensitivity {noise}", flush=True)
+    assert np.all(err <= ROUNDOFF_FACTOR * noise + floor), (what, err / np.maximum(noise, 1e-300))
+
+
 def _assert_close(got, ref, tol2=TOL_L2, tolinf=TOL_INF, what=""):
     l2, linf = rel_errors(got, ref)
     print(f"{what}: rel L2 {l2}, rel Linf {linf}", flush=True)
@@ -190,8 +216,9 @@ def test_hybrid_with_oracle_flags(pk, torch_cuda, orc):
         fl = _dev(torch_cuda, flags)
         pk.ocfd_set_flags(s.h, fl)
         ref = orc.dudt(P, met, case.U0, flags=flags)
+        ref_pert = orc.dudt(P, met, _ulp_perturbed(case.U0), flags=flags)
         got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy()
-        _assert_close(got, ref, TOL_DUDT_L2, TOL_DUDT_INF, what=f"hybrid forced flags {low}")
+        _assert_within_roundoff(got, ref, ref_pert, what=f"hybrid forced flags {low}")
 
 
 def test_hybrid_own_sensor(pk, torch_cuda, orc):
@@ -206,8 +233,9 @@ def test_hybrid_own_sensor(pk, torch_cuda, orc):
     assert np.abs(theta - case.theta1).min() > 1e-12
     s = _solver(pk, torch_cuda, case)
     ref = orc.dudt(P, met, case.U0)
+    ref_pert = orc.dudt(P, met, _ulp_perturbed(case.U0), flags=flags)
     got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy()
-    _assert_close(got, ref, TOL_DUDT_L2, TOL_DUDT_INF, what="hybrid own sensor")
+    _assert_within_roundoff(got, ref, ref_pert, what="hybrid own sensor")
 
 
 # --------------------------------------------------------------- reductions
@@ -243,7 +271,8 @@ def _sampled_parity(pk, torch, orc, case, nsamp=1500):
     _assert_close(got[:, nodes], ref, what=f"{case.name} sampled stage 1")
     # dU/dt itself at full size (same sweeps, final sweep storing dU/dt)
     dudt = s.dudt(_dev(torch, case.U0)).cpu().numpy().reshape(5, -1)
-    _assert_close(dudt[:, nodes], L.T, TOL_DUDT_L2, TOL_DUDT_INF, what=f"{case.name} sampled dU/dt")
+    L_pert = orc.dudt_points(P, met, _ulp_perturbed(case.U0), nodes)
+    _assert_within_roundoff(dudt[:, nodes], L.T, L_pert.T, what=f"{case.name} sampled dU/dt")
     del s
 
 
