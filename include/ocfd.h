@@ -47,6 +47,13 @@ extern "C" {
 #define OCFD_LOWDISS_UD7 0    /* seventh-order upwind, eq 41 */
 #define OCFD_LOWDISS_C8 1     /* eighth-order central */
 
+/* Arithmetic of the inviscid path.  MIXED: Steger-Warming split, smoothness
+   indicators and reconstruction in FP32; metrics, the interface-flux
+   difference (sum of the two FP32 halves taken in FP64), viscous terms, the
+   Runge-Kutta accumulation and reductions stay FP64. */
+#define OCFD_PREC_FP64 0
+#define OCFD_PREC_MIXED 1
+
 /* Parts of the right-hand side for ocfd_dudt (bit mask). */
 #define OCFD_PART_XI 1
 #define OCFD_PART_ETA 2
@@ -85,7 +92,8 @@ typedef struct ocfd_params {
   int32_t viscous;         /* 0: Euler; 6: sixth-order central viscous terms */
   int32_t scheme;          /* OCFD_SCHEME_* */
   int32_t lowdiss;         /* OCFD_LOWDISS_* */
-  int32_t reserved[5];     /* must be zero */
+  int32_t precision;       /* OCFD_PREC_* */
+  int32_t reserved[4];     /* must be zero */
 } ocfd_params;
 
 typedef struct ocfd_solver ocfd_solver;

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(HERE, "libocfd.so")
 OCFD_OK = 0
 OCFD_SCHEME_WENO7, OCFD_SCHEME_HYBRID = 0, 1
 OCFD_LOWDISS_UD7, OCFD_LOWDISS_C8 = 0, 1
+OCFD_PREC_FP64, OCFD_PREC_MIXED = 0, 1
 OCFD_PART_XI, OCFD_PART_ETA, OCFD_PART_ZETA, OCFD_PART_VISC, OCFD_PART_ALL = 1, 2, 4, 8, 15
 OCFD_RED_COUNT = 9
 OCFD_K_COUNT = 6
@@ -39,7 +40,8 @@ class ocfd_params(ctypes.Structure):
         ("theta1", ctypes.c_double), ("theta2", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
         ("viscous", ctypes.c_int32), ("scheme", ctypes.c_int32), ("lowdiss", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 5),
+        ("precision", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -204,6 +206,7 @@ def params_from(case, **overrides) -> ocfd_params:
     p.viscous = int(case.viscous)
     p.scheme = OCFD_SCHEME_HYBRID if case.scheme == "hybrid" else OCFD_SCHEME_WENO7
     p.lowdiss = OCFD_LOWDISS_C8 if case.lowdiss == "c8" else OCFD_LOWDISS_UD7
+    p.precision = OCFD_PREC_MIXED if getattr(case, "precision", "fp64") == "mixed" else OCFD_PREC_FP64
     for k, v in overrides.items():
         setattr(p, k, v)
     return p

@@ -86,7 +86,8 @@ bool valid_params(const ocfd_params* p, std::string* why) {
   if (p->scheme != OCFD_SCHEME_WENO7 && p->scheme != OCFD_SCHEME_HYBRID) { *why = "unknown scheme"; return false; }
   if (p->lowdiss != OCFD_LOWDISS_UD7 && p->lowdiss != OCFD_LOWDISS_C8) { *why = "unknown lowdiss"; return false; }
   if (!(p->weno_eps > 0.0)) { *why = "weno_eps must be positive"; return false; }
-  for (int i = 0; i < 5; ++i)
+  if (p->precision != OCFD_PREC_FP64 && p->precision != OCFD_PREC_MIXED) { *why = "unknown precision"; return false; }
+  for (int i = 0; i < 4; ++i)
     if (p->reserved[i] != 0) { *why = "reserved fields must be zero"; return false; }
   return true;
 }
@@ -104,6 +105,8 @@ void setup_geo_phys(ocfd_solver* s) {
   Phys& ph = s->ph;
   ph.gamma = p.gamma;
   ph.gm1 = p.gamma - 1.0;
+  ph.inv_gm1 = 1.0 / (p.gamma - 1.0);
+  ph.inv_2g = 1.0 / (2.0 * p.gamma);
   ph.Ma2 = p.Ma * p.Ma;
   ph.inv_Re = p.viscous ? 1.0 / p.Re : 0.0;
   ph.kcoef = p.viscous ? 1.0 / ((p.gamma - 1.0) * p.Ma * p.Ma * p.Pr * p.Re) : 0.0;
@@ -228,6 +231,7 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
   A.dt = dt;
   A.hybrid = hyb ? 1 : 0;
   A.lowdiss = s->p.lowdiss;
+  A.mixed = s->p.precision == OCFD_PREC_MIXED ? 1 : 0;
   for (int d = 0; d < 3; ++d) {
     A.inviscid = (parts >> d) & 1;
     A.viscous = visc ? 1 : 0;

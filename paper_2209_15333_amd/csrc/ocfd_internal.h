@@ -19,6 +19,7 @@ struct Geo {
 // Physical constants as the kernels use them.
 struct Phys {
   double gamma, gm1;        // gamma, gamma - 1
+  double inv_gm1, inv_2g;   // 1 / (gamma - 1), 1 / (2 gamma)
   double Ma2;               // Ma^2
   double inv_Re;            // 1 / Re
   double kcoef;             // 1 / ((gamma-1) Ma^2 Pr Re): heat conductivity per unit mu (eq 14)
@@ -53,6 +54,7 @@ struct SweepArgs {
   int viscous;           // add the viscous flux derivative of this direction
   int hybrid;            // 0: WENO7 everywhere; 1: sensor / flags select the stencil
   int lowdiss;           // OCFD_LOWDISS_*
+  int mixed;             // 1: split and reconstruction in FP32 (difference, RK in FP64)
 };
 
 // Kernel launch entry points (ocfd_kernels.hip).  All return hipError_t of the launch.

@@ -19,6 +19,13 @@ __device__ __forceinline__ int wrap(int p, int n) {
   return p;
 }
 
+// The same for -n <= p < 2n (one conditional step each way).
+__device__ __forceinline__ int wrap1(int p, int n) {
+  p += (p < 0) ? n : 0;
+  p -= (p >= n) ? n : 0;
+  return p;
+}
+
 // Steger-Warming split of one node (eq 19-30).  The vector of eq 23, with the
 // three momentum rows using k1, k2, k3 and the energy row
 // (g-1) l1 |u|^2 + W + l4 |u - c k|^2 / 2 + l5 |u + c k|^2 / 2, is rearranged
@@ -28,35 +35,47 @@ __device__ __forceinline__ int wrap(int p, int n) {
 //   f4 = s (|u|^2 ((g-1) l1 + B/2) + B c^2 / (g-1) + D (u.k)),  s = rho / (2 g),
 // evaluated once with the positive and once with the negative eigenvalue
 // parts of eq 29.
-__device__ __forceinline__ void sw_split(const Phys& ph, double rho, double u, double v, double w, double p,
-                                         double a0, double a1, double a2, double* fp, double* fm) {
-  const double c2 = ph.gamma * p / rho;
-  const double c = sqrt(c2);
-  const double sig = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
-  const double isig = 1.0 / sig;
-  const double k0 = a0 * isig, k1 = a1 * isig, k2 = a2 * isig;
-  const double V = a0 * u + a1 * v + a2 * w;
-  const double cs = c * sig;
-  const double l4 = V - cs, l5 = V + cs;
-  const double q2 = u * u + v * v + w * w;
-  const double uk = V * isig;
-  const double s = rho / (2.0 * ph.gamma);
-  const double c2g = c2 / ph.gm1;
+template <typename R>
+__device__ __forceinline__ R rcp_r(R x);
+template <>
+__device__ __forceinline__ double rcp_r<double>(double x) { return 1.0 / x; }
+template <>
+__device__ __forceinline__ float rcp_r<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// R is the precision of the split and of the reconstruction: double for the
+// FP64 path, float for the mixed form.
+template <typename R>
+__device__ __forceinline__ void sw_split(const Phys& ph, R rho, R ir, R u, R v, R w, R p, R a0, R a1, R a2, R* fp,
+                                         R* fm) {
+  const R gm1 = (R)ph.gm1;
+  const R c2 = (R)ph.gamma * p * ir;
+  const R c = sqrt(c2);
+  const R sig = sqrt(a0 * a0 + a1 * a1 + a2 * a2);
+  const R isig = rcp_r<R>(sig);
+  const R k0 = a0 * isig, k1 = a1 * isig, k2 = a2 * isig;
+  const R V = a0 * u + a1 * v + a2 * w;
+  const R cs = c * sig;
+  const R l4 = V - cs, l5 = V + cs;
+  const R q2 = u * u + v * v + w * w;
+  const R uk = V * isig;
+  const R s = rho * (R)ph.inv_2g;
+  const R c2g = c2 * (R)ph.inv_gm1;
+  const R half = (R)0.5;
 #pragma unroll
   for (int sgn = 0; sgn < 2; ++sgn) {
-    const double L1 = sgn == 0 ? 0.5 * (V + fabs(V)) : 0.5 * (V - fabs(V));
-    const double L4 = sgn == 0 ? 0.5 * (l4 + fabs(l4)) : 0.5 * (l4 - fabs(l4));
-    const double L5 = sgn == 0 ? 0.5 * (l5 + fabs(l5)) : 0.5 * (l5 - fabs(l5));
-    const double A = 2.0 * ph.gm1 * L1;
-    const double B = L4 + L5;
-    const double D = c * (L5 - L4);
-    const double AB = A + B;
-    double* f = sgn == 0 ? fp : fm;
+    const R L1 = sgn == 0 ? half * (V + fabs(V)) : half * (V - fabs(V));
+    const R L4 = sgn == 0 ? half * (l4 + fabs(l4)) : half * (l4 - fabs(l4));
+    const R L5 = sgn == 0 ? half * (l5 + fabs(l5)) : half * (l5 - fabs(l5));
+    const R A = (R)2 * gm1 * L1;
+    const R B = L4 + L5;
+    const R D = c * (L5 - L4);
+    const R AB = A + B;
+    R* f = sgn == 0 ? fp : fm;
     f[0] = s * AB;
     f[1] = s * (AB * u + D * k0);
     f[2] = s * (AB * v + D * k1);
     f[3] = s * (AB * w + D * k2);
-    f[4] = s * (q2 * (ph.gm1 * L1 + 0.5 * B) + B * c2g + D * uk);
+    f[4] = s * (q2 * (gm1 * L1 + half * B) + B * c2g + D * uk);
   }
 }
 
@@ -74,48 +93,56 @@ __device__ __forceinline__ void sw_split(const Phys& ph, double rho, double u, d
 // form.  The candidate values at j+1/2 follow from the same differences.  The
 // four weight divisions are folded into one: w_r = d_r prod_{s != r} (eps + beta_s)^2
 // with d = (1, 12, 18, 4)/35 (the common 1/35 cancels).
-__device__ __forceinline__ double weno7(double a0, double a1, double a2, double a3, double a4, double a5, double a6,
-                                        double eps) {
-  const double D0 = a1 - a0, D1 = a2 - a1, D2 = a3 - a2, D3 = a4 - a3, D4 = a5 - a4, D5 = a6 - a5;
-  const double E0 = D1 - D0, E1 = D2 - D1, E2 = D3 - D2, E3 = D4 - D3, E4 = D5 - D4;
-  const double G0 = E1 - E0, G1 = E2 - E1, G2 = E3 - E2, G3 = E4 - E3;
-  (void)E4;
+template <typename R>
+__device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R eps) {
+  const R D0 = a1 - a0, D1 = a2 - a1, D2 = a3 - a2, D3 = a4 - a3, D4 = a5 - a4, D5 = a6 - a5;
+  const R E0 = D1 - D0, E1 = D2 - D1, E2 = D3 - D2, E3 = D4 - D3, E4 = D5 - D4;
+  const R G0 = E1 - E0, G1 = E2 - E1, G2 = E3 - E2, G3 = E4 - E3;
   // t_r = d1 + d3/24 and d2 of each candidate
-  const double t0 = D0 + 2.5 * E0 + (11.0 / 6.0) * G0, s0 = E0 + 2.0 * G0;
-  const double t1 = D1 + 1.5 * E1 + (1.0 / 3.0) * G1, s1 = E1 + G1;
-  const double t2 = D2 + 0.5 * E2 - (1.0 / 6.0) * G2, s2 = E2;
-  const double t3 = D3 - 0.5 * E3 + (1.0 / 3.0) * G3, s3 = E3 - G3;
-  constexpr double C2 = 13.0 / 12.0, C3 = 781.0 / 720.0;
-  double e0 = eps + (t0 * t0 + C2 * s0 * s0 + C3 * G0 * G0);
-  double e1 = eps + (t1 * t1 + C2 * s1 * s1 + C3 * G1 * G1);
-  double e2 = eps + (t2 * t2 + C2 * s2 * s2 + C3 * G2 * G2);
-  double e3 = eps + (t3 * t3 + C2 * s3 * s3 + C3 * G3 * G3);
+  const R t0 = D0 + (R)2.5 * E0 + (R)(11.0 / 6.0) * G0, s0 = E0 + (R)2 * G0;
+  const R t1 = D1 + (R)1.5 * E1 + (R)(1.0 / 3.0) * G1, s1 = E1 + G1;
+  const R t2 = D2 + (R)0.5 * E2 - (R)(1.0 / 6.0) * G2, s2 = E2;
+  const R t3 = D3 - (R)0.5 * E3 + (R)(1.0 / 3.0) * G3, s3 = E3 - G3;
+  const R C2 = (R)(13.0 / 12.0), C3 = (R)(781.0 / 720.0);
+  R e0 = eps + (t0 * t0 + C2 * s0 * s0 + C3 * G0 * G0);
+  R e1 = eps + (t1 * t1 + C2 * s1 * s1 + C3 * G1 * G1);
+  R e2 = eps + (t2 * t2 + C2 * s2 * s2 + C3 * G2 * G2);
+  R e3 = eps + (t3 * t3 + C2 * s3 * s3 + C3 * G3 * G3);
   e0 *= e0;
   e1 *= e1;
   e2 *= e2;
   e3 *= e3;
   // candidate values at j+1/2 relative to a3 = f_j
-  const double q0 = 0.5 * D0 + (4.0 / 3.0) * E0 + (13.0 / 12.0) * G0;
-  const double q1 = 0.5 * D1 + (5.0 / 6.0) * E1 + 0.25 * G1;
-  const double q2 = 0.5 * D2 + (1.0 / 3.0) * E2 - (1.0 / 12.0) * G2;
-  const double q3 = 0.5 * D3 - (1.0 / 6.0) * E3 + (1.0 / 12.0) * G3;
-  const double e01 = e0 * e1, e23 = e2 * e3;
-  const double w0 = e1 * e23;
-  const double w1 = 12.0 * e0 * e23;
-  const double w2 = 18.0 * e3 * e01;
-  const double w3 = 4.0 * e2 * e01;
+  const R q0 = (R)0.5 * D0 + (R)(4.0 / 3.0) * E0 + (R)(13.0 / 12.0) * G0;
+  const R q1 = (R)0.5 * D1 + (R)(5.0 / 6.0) * E1 + (R)0.25 * G1;
+  const R q2 = (R)0.5 * D2 + (R)(1.0 / 3.0) * E2 - (R)(1.0 / 12.0) * G2;
+  const R q3 = (R)0.5 * D3 - (R)(1.0 / 6.0) * E3 + (R)(1.0 / 12.0) * G3;
+  if (sizeof(R) == 4) {
+    // FP32: the weights d_r / (eps + beta_r)^2 from four reciprocals; the
+    // folded product of three (eps + beta)^2 factors can leave the float range.
+    const R i0 = rcp_r<R>(e0), i1 = rcp_r<R>(e1), i2 = rcp_r<R>(e2), i3 = rcp_r<R>(e3);
+    const R w0 = i0, w1 = (R)12 * i1, w2 = (R)18 * i2, w3 = (R)4 * i3;
+    return a3 + (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) * rcp_r<R>(w0 + w1 + w2 + w3);
+  }
+  const R e01 = e0 * e1, e23 = e2 * e3;
+  const R w0 = e1 * e23;
+  const R w1 = (R)12 * e0 * e23;
+  const R w2 = (R)18 * e3 * e01;
+  const R w3 = (R)4 * e2 * e01;
   return a3 + (w0 * q0 + w1 * q1 + w2 * q2 + w3 * q3) / (w0 + w1 + w2 + w3);
 }
 
 // Seventh-order upwind value at j+1/2 (eq 41).
-__device__ __forceinline__ double ud7(double a0, double a1, double a2, double a3, double a4, double a5, double a6) {
-  return (-3.0 * a0 + 25.0 * a1 - 101.0 * a2 + 319.0 * a3 + 214.0 * a4 - 38.0 * a5 + 4.0 * a6) * (1.0 / 420.0);
+template <typename R>
+__device__ __forceinline__ R ud7(R a0, R a1, R a2, R a3, R a4, R a5, R a6) {
+  return ((R)-3 * a0 + (R)25 * a1 - (R)101 * a2 + (R)319 * a3 + (R)214 * a4 - (R)38 * a5 + (R)4 * a6) *
+         (R)(1.0 / 420.0);
 }
 
 // Eighth-order central value at j+1/2 over g_{j-3..j+4}.
-__device__ __forceinline__ double c8(double g0, double g1, double g2, double g3, double g4, double g5, double g6,
-                                     double g7) {
-  return (-3.0 * (g0 + g7) + 29.0 * (g1 + g6) - 139.0 * (g2 + g5) + 533.0 * (g3 + g4)) * (1.0 / 840.0);
+template <typename R>
+__device__ __forceinline__ R c8(R g0, R g1, R g2, R g3, R g4, R g5, R g6, R g7) {
+  return ((R)-3 * (g0 + g7) + (R)29 * (g1 + g6) - (R)139 * (g2 + g5) + (R)533 * (g3 + g4)) * (R)(1.0 / 840.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -141,14 +168,14 @@ constexpr int SW_S = 16;
 constexpr int SW_T = SW_W * SW_S;
 constexpr int RING = 32;
 
-template <int DIR, int MODE, bool HYB>
+template <int DIR, int MODE, bool HYB, typename R>
 __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   constexpr int CD = (DIR == 0) ? 1 : 0;  // direction across the lines of the group
   constexpr int OD = (DIR == 2) ? 1 : 2;  // remaining direction
   constexpr int NVAL = HYB ? 11 : 10;     // f+ (5), f- (5), node sensor
   constexpr int SLOT = NVAL * SW_W + 1;   // padded against bank conflicts
   constexpr int FHS = 5 * SW_W + 1;
-  __shared__ double ring[RING * SLOT];
+  __shared__ R ring[RING * SLOT];
   __shared__ double fh[(SW_S + 1) * FHS];  // fh[0]: carried flux; fh[s+1]: interface j0+s
   __shared__ double fh0[FHS];             // flux at 1/2, for node 0 of a periodic line
 
@@ -169,7 +196,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   const bool gcol_ok = col0 + gc < ncol;
   const bool rcol_ok = col0 + rc < ncol;
   const double ih = A.ph.ih[DIR];
-  const double eps = A.ph.eps;
+  const R eps = (R)A.ph.eps;
 
   // Raw inputs of one node: conserved variables, row DIR of the metrics / J,
   // node sensor.  Fetched one chunk ahead so the loads overlap the
@@ -181,7 +208,8 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   };
   auto fetch = [&](int m, int col) {
     NodeIn r;
-    const long long id = base + (long long)col * sc + (long long)wrap(m, n) * sd;
+    const int jm = n >= 8 ? wrap1(m, n) : wrap(m, n);
+    const long long id = base + (long long)col * sc + (long long)jm * sd;
 #pragma unroll
     for (int q = 0; q < 5; ++q) r.U[q] = A.U[q * N + id];
 #pragma unroll
@@ -197,15 +225,15 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     const double v = in.U[2] * ir;
     const double w = in.U[3] * ir;
     const double p = A.ph.gm1 * (in.U[4] - 0.5 * rho * (u * u + v * v + w * w));
-    double fp[5], fm[5];
-    sw_split(A.ph, rho, u, v, w, p, in.a[0], in.a[1], in.a[2], fp, fm);
-    double* slot = ring + (m & (RING - 1)) * SLOT + col;
+    R fp[5], fm[5];
+    sw_split<R>(A.ph, (R)rho, (R)ir, (R)u, (R)v, (R)w, (R)p, (R)in.a[0], (R)in.a[1], (R)in.a[2], fp, fm);
+    R* slot = ring + (m & (RING - 1)) * SLOT + col;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       slot[q * SW_W] = fp[q];
       slot[(5 + q) * SW_W] = fm[q];
     }
-    if (HYB) slot[10 * SW_W] = in.th;
+    if (HYB) slot[10 * SW_W] = (R)in.th;
   };
 
   // Output of node j of line col from its two interface fluxes.
@@ -215,9 +243,12 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) r[q] = A.inviscid ? -(Fr[q * SW_W] - Fl[q * SW_W]) * ih : 0.0;
     if (A.viscous) {
-      const long long o1p = (long long)(wrap(j + 1, n) - j) * sd, o1m = (long long)(wrap(j - 1, n) - j) * sd;
-      const long long o2p = (long long)(wrap(j + 2, n) - j) * sd, o2m = (long long)(wrap(j - 2, n) - j) * sd;
-      const long long o3p = (long long)(wrap(j + 3, n) - j) * sd, o3m = (long long)(wrap(j - 3, n) - j) * sd;
+      // offsets of the six neighbours along the line (wrapped at the seam)
+      auto off = [&](int k) {
+        const int p = j + k;
+        return (long long)((n >= 8 ? wrap1(p, n) : wrap(p, n)) - j) * sd;
+      };
+      const long long o1p = off(1), o1m = off(-1), o2p = off(2), o2m = off(-2), o3p = off(3), o3m = off(-3);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const double* F = A.Fv + (long long)(4 * DIR + q) * N + id;
@@ -232,10 +263,10 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
 #pragma unroll
       for (int q = 0; q < 5; ++q) A.rhs[q * N + id] += r[q];
     } else {
-      const double jinv = A.met[9 * N + id];
+      const double ij = 1.0 / A.met[9 * N + id];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        const double L = (A.rhs[q * N + id] + r[q]) / jinv;
+        const double L = (A.rhs[q * N + id] + r[q]) * ij;
         if (MODE == MODE_RK)
           A.out[q * N + id] = A.a * A.Un[q * N + id] + A.b * (A.U[q * N + id] + A.dt * L);
         else
@@ -270,31 +301,31 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
       bool low = false;
       if (HYB) {
         if (A.flags) {
-          low = A.flags[DIR * N + base + (long long)rc * sc + (long long)wrap(j, n) * sd] == 0;
+          low = A.flags[DIR * N + base + (long long)rc * sc + (long long)(n >= 8 ? wrap1(j, n) : wrap(j, n)) * sd] == 0;
         } else {
-          double mx = 0.0;
+          R mx = (R)0;
 #pragma unroll
           for (int o = -3; o <= 4; ++o) mx = fmax(mx, ring[((j + o) & (RING - 1)) * SLOT + 10 * SW_W + rc]);
-          low = mx <= A.ph.theta1;
+          low = mx <= (R)A.ph.theta1;
         }
       }
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        const double* P = ring + rc + q * SW_W;
-        const double* M = ring + rc + (5 + q) * SW_W;
+        const R* P = ring + rc + q * SW_W;
+        const R* M = ring + rc + (5 + q) * SW_W;
 #define RP(o) P[((j + (o)) & (RING - 1)) * SLOT]
 #define RM(o) M[((j + (o)) & (RING - 1)) * SLOT]
         double F;
         if (HYB && low) {
           if (A.lowdiss == OCFD_LOWDISS_C8)
-            F = c8(RP(-3) + RM(-3), RP(-2) + RM(-2), RP(-1) + RM(-1), RP(0) + RM(0), RP(1) + RM(1), RP(2) + RM(2),
-                   RP(3) + RM(3), RP(4) + RM(4));
+            F = (double)c8<R>(RP(-3) + RM(-3), RP(-2) + RM(-2), RP(-1) + RM(-1), RP(0) + RM(0), RP(1) + RM(1),
+                              RP(2) + RM(2), RP(3) + RM(3), RP(4) + RM(4));
           else
-            F = ud7(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3)) +
-                ud7(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2));
+            F = (double)ud7<R>(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3)) +
+                (double)ud7<R>(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2));
         } else {
-          F = weno7(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3), eps) +
-              weno7(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2), eps);
+          F = (double)weno7<R>(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3), eps) +
+              (double)weno7<R>(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2), eps);
         }
 #undef RP
 #undef RM
@@ -304,7 +335,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     __syncthreads();
     if (c == 0 && t < 5 * SW_W) fh0[(t / SW_W) * SW_W + (t % SW_W)] = fh[FHS + (t / SW_W) * SW_W + (t % SW_W)];
     if (gcol_ok && c * SW_S + gs < n && (c > 0 || gs > 0))
-      emit(wrap(j0 + gs, n), gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc);
+      emit(n >= 8 ? wrap1(j0 + gs, n) : wrap(j0 + gs, n), gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc);
     __syncthreads();
     if (t < 5 * SW_W) {
       const int last = min(SW_S, n - c * SW_S);
@@ -321,10 +352,17 @@ static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   constexpr int CD = (DIR == 0) ? 1 : 0;
   constexpr int OD = (DIR == 2) ? 1 : 2;
   dim3 grid((a.g.n[CD] + SW_W - 1) / SW_W, a.g.n[OD]);
-  if (a.hybrid)
-    hipLaunchKernelGGL((k_sweep<DIR, MODE, true>), grid, dim3(SW_T), 0, st, a);
-  else
-    hipLaunchKernelGGL((k_sweep<DIR, MODE, false>), grid, dim3(SW_T), 0, st, a);
+  if (a.mixed) {
+    if (a.hybrid)
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, float>), grid, dim3(SW_T), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, float>), grid, dim3(SW_T), 0, st, a);
+  } else {
+    if (a.hybrid)
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, double>), grid, dim3(SW_T), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, double>), grid, dim3(SW_T), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -1,0 +1,72 @@
+"""Mixed-precision form: Steger-Warming split, smoothness indicators and
+reconstruction in FP32, flux difference / viscous terms / RK accumulation /
+reductions in FP64.  Bar: per-field relative L2 drift <= 1e-5 against the FP64
+oracle after 100 substeps, conserved totals held to FP64 roundoff."""
+import numpy as np
+import pytest
+
+import workloads
+from helpers import rel_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL_DRIFT = 1e-5
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2209_15333_amd as pk
+    pk.lib()
+    return pk
+
+
+def _run(pk, case, n):
+    import torch
+    s = pk.Solver(pk.params_from(case))
+    s.set_grid(torch.from_numpy(case.xyz).cuda())
+    s.set_state(torch.from_numpy(case.U0).cuda())
+    r0 = np.array(s.reduce(case.dt))
+    s.advance(n, case.dt)
+    r1 = np.array(s.reduce(case.dt))
+    return s.state().cpu().numpy(), r0, r1
+
+
+@pytest.mark.parametrize("which", ["tgv32", "vortex", "tgv-hybrid"])
+def test_mixed_drift_vs_fp64_oracle(pk, orc, which):
+    if which == "tgv32":
+        case = workloads.taylor_green(32)
+    elif which == "vortex":
+        case = workloads.isentropic_vortex(shape=(48, 40, 8), distorted=True, dt=0.02)
+    else:
+        case = workloads.taylor_green(shape=(32, 24, 20), distorted=True, dt=1e-3)
+        case.scheme = "hybrid"
+    P = orc.params_from_case(case)
+    met = orc.metrics(P, case.xyz)
+    ref, _, _ = orc.advance(P, met, case.U0, 100, case.dt)
+    case.precision = "mixed"
+    got, r0, r1 = _run(pk, case, 100)
+    l2, linf = rel_errors(got, ref)
+    print(f"{which}: mixed vs FP64 oracle after 100 substeps: rel L2 {l2}, rel Linf {linf}", flush=True)
+    assert np.all(l2 <= TOL_DRIFT)
+    # the mixed form still conserves to FP64 roundoff
+    assert abs(r1[0] - r0[0]) <= 1e-13 * abs(r0[0])
+    assert abs(r1[4] - r0[4]) <= 1e-13 * abs(r0[4])
+
+
+@pytest.mark.parametrize("which", ["tgv", "vortex"])
+def test_mixed_full_size_drift(pk, which):
+    """100 substeps of the 256^3 distorted workloads in the mixed form against
+    the FP64 path (parity-checked against the oracle to 1e-12 elsewhere)."""
+    case = (workloads.taylor_green(256, distorted=True) if which == "tgv"
+            else workloads.isentropic_vortex(256, distorted=True))
+    ref, _, _ = _run(pk, case, 100)
+    case.precision = "mixed"
+    got, r0, r1 = _run(pk, case, 100)
+    l2, linf = rel_errors(got, ref)
+    print(f"{which}256 mixed vs FP64 after 100 substeps: rel L2 {l2}, rel Linf {linf}", flush=True)
+    assert np.all(l2 <= TOL_DRIFT)
+    assert abs(r1[0] - r0[0]) <= 1e-13 * abs(r0[0])
+    assert abs(r1[4] - r0[4]) <= 1e-13 * abs(r0[4])

@@ -55,6 +55,7 @@ class Case:
     lowdiss: str = "c8"                  # "ud7" | "c8"
     three_way: bool = False
     inflow: Optional[np.ndarray] = None
+    precision: str = "fp64"              # "fp64" | "mixed" (GPU only)
 
     @property
     def N(self) -> int:
@@ -209,3 +210,56 @@ def sod(n: int = 200, axis: int = 0, width: int = 4) -> Case:
     steps = int(round(0.2 / dt))
     return Case(name=f"sod{n}-axis{axis}", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=conserved(g, rho, zero, zero, zero, p),
                 period=tuple(Ls), h=h, dt=dt, nsteps=3 * steps, gamma=g, Re=1.0, Ma=1.0 / math.sqrt(1.4), viscous=0)
+
+
+def isotropic_turbulence(n: int = 512, seed: int = 22093, k0: float = 4.0, Mt: float = 0.6,
+                         Re_lambda: float = 100.0, dt: Optional[float] = None, nsteps: int = 500) -> Case:
+    """Decaying compressible isotropic turbulence on [0, 2 pi)^3.
+
+    Solenoidal velocity with energy spectrum E(k) ~ k^4 exp(-2 k^2 / k0^2):
+    each Fourier mode gets a complex Gaussian amplitude (PCG64(seed)) scaled
+    to the spectrum, the k = 0 mode is removed and the field projected onto
+    its divergence-free part.  Scaled to u_rms = 1 per component, so the
+    turbulent Mach number sqrt(<u.u>)/c = Mt fixes c and Ma = 1/c.  Uniform
+    rho = T = 1.  Re = Re_lambda / (u_rms lambda) with the Taylor microscale
+    lambda = u_rms / rms(du/dx) measured on the field (spectrally).  Pr 0.72.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k1 = np.fft.fftfreq(n, d=1.0 / n)
+    kz, ky, kx = np.meshgrid(k1, k1, np.fft.rfftfreq(n, d=1.0 / n), indexing="ij")
+    kk = np.sqrt(kx * kx + ky * ky + kz * kz)
+    spec = np.where(kk > 0, kk ** 4 * np.exp(-2.0 * kk * kk / (k0 * k0)), 0.0)
+    # amplitude per mode so that the shell sum follows E(k): |u_k|^2 ~ E(k) / (4 pi k^2)
+    amp = np.where(kk > 0, np.sqrt(spec / (4.0 * math.pi * np.maximum(kk, 1e-30) ** 2)), 0.0)
+    uh = []
+    for _ in range(3):
+        re = rng.standard_normal(kk.shape)
+        im = rng.standard_normal(kk.shape)
+        uh.append(amp * (re + 1j * im))
+    # project out the compressive part: u <- u - k (k.u) / |k|^2
+    kdotu = kx * uh[0] + ky * uh[1] + kz * uh[2]
+    k2 = np.where(kk > 0, kk * kk, 1.0)
+    uh[0] = uh[0] - kx * kdotu / k2
+    uh[1] = uh[1] - ky * kdotu / k2
+    uh[2] = uh[2] - kz * kdotu / k2
+    vel = [np.fft.irfftn(c, s=(n, n, n), axes=(0, 1, 2)) for c in uh]
+    dudx = np.fft.irfftn(1j * kx * uh[0], s=(n, n, n), axes=(0, 1, 2))
+    del uh, kdotu
+    urms = math.sqrt(sum(float(np.mean(v * v)) for v in vel) / 3.0)
+    vel = [v / urms for v in vel]
+    lam = 1.0 / math.sqrt(float(np.mean((dudx / urms) ** 2)))   # u_rms = 1 after scaling
+    c = math.sqrt(3.0) / Mt
+    Ma = 1.0 / c
+    g = 1.4
+    L = (TWO_PI, TWO_PI, TWO_PI)
+    h = (TWO_PI / n,) * 3
+    xyz = periodic_grid((n, n, n), L)
+    rho = np.ones((n, n, n))
+    p = rho / (g * Ma * Ma)
+    if dt is None:
+        dt = 0.3 * h[0] / (3.0 * (4.0 + c))
+    case = Case(name=f"hit{n}", nx=n, ny=n, nz=n, xyz=xyz, U0=conserved(g, rho, vel[0], vel[1], vel[2], p),
+                period=L, h=h, dt=dt, nsteps=nsteps, gamma=g, Re=Re_lambda / lam, Ma=Ma, viscous=6,
+                scheme="hybrid", lowdiss="c8")
+    case.taylor_microscale = lam
+    return case
