@@ -54,6 +54,10 @@ extern "C" {
 #define OCFD_PREC_FP64 0
 #define OCFD_PREC_MIXED 1
 
+/* Shock sensor of the hybrid scheme. */
+#define OCFD_SENSOR_PLAIN 0    /* modified Jameson pressure sensor, eq 42-43 */
+#define OCFD_SENSOR_LEARNED 1  /* perceptron on local flow features (ocfd_sensor_* below) */
+
 /* Parts of the right-hand side for ocfd_dudt (bit mask). */
 #define OCFD_PART_XI 1
 #define OCFD_PART_ETA 2
@@ -93,7 +97,10 @@ typedef struct ocfd_params {
   int32_t scheme;          /* OCFD_SCHEME_* */
   int32_t lowdiss;         /* OCFD_LOWDISS_* */
   int32_t precision;       /* OCFD_PREC_* */
-  int32_t reserved[4];     /* must be zero */
+  int32_t sensor;          /* hybrid only: OCFD_SENSOR_PLAIN (eq 42-43) or OCFD_SENSOR_LEARNED */
+  int32_t sensor_every;    /* learned sensor: re-evaluate the flags every this many substeps (>= 1) */
+  int32_t audit_every;     /* learned sensor: compare with the plain sensor every this many substeps (0: never) */
+  int32_t reserved[1];     /* must be zero */
 } ocfd_params;
 
 typedef struct ocfd_solver ocfd_solver;
@@ -169,6 +176,56 @@ int ocfd_set_flags(ocfd_solver* s, const uint8_t* flags_dev);
 int ocfd_profile(ocfd_solver* s, int32_t enable);
 int ocfd_profile_read(ocfd_solver* s, double* ms_host, int64_t* count_host);
 const char* ocfd_kernel_name(int32_t kernel_class);
+
+/* ---- Learned shock sensor ------------------------------------------------
+   A perceptron 32 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid) maps, for interface
+   j+1/2 along a direction, four features of each of the 8 nodes j-3..j+4
+   (Delta div u / c, Delta |curl u| / c with Delta = (1/J)^(1/3), and the
+   pressure and density jumps |q+ - q-|/(q+ + q-) along that direction) to the
+   probability that the interface needs WENO.  It replaces the pressure sensor
+   of eq 42-43 in the hybrid scheme: an interface takes WENO7 iff p >= tau.
+   Inference and training run on bf16 matrix cores with FP32 accumulation and
+   FP32 master weights.  Parameters: one flat FP32 array of
+   ocfd_sensor_nparams() values: W1 [32 inputs][32 units], b1 [32],
+   W2 [32][32], b2 [32], w3 [32], b3 [1]. */
+int32_t ocfd_sensor_nparams(void);
+int ocfd_sensor_set_params(ocfd_solver* s, const float* params_host);
+int ocfd_sensor_get_params(ocfd_solver* s, float* params_host);
+/* Decision threshold tau (default 0.5; ocfd_sensor_calibrate sets it). */
+int ocfd_sensor_set_threshold(ocfd_solver* s, double tau);
+/* Flags [3][N] (1 = WENO7) of the state U_dev by the plain sensor or by the
+   network, written to flags_dev.  Errors: STATE (network not set). */
+int ocfd_sensor_flags(ocfd_solver* s, const double* U_dev, int32_t which, uint8_t* flags_dev);
+/* Caller-owned device buffer for training samples: each sample is 32 bf16
+   inputs, a label, a weight and bookkeeping, ocfd_sensor_sample_bytes(cap)
+   bytes for cap samples. */
+size_t ocfd_sensor_sample_bytes(int64_t capacity);
+int ocfd_sensor_bind_samples(ocfd_solver* s, void* samples_dev, size_t bytes);
+/* Append samples from the current state labelled by the plain sensor: an
+   interface is kept with probability keep_weno (label 1) or keep_low
+   (label 0) by a counter-based hash of (seed, direction, node), in node order.
+   *total_host receives the number of stored samples.  Synchronises. */
+int ocfd_sensor_collect(ocfd_solver* s, uint64_t seed, double keep_weno, double keep_low, int64_t* total_host);
+/* Train on the first (1 - holdout) of the stored samples: `epochs` passes of
+   mini-batches of `batch` samples in a seeded random order, Adam with
+   learning rate lr.  stats_host[4] = loss of the first and of the last
+   epoch, number of steps, training samples.  Synchronises. */
+int ocfd_sensor_train(ocfd_solver* s, int32_t epochs, int32_t batch, float lr, uint64_t seed, double holdout,
+                      double* stats_host);
+/* Set tau from the held-out samples so that every held-out WENO interface is
+   kept: tau = margin * min probability over them.  out_host[4] = tau,
+   recall, false-positive rate, held-out samples.  Synchronises. */
+int ocfd_sensor_calibrate(ocfd_solver* s, double holdout, double margin, double* out_host);
+/* Loss and gradient over n given samples with the current weights (no
+   update): grad_host[nparams] then the loss.  X_dev: [n][32] bf16 bit
+   patterns.  Synchronises. */
+int ocfd_sensor_grad(ocfd_solver* s, const uint16_t* X_dev, const uint8_t* y_dev, const float* w_dev, int64_t n,
+                     float* grad_host);
+/* Audit counters of the learned sensor since the solver started:
+   out_host[6] = audits run, interfaces compared, plain WENO interfaces,
+   learned WENO interfaces, missed WENO interfaces (fell back to WENO),
+   mismatches.  */
+int ocfd_sensor_audit(ocfd_solver* s, double* out_host);
 
 const char* ocfd_last_error(const ocfd_solver* s);
 void ocfd_destroy(ocfd_solver* s);

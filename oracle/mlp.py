@@ -1,0 +1,151 @@
+"""CPU oracle of the learned shock sensor (test infrastructure only).
+
+The learned sensor replaces the pressure sensor of the hybrid scheme
+(Sec. 2.2.3, eq 42-43) by a small multilayer perceptron that maps a local
+stencil of flow features to the probability that an interface needs the
+WENO stencil.  This module holds, in plain numpy:
+
+* the node features: Delta * div(u) / c, Delta * |curl u| / c (Delta = (1/J)^(1/3),
+  the cell size), and along each grid direction the pressure and density
+  jumps |q(j+1) - q(j-1)| / (q(j+1) + q(j-1)); velocity derivatives are
+  second-order central differences mapped to x, y, z with the node metrics;
+* the interface input: the four features (two shared, two of the interface's
+  direction) of the 8 nodes j-3 .. j+4 of the interface j+1/2, node-major;
+* the network 32 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid), its weighted
+  binary cross-entropy loss and the exact backward pass in FP64;
+* the same forward/backward with values rounded to bfloat16 at the points
+  where the GPU kernels feed its matrix cores (inputs, weights of the two
+  hidden layers, hidden activations, back-propagated pre-activation
+  gradients), so the two can be compared on identical operands.
+
+Parameters are one flat float array: W1 [32 in x 32 out] (row = input),
+b1 [32], W2 [32 x 32], b2 [32], w3 [32], b3 [1].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+NIN, NH = 32, 32
+SIZES = [("W1", (NIN, NH)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)), ("w3", (NH,)), ("b3", (1,))]
+NPARAM = sum(int(np.prod(s)) for _, s in SIZES)
+
+
+def unpack(theta):
+    out, o = {}, 0
+    for name, shape in SIZES:
+        n = int(np.prod(shape))
+        out[name] = np.asarray(theta[o:o + n], dtype=np.float64).reshape(shape)
+        o += n
+    return out
+
+
+def pack(d):
+    return np.concatenate([np.asarray(d[name], dtype=np.float64).ravel() for name, _ in SIZES])
+
+
+def init_params(seed: int = 0):
+    """He-uniform hidden layers, small output layer (numpy PCG64)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    d = {"W1": rng.uniform(-1, 1, (NIN, NH)) * np.sqrt(6.0 / NIN), "b1": np.zeros(NH),
+         "W2": rng.uniform(-1, 1, (NH, NH)) * np.sqrt(6.0 / NH), "b2": np.zeros(NH),
+         "w3": rng.uniform(-1, 1, NH) * np.sqrt(6.0 / NH) * 0.1, "b3": np.zeros(1)}
+    return pack(d)
+
+
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    lsb = (u >> 16) & 1
+    r = ((u + 0x7FFF + lsb) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _sigmoid(z):
+    return 1.0 / (1.0 + np.exp(-z))
+
+
+def forward(theta, X, round_bf16: bool = False):
+    """Probabilities for inputs X [n, 32]; returns (p, cache)."""
+    P = unpack(theta)
+    r = bf16 if round_bf16 else (lambda v: np.asarray(v, dtype=np.float64))
+    x = r(X)
+    a1 = x @ r(P["W1"]) + P["b1"]
+    h1 = r(np.maximum(a1, 0.0))
+    a2 = h1 @ r(P["W2"]) + P["b2"]
+    h2 = np.maximum(a2, 0.0)
+    z = h2 @ P["w3"] + P["b3"][0]
+    return _sigmoid(z), (x, a1, h1, a2, h2, z)
+
+
+def loss_and_grad(theta, X, y, w, round_bf16: bool = False):
+    """Weighted binary cross-entropy  L = -sum_i w_i [y_i log p_i + (1-y_i) log(1-p_i)] / sum_i w_i
+    and its gradient with respect to the flat parameters."""
+    P = unpack(theta)
+    r = bf16 if round_bf16 else (lambda v: np.asarray(v, dtype=np.float64))
+    p, (x, a1, h1, a2, h2, z) = forward(theta, X, round_bf16)
+    y = np.asarray(y, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    W = w.sum()
+    eps = 1e-12
+    L = -np.sum(w * (y * np.log(p + eps) + (1 - y) * np.log(1 - p + eps))) / W
+    dz = w * (p - y) / W                          # dL/dz
+    g = {"w3": h2.T @ dz, "b3": np.array([dz.sum()])}
+    da2 = np.outer(dz, P["w3"]) * (a2 > 0)       # dL/da2
+    g["W2"] = h1.T @ r(da2)
+    g["b2"] = da2.sum(axis=0)
+    dh1 = r(da2) @ r(P["W2"]).T
+    da1 = dh1 * (a1 > 0)
+    g["W1"] = x.T @ r(da1)
+    g["b1"] = da1.sum(axis=0)
+    return L, pack(g)
+
+
+# ------------------------------------------------------------------ features
+
+def node_features(gamma: float, h, met: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Node features [8, nz, ny, nx]: Delta div/c, Delta |curl|/c, then for
+    xi, eta, zeta the pressure jump and the density jump.  Periodic grids."""
+    rho = U[0]
+    vel = [U[1] / rho, U[2] / rho, U[3] / rho]
+    p = (gamma - 1.0) * (U[4] - 0.5 * rho * (vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2))
+    c = np.sqrt(gamma * p / rho)
+    jinv = met[9]
+    axis = {0: 2, 1: 1, 2: 0}
+    # d(vel_a)/d(xi_d), second-order central
+    dvd = [[(np.roll(vel[a], -1, axis[d]) - np.roll(vel[a], 1, axis[d])) / (2.0 * h[d]) for d in range(3)]
+           for a in range(3)]
+    grad = [[sum((met[3 * d + col] / jinv) * dvd[a][d] for d in range(3)) for col in range(3)] for a in range(3)]
+    div = grad[0][0] + grad[1][1] + grad[2][2]
+    wx = grad[2][1] - grad[1][2]
+    wy = grad[0][2] - grad[2][0]
+    wz = grad[1][0] - grad[0][1]
+    vort = np.sqrt(wx * wx + wy * wy + wz * wz)
+    delta = np.cbrt(np.abs(jinv))
+    F = np.zeros((8,) + rho.shape)
+    F[0] = delta * div / c
+    F[1] = delta * vort / c
+    for d in range(3):
+        for k, q in enumerate((p, rho)):
+            qp = np.roll(q, -1, axis[d])
+            qm = np.roll(q, 1, axis[d])
+            F[2 + 2 * d + k] = np.abs(qp - qm) / (qp + qm)
+    return F
+
+
+def interface_inputs(F: np.ndarray, d: int, nodes: np.ndarray) -> np.ndarray:
+    """Inputs [n, 32] of the interfaces (node + 1/2 along direction d) at the
+    given linear node indices: x[4t + f] = feature f of node j - 3 + t."""
+    nz, ny, nx = F.shape[1:]
+    n = (nx, ny, nz)[d]
+    k, j, i = np.unravel_index(nodes, (nz, ny, nx))
+    pos = (i, j, k)[d]
+    X = np.zeros((len(nodes), 32))
+    for t in range(8):
+        q = (pos + t - 3) % n
+        ii, jj, kk = (q if d == 0 else i), (q if d == 1 else j), (q if d == 2 else k)
+        X[:, 4 * t + 0] = F[0][kk, jj, ii]
+        X[:, 4 * t + 1] = F[1][kk, jj, ii]
+        X[:, 4 * t + 2] = F[2 + 2 * d][kk, jj, ii]
+        X[:, 4 * t + 3] = F[3 + 2 * d][kk, jj, ii]
+    return X

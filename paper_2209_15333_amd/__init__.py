@@ -23,6 +23,7 @@ OCFD_OK = 0
 OCFD_SCHEME_WENO7, OCFD_SCHEME_HYBRID = 0, 1
 OCFD_LOWDISS_UD7, OCFD_LOWDISS_C8 = 0, 1
 OCFD_PREC_FP64, OCFD_PREC_MIXED = 0, 1
+OCFD_SENSOR_PLAIN, OCFD_SENSOR_LEARNED = 0, 1
 OCFD_PART_XI, OCFD_PART_ETA, OCFD_PART_ZETA, OCFD_PART_VISC, OCFD_PART_ALL = 1, 2, 4, 8, 15
 OCFD_RED_COUNT = 9
 OCFD_K_COUNT = 6
@@ -41,7 +42,8 @@ class ocfd_params(ctypes.Structure):
         ("weno_eps", ctypes.c_double),
         ("viscous", ctypes.c_int32), ("scheme", ctypes.c_int32), ("lowdiss", ctypes.c_int32),
         ("precision", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("sensor", ctypes.c_int32), ("sensor_every", ctypes.c_int32), ("audit_every", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 1),
     ]
 
 
@@ -84,6 +86,23 @@ def lib() -> ctypes.CDLL:
         L.ocfd_last_error.restype = ctypes.c_char_p
         L.ocfd_destroy.argtypes = [vp]
         L.ocfd_destroy.restype = None
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.ocfd_sensor_nparams.argtypes = []
+        L.ocfd_sensor_nparams.restype = ctypes.c_int32
+        L.ocfd_sensor_set_params.argtypes = [vp, fp]
+        L.ocfd_sensor_get_params.argtypes = [vp, fp]
+        L.ocfd_sensor_set_threshold.argtypes = [vp, ctypes.c_double]
+        L.ocfd_sensor_flags.argtypes = [vp, vp, ctypes.c_int32, vp]
+        L.ocfd_sensor_sample_bytes.argtypes = [ctypes.c_int64]
+        L.ocfd_sensor_sample_bytes.restype = ctypes.c_size_t
+        L.ocfd_sensor_bind_samples.argtypes = [vp, vp, ctypes.c_size_t]
+        L.ocfd_sensor_collect.argtypes = [vp, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
+                                          ctypes.POINTER(ctypes.c_int64)]
+        L.ocfd_sensor_train.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
+                                        ctypes.c_double, dp]
+        L.ocfd_sensor_calibrate.argtypes = [vp, ctypes.c_double, ctypes.c_double, dp]
+        L.ocfd_sensor_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int64, fp]
+        L.ocfd_sensor_audit.argtypes = [vp, dp]
         _lib = L
     return _lib
 
@@ -188,6 +207,82 @@ def ocfd_destroy(h):
     lib().ocfd_destroy(h)
 
 
+def ocfd_sensor_nparams() -> int:
+    return int(lib().ocfd_sensor_nparams())
+
+
+def _f32(a):
+    import numpy as np
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def ocfd_sensor_set_params(h, params):
+    a, p = _f32(params)
+    if a.size != ocfd_sensor_nparams():
+        raise OcfdError(f"expected {ocfd_sensor_nparams()} parameters, got {a.size}")
+    _check(h, lib().ocfd_sensor_set_params(h, p), "ocfd_sensor_set_params")
+
+
+def ocfd_sensor_get_params(h):
+    import numpy as np
+    a, p = _f32(np.zeros(ocfd_sensor_nparams()))
+    _check(h, lib().ocfd_sensor_get_params(h, p), "ocfd_sensor_get_params")
+    return a
+
+
+def ocfd_sensor_set_threshold(h, tau: float):
+    _check(h, lib().ocfd_sensor_set_threshold(h, tau), "ocfd_sensor_set_threshold")
+
+
+def ocfd_sensor_flags(h, U: torch.Tensor, which: int, flags: torch.Tensor):
+    if flags.dtype != torch.uint8:
+        raise OcfdError("flags must be uint8")
+    _check(h, lib().ocfd_sensor_flags(h, _ptr(U), which, _ptr(flags)), "ocfd_sensor_flags")
+
+
+def ocfd_sensor_sample_bytes(capacity: int) -> int:
+    return int(lib().ocfd_sensor_sample_bytes(capacity))
+
+
+def ocfd_sensor_bind_samples(h, buf: torch.Tensor):
+    _check(h, lib().ocfd_sensor_bind_samples(h, _ptr(buf), buf.numel() * buf.element_size()),
+           "ocfd_sensor_bind_samples")
+
+
+def ocfd_sensor_collect(h, seed: int, keep_weno: float, keep_low: float) -> int:
+    tot = ctypes.c_int64()
+    _check(h, lib().ocfd_sensor_collect(h, seed, keep_weno, keep_low, ctypes.byref(tot)), "ocfd_sensor_collect")
+    return tot.value
+
+
+def ocfd_sensor_train(h, epochs: int, batch: int, lr: float, seed: int, holdout: float):
+    out = (ctypes.c_double * 4)()
+    _check(h, lib().ocfd_sensor_train(h, epochs, batch, lr, seed, holdout, out), "ocfd_sensor_train")
+    return list(out)
+
+
+def ocfd_sensor_calibrate(h, holdout: float, margin: float):
+    out = (ctypes.c_double * 4)()
+    _check(h, lib().ocfd_sensor_calibrate(h, holdout, margin, out), "ocfd_sensor_calibrate")
+    return list(out)
+
+
+def ocfd_sensor_grad(h, X: torch.Tensor, y: torch.Tensor, w: torch.Tensor):
+    """X: [n, 32] int16 tensor holding bf16 bit patterns; y uint8 [n]; w float32 [n]."""
+    import numpy as np
+    n = X.shape[0]
+    g, p = _f32(np.zeros(ocfd_sensor_nparams() + 1))
+    _check(h, lib().ocfd_sensor_grad(h, _ptr(X), _ptr(y), _ptr(w), n, p), "ocfd_sensor_grad")
+    return g[:-1], float(g[-1])
+
+
+def ocfd_sensor_audit(h):
+    out = (ctypes.c_double * 6)()
+    _check(h, lib().ocfd_sensor_audit(h, out), "ocfd_sensor_audit")
+    return list(out)
+
+
 # ----------------------------------------------------------------- convenience
 
 def params_from(case, **overrides) -> ocfd_params:
@@ -207,6 +302,9 @@ def params_from(case, **overrides) -> ocfd_params:
     p.scheme = OCFD_SCHEME_HYBRID if case.scheme == "hybrid" else OCFD_SCHEME_WENO7
     p.lowdiss = OCFD_LOWDISS_C8 if case.lowdiss == "c8" else OCFD_LOWDISS_UD7
     p.precision = OCFD_PREC_MIXED if getattr(case, "precision", "fp64") == "mixed" else OCFD_PREC_FP64
+    p.sensor = OCFD_SENSOR_LEARNED if getattr(case, "sensor", "plain") == "learned" else OCFD_SENSOR_PLAIN
+    p.sensor_every = int(getattr(case, "sensor_every", 1))
+    p.audit_every = int(getattr(case, "audit_every", 0))
     for k, v in overrides.items():
         setattr(p, k, v)
     return p

@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -29,6 +31,23 @@ struct ocfd_solver {
   double* partial = nullptr;
   double* red = nullptr;
   const uint8_t* flags = nullptr;
+  // learned sensor
+  float* feat = nullptr;          // [8][N] node features
+  uint8_t* lflags = nullptr;      // [3][N] learned flags
+  uint8_t* pflags = nullptr;      // [3][N] plain flags (audit, collection)
+  float* mlp = nullptr;           // [NPARAM] FP32 master weights
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  float* grad = nullptr;          // [NPARAM + 1]
+  float* gpartial = nullptr;      // [GRAD_BLOCKS][NPARAM + 1]
+  unsigned long long* cnt = nullptr;   // [COUNT_BLOCKS * 4]
+  bool mlp_ready = false;
+  double tau = 0.5;
+  int adam_t = 0;
+  long long substep = 0;
+  double audit[6] = {0, 0, 0, 0, 0, 0};
+  char* smp = nullptr;            // caller-bound sample buffer
+  long long smp_cap = 0, smp_n = 0;
   int stage = 0;
   bool have_grid = false;
   bool have_state = false;
@@ -66,6 +85,9 @@ constexpr int WS_MET = 10, WS_STATE = 5, WS_RHS = 5, WS_PRIM = 4, WS_FV = 12, WS
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+constexpr int GRAD_BLOCKS = 64;     // workgroups of one training step
+constexpr int COUNT_BLOCKS = 1024;  // workgroups of the collection / flag-count passes
+
 bool valid_params(const ocfd_params* p, std::string* why) {
   char buf[256];
   if (!p) { *why = "null params"; return false; }
@@ -87,8 +109,9 @@ bool valid_params(const ocfd_params* p, std::string* why) {
   if (p->lowdiss != OCFD_LOWDISS_UD7 && p->lowdiss != OCFD_LOWDISS_C8) { *why = "unknown lowdiss"; return false; }
   if (!(p->weno_eps > 0.0)) { *why = "weno_eps must be positive"; return false; }
   if (p->precision != OCFD_PREC_FP64 && p->precision != OCFD_PREC_MIXED) { *why = "unknown precision"; return false; }
-  for (int i = 0; i < 4; ++i)
-    if (p->reserved[i] != 0) { *why = "reserved fields must be zero"; return false; }
+  if (p->sensor != OCFD_SENSOR_PLAIN && p->sensor != OCFD_SENSOR_LEARNED) { *why = "unknown sensor"; return false; }
+  if (p->sensor_every < 0 || p->audit_every < 0) { *why = "sensor_every and audit_every must be >= 0"; return false; }
+  if (p->reserved[0] != 0) { *why = "reserved fields must be zero"; return false; }
   return true;
 }
 
@@ -138,6 +161,15 @@ size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver
   double* th = take(WS_THETA * fb);
   double* partial = take((size_t)nred * OCFD_RED_COUNT * sizeof(double));
   double* red = take(16 * sizeof(double));
+  float* feat = (float*)take(8 * (size_t)N * sizeof(float));
+  uint8_t* lflags = (uint8_t*)take(3 * (size_t)N);
+  uint8_t* pflags = (uint8_t*)take(3 * (size_t)N);
+  float* mlp = (float*)take(MLP_NPARAM * sizeof(float));
+  float* am = (float*)take(MLP_NPARAM * sizeof(float));
+  float* av = (float*)take(MLP_NPARAM * sizeof(float));
+  float* grad = (float*)take((MLP_NPARAM + 1) * sizeof(float));
+  float* gpart = (float*)take((size_t)GRAD_BLOCKS * (MLP_NPARAM + 1) * sizeof(float));
+  unsigned long long* cnt = (unsigned long long*)take((size_t)COUNT_BLOCKS * 4 * sizeof(unsigned long long));
   (void)p;
   if (s) {
     s->met = met;
@@ -150,6 +182,15 @@ size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver
     s->theta = th;
     s->partial = partial;
     s->red = red;
+    s->feat = feat;
+    s->lflags = lflags;
+    s->pflags = pflags;
+    s->mlp = mlp;
+    s->adam_m = am;
+    s->adam_v = av;
+    s->grad = grad;
+    s->gpartial = gpart;
+    s->cnt = cnt;
   }
   return off;
 }
@@ -192,8 +233,53 @@ bool ready(ocfd_solver* s, int* rc) {
 
 // Evaluate the right-hand side of U_cur.  mode MODE_RK writes the next stage
 // into out; MODE_DUDT writes dU/dt into out.
+// Flags of the learned sensor for this substep: the network is re-evaluated
+// every sensor_every substeps; every audit_every substeps the plain sensor is
+// evaluated too, and interfaces it marks but the network missed fall back to
+// WENO (the union of both flag fields is used).
+int learned_flags(ocfd_solver* s, const double* Ucur, bool count_substep) {
+  if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "learned sensor selected but no network parameters set");
+  hipError_t e = hipSuccess;
+  const long long k = s->substep;
+  const int every = s->p.sensor_every > 0 ? s->p.sensor_every : 1;
+  if (!count_substep || k % every == 0) {
+    Timed tm(s, OCFD_K_OTHER);
+    e = launch_features(s->g, s->ph, Ucur, s->met, s->feat, s->st);
+    if (e == hipSuccess) e = launch_mlp_flags(s->g, s->feat, s->mlp, (float)s->tau, s->lflags, s->st);
+    if (e != hipSuccess) return hip_fail(s, e, "learned sensor kernels");
+  }
+  if (count_substep && s->p.audit_every > 0 && k % s->p.audit_every == 0) {
+    e = launch_sensor(s->g, s->ph, Ucur, s->theta, s->st);
+    if (e == hipSuccess) e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
+    if (e == hipSuccess) e = launch_flag_stats(s->pflags, s->lflags, 3 * s->g.N, s->cnt, COUNT_BLOCKS, s->st);
+    std::vector<unsigned long long> c(COUNT_BLOCKS * 4);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(c.data(), s->cnt, c.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    if (e != hipSuccess) return hip_fail(s, e, "sensor audit");
+    unsigned long long plain = 0, missed = 0, extra = 0, mism = 0;
+    for (int b = 0; b < COUNT_BLOCKS; ++b) {
+      plain += c[4 * b];
+      missed += c[4 * b + 2];   // plain WENO, learned low
+      extra += c[4 * b + 1];
+      mism += c[4 * b + 3];
+    }
+    s->audit[0] += 1;
+    s->audit[1] += 3.0 * (double)s->g.N;
+    s->audit[2] += (double)plain;
+    s->audit[3] += (double)(plain - missed + extra);
+    s->audit[4] += (double)missed;
+    s->audit[5] += (double)mism;
+    if (missed) {
+      e = launch_flags_or(s->lflags, s->pflags, 3 * s->g.N, s->st);
+      if (e != hipSuccess) return hip_fail(s, e, "flag union");
+    }
+  }
+  return OCFD_OK;
+}
+
 int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const double* Un, double a, double b,
-            double dt, int parts) {
+            double dt, int parts, bool count_substep = false) {
   hipError_t e;
   const bool visc = s->p.viscous && (parts & OCFD_PART_VISC);
   const bool hyb = s->p.scheme == OCFD_SCHEME_HYBRID;
@@ -209,7 +295,12 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
     }
     if (e != hipSuccess) return hip_fail(s, e, "viscous flux kernel");
   }
-  if (hyb && !s->flags) {
+  const uint8_t* flags = s->flags;
+  if (hyb && !flags && s->p.sensor == OCFD_SENSOR_LEARNED) {
+    int rc = learned_flags(s, Ucur, count_substep);
+    if (rc) return rc;
+    flags = s->lflags;
+  } else if (hyb && !flags) {
     Timed tm(s, OCFD_K_OTHER);
     e = launch_sensor(s->g, s->ph, Ucur, s->theta, s->st);
     if (e != hipSuccess) return hip_fail(s, e, "sensor kernel");
@@ -222,7 +313,7 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
   A.met = s->met;
   A.Fv = visc ? s->Fv : nullptr;
   A.theta = s->theta;
-  A.flags = s->flags;
+  A.flags = flags;
   A.rhs = s->rhs;
   A.Un = Un;
   A.out = out;
@@ -268,6 +359,9 @@ int ocfd_params_default(ocfd_params* p) {
   p->viscous = 6;
   p->scheme = OCFD_SCHEME_WENO7;
   p->lowdiss = OCFD_LOWDISS_C8;
+  p->sensor = OCFD_SENSOR_PLAIN;
+  p->sensor_every = 1;
+  p->audit_every = 0;
   return OCFD_OK;
 }
 
@@ -403,9 +497,10 @@ int ocfd_advance(ocfd_solver* s, int32_t n, double dt) {
     const int k = s->stage;
     const double* cur = s->Ub[k];
     double* nxt = s->Ub[(k + 1) % 3];
-    rc = run_rhs(s, cur, MODE_RK, nxt, s->Ub[0], A[k], B[k], dt, OCFD_PART_ALL);
+    rc = run_rhs(s, cur, MODE_RK, nxt, s->Ub[0], A[k], B[k], dt, OCFD_PART_ALL, true);
     if (rc) return rc;
     s->stage = (k + 1) % 3;
+    s->substep += 1;
   }
   return OCFD_OK;
 }
@@ -467,6 +562,253 @@ int ocfd_profile_read(ocfd_solver* s, double* ms, int64_t* count) {
     ms[r.cls] += t;
     count[r.cls] += 1;
   }
+  return OCFD_OK;
+}
+
+// ---------------------------------------------------------------- learned sensor
+
+int32_t ocfd_sensor_nparams(void) { return MLP_NPARAM; }
+
+int ocfd_sensor_set_params(ocfd_solver* s, const float* P) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!P) return fail(s, OCFD_ERR_BADARG, "null parameters");
+  for (int k = 0; k < MLP_NPARAM; ++k)
+    if (!std::isfinite(P[k])) return fail(s, OCFD_ERR_BADARG, "non-finite parameter %d", k);
+  hipError_t e = hipMemcpyAsync(s->mlp, P, MLP_NPARAM * sizeof(float), hipMemcpyHostToDevice, s->st);
+  if (e == hipSuccess) e = hipMemsetAsync(s->adam_m, 0, MLP_NPARAM * sizeof(float), s->st);
+  if (e == hipSuccess) e = hipMemsetAsync(s->adam_v, 0, MLP_NPARAM * sizeof(float), s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "parameter upload");
+  s->adam_t = 0;
+  s->mlp_ready = true;
+  return OCFD_OK;
+}
+
+int ocfd_sensor_get_params(ocfd_solver* s, float* P) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!P) return fail(s, OCFD_ERR_BADARG, "null parameters");
+  if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "no network parameters set");
+  hipError_t e = hipMemcpyAsync(P, s->mlp, MLP_NPARAM * sizeof(float), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "parameter download");
+}
+
+int ocfd_sensor_set_threshold(ocfd_solver* s, double tau) {
+  if (!s) return OCFD_ERR_BADARG;
+  if (!(tau >= 0.0 && tau <= 1.0)) return fail(s, OCFD_ERR_BADARG, "threshold %g not in [0, 1]", tau);
+  s->tau = tau;
+  return OCFD_OK;
+}
+
+int ocfd_sensor_flags(ocfd_solver* s, const double* U, int32_t which, uint8_t* flags) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!U || !flags) return fail(s, OCFD_ERR_BADARG, "null argument");
+  if (!s->have_grid) return fail(s, OCFD_ERR_STATE, "no grid set");
+  hipError_t e;
+  if (which == OCFD_SENSOR_PLAIN) {
+    e = launch_sensor(s->g, s->ph, U, s->theta, s->st);
+    if (e == hipSuccess) e = launch_plain_flags(s->g, s->ph.theta1, s->theta, flags, s->st);
+  } else if (which == OCFD_SENSOR_LEARNED) {
+    if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "no network parameters set");
+    e = launch_features(s->g, s->ph, U, s->met, s->feat, s->st);
+    if (e == hipSuccess) e = launch_mlp_flags(s->g, s->feat, s->mlp, (float)s->tau, flags, s->st);
+  } else {
+    return fail(s, OCFD_ERR_BADARG, "unknown sensor %d", which);
+  }
+  return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "sensor kernels");
+}
+
+// Sample buffer layout for capacity C: X [C][32] bf16 | w [C] f32 | idx [C] i32 | prob [C] f32 | y [C] u8.
+static size_t smp_off_w(long long C) { return (size_t)C * 64; }
+static size_t smp_off_idx(long long C) { return smp_off_w(C) + (size_t)C * 4; }
+static size_t smp_off_prob(long long C) { return smp_off_idx(C) + (size_t)C * 4; }
+static size_t smp_off_y(long long C) { return smp_off_prob(C) + (size_t)C * 4; }
+
+size_t ocfd_sensor_sample_bytes(int64_t capacity) { return capacity > 0 ? smp_off_y(capacity) + (size_t)capacity : 0; }
+
+int ocfd_sensor_bind_samples(ocfd_solver* s, void* dev, size_t bytes) {
+  if (!s) return OCFD_ERR_BADARG;
+  if (!dev) return fail(s, OCFD_ERR_BADARG, "null sample buffer");
+  if (((uintptr_t)dev) & 255) return fail(s, OCFD_ERR_BADARG, "sample buffer not 256-byte aligned");
+  long long cap = (long long)(bytes / 77);
+  while (cap > 0 && ocfd_sensor_sample_bytes(cap) > bytes) --cap;
+  if (cap < 16) return fail(s, OCFD_ERR_BADSIZE, "sample buffer of %zu bytes holds fewer than 16 samples", bytes);
+  s->smp = (char*)dev;
+  s->smp_cap = cap;
+  s->smp_n = 0;
+  return OCFD_OK;
+}
+
+int ocfd_sensor_collect(ocfd_solver* s, uint64_t seed, double keep_weno, double keep_low, int64_t* total) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!total) return fail(s, OCFD_ERR_BADARG, "null output");
+  if (!s->smp) return fail(s, OCFD_ERR_STATE, "no sample buffer bound");
+  if (!s->have_grid || !s->have_state) return fail(s, OCFD_ERR_STATE, "grid and state must be set first");
+  if (!(keep_weno >= 0 && keep_weno <= 1 && keep_low >= 0 && keep_low <= 1))
+    return fail(s, OCFD_ERR_BADARG, "keep probabilities must be in [0, 1]");
+  const uint32_t tp = (uint32_t)std::min(4294967295.0, keep_weno * 4294967296.0);
+  const uint32_t tl = (uint32_t)std::min(4294967295.0, keep_low * 4294967296.0);
+  const double* U = s->Ub[s->stage];
+  hipError_t e = launch_sensor(s->g, s->ph, U, s->theta, s->st);
+  if (e == hipSuccess) e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
+  if (e == hipSuccess) e = launch_features(s->g, s->ph, U, s->met, s->feat, s->st);
+  if (e == hipSuccess) e = launch_collect_count(s->g, s->pflags, seed, tp, tl, s->cnt, COUNT_BLOCKS, s->st);
+  std::vector<unsigned long long> c(COUNT_BLOCKS);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(c.data(), s->cnt, COUNT_BLOCKS * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "sample count");
+  unsigned long long acc = (unsigned long long)s->smp_n;
+  for (int b = 0; b < COUNT_BLOCKS; ++b) {
+    const unsigned long long v = c[b];
+    c[b] = acc;
+    acc += v;
+  }
+  e = hipMemcpyAsync(s->cnt, c.data(), COUNT_BLOCKS * sizeof(unsigned long long), hipMemcpyHostToDevice, s->st);
+  const long long C = s->smp_cap;
+  if (e == hipSuccess)
+    e = launch_collect_write(s->g, s->pflags, s->feat, seed, tp, tl, s->cnt, C, (uint16_t*)s->smp,
+                             (uint8_t*)(s->smp + smp_off_y(C)), (float*)(s->smp + smp_off_w(C)), COUNT_BLOCKS, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "sample write");
+  s->smp_n = (long long)std::min<unsigned long long>(acc, (unsigned long long)C);
+  *total = s->smp_n;
+  return OCFD_OK;
+}
+
+// One gradient evaluation (and Adam step when lr > 0) over nb samples listed in idx_dev.
+static int grad_step(ocfd_solver* s, const uint16_t* X, const uint8_t* y, const float* w, const int* idx, long long nb,
+                     float Wsum, float lr) {
+  if (lr > 0.f) s->adam_t += 1;
+  hipError_t e = launch_mlp_grad(X, y, w, idx, nb, Wsum, s->mlp, s->gpartial, GRAD_BLOCKS, s->grad, s->mlp,
+                                 s->adam_m, s->adam_v, lr, s->adam_t, s->st);
+  return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "training kernels");
+}
+
+int ocfd_sensor_train(ocfd_solver* s, int32_t epochs, int32_t batch, float lr, uint64_t seed, double holdout,
+                      double* stats) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!stats) return fail(s, OCFD_ERR_BADARG, "null output");
+  if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "set initial network parameters first");
+  if (epochs < 1 || batch < 16 || !(lr > 0.f) || !(holdout >= 0.0 && holdout < 1.0))
+    return fail(s, OCFD_ERR_BADARG, "bad training arguments");
+  const long long C = s->smp_cap;
+  const long long ntrain = (long long)((1.0 - holdout) * (double)s->smp_n);
+  if (ntrain < batch) return fail(s, OCFD_ERR_STATE, "%lld training samples, fewer than one batch", ntrain);
+  std::vector<float> hw(ntrain);
+  hipError_t e = hipMemcpyAsync(hw.data(), s->smp + smp_off_w(C), ntrain * sizeof(float), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "weight download");
+  std::vector<int> perm(ntrain);
+  std::mt19937_64 rng(seed);
+  int* didx = (int*)(s->smp + smp_off_idx(C));
+  const uint16_t* X = (const uint16_t*)s->smp;
+  const uint8_t* y = (const uint8_t*)(s->smp + smp_off_y(C));
+  const float* w = (const float*)(s->smp + smp_off_w(C));
+  double first = 0, last = 0;
+  long long steps = 0;
+  for (int ep = 0; ep < epochs; ++ep) {
+    for (long long k = 0; k < ntrain; ++k) perm[k] = (int)k;
+    std::shuffle(perm.begin(), perm.end(), rng);
+    e = hipMemcpyAsync(didx, perm.data(), ntrain * sizeof(int), hipMemcpyHostToDevice, s->st);
+    if (e != hipSuccess) return hip_fail(s, e, "index upload");
+    double eloss = 0.0;
+    long long nbatch = 0;
+    for (long long b0 = 0; b0 + batch <= ntrain; b0 += batch) {
+      double W = 0.0;
+      for (long long k = b0; k < b0 + batch; ++k) W += hw[perm[k]];
+      rc = grad_step(s, X, y, w, didx + b0, batch, (float)W, lr);
+      if (rc) return rc;
+      float L = 0.f;
+      e = hipMemcpyAsync(&L, s->grad + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToHost, s->st);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+      if (e != hipSuccess) return hip_fail(s, e, "loss download");
+      eloss += L;
+      nbatch += 1;
+      steps += 1;
+    }
+    eloss /= (double)(nbatch > 0 ? nbatch : 1);
+    if (ep == 0) first = eloss;
+    last = eloss;
+  }
+  stats[0] = first;
+  stats[1] = last;
+  stats[2] = (double)steps;
+  stats[3] = (double)ntrain;
+  return OCFD_OK;
+}
+
+int ocfd_sensor_calibrate(ocfd_solver* s, double holdout, double margin, double* out) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!out) return fail(s, OCFD_ERR_BADARG, "null output");
+  if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "no network parameters set");
+  if (!(holdout > 0.0 && holdout < 1.0) || !(margin > 0.0 && margin <= 1.0))
+    return fail(s, OCFD_ERR_BADARG, "holdout in (0,1) and margin in (0,1] required");
+  const long long C = s->smp_cap;
+  const long long a = (long long)((1.0 - holdout) * (double)s->smp_n);
+  const long long nh = s->smp_n - a;
+  if (nh < 1) return fail(s, OCFD_ERR_STATE, "no held-out samples");
+  float* prob = (float*)(s->smp + smp_off_prob(C));
+  hipError_t e = launch_mlp_prob((const uint16_t*)s->smp + a * 32, nh, s->mlp, prob, s->st);
+  std::vector<float> p(nh);
+  std::vector<uint8_t> y(nh);
+  if (e == hipSuccess) e = hipMemcpyAsync(p.data(), prob, nh * sizeof(float), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipMemcpyAsync(y.data(), s->smp + smp_off_y(C) + a, nh, hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "calibration");
+  double pmin = 1.0;
+  long long npos = 0, nneg = 0;
+  for (long long k = 0; k < nh; ++k)
+    if (y[k]) { pmin = std::min(pmin, (double)p[k]); ++npos; } else { ++nneg; }
+  s->tau = npos ? margin * pmin : 0.5;
+  long long fp = 0, tp = 0;
+  for (long long k = 0; k < nh; ++k) {
+    const bool on = p[k] >= (float)s->tau;
+    if (y[k] && on) ++tp;
+    if (!y[k] && on) ++fp;
+  }
+  out[0] = s->tau;
+  out[1] = npos ? (double)tp / (double)npos : 1.0;
+  out[2] = nneg ? (double)fp / (double)nneg : 0.0;
+  out[3] = (double)nh;
+  return OCFD_OK;
+}
+
+int ocfd_sensor_grad(ocfd_solver* s, const uint16_t* X, const uint8_t* y, const float* w, int64_t n, float* grad) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!X || !y || !w || !grad || n < 1) return fail(s, OCFD_ERR_BADARG, "bad argument");
+  if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "no network parameters set");
+  if (!s->smp || s->smp_cap < n) return fail(s, OCFD_ERR_STATE, "bind a sample buffer of at least n samples");
+  std::vector<int> idx(n);
+  std::vector<float> hw(n);
+  double W = 0.0;
+  hipError_t e = hipMemcpyAsync(hw.data(), w, n * sizeof(float), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "weight download");
+  for (long long k = 0; k < n; ++k) {
+    idx[k] = (int)k;
+    W += hw[k];
+  }
+  int* didx = (int*)(s->smp + smp_off_idx(s->smp_cap));
+  e = hipMemcpyAsync(didx, idx.data(), n * sizeof(int), hipMemcpyHostToDevice, s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "index upload");
+  rc = grad_step(s, X, y, w, didx, n, (float)W, 0.f);
+  if (rc) return rc;
+  e = hipMemcpyAsync(grad, s->grad, (MLP_NPARAM + 1) * sizeof(float), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "gradient download");
+}
+
+int ocfd_sensor_audit(ocfd_solver* s, double* out) {
+  if (!s || !out) return OCFD_ERR_BADARG;
+  for (int k = 0; k < 6; ++k) out[k] = s->audit[k];
   return OCFD_OK;
 }
 

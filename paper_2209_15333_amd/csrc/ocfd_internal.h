@@ -8,6 +8,18 @@
 
 namespace ocfd {
 
+// Learned-sensor perceptron 32 -> 32 -> 32 -> 1: offsets in the flat FP32
+// parameter array (W1 [input][unit], b1, W2 [input][unit], b2, w3, b3).
+constexpr int MLP_IN = 32;
+constexpr int MLP_H = 32;
+constexpr int MLP_W1 = 0;
+constexpr int MLP_B1 = MLP_W1 + MLP_IN * MLP_H;
+constexpr int MLP_W2 = MLP_B1 + MLP_H;
+constexpr int MLP_B2 = MLP_W2 + MLP_H * MLP_H;
+constexpr int MLP_W3 = MLP_B2 + MLP_H;
+constexpr int MLP_B3 = MLP_W3 + MLP_H;
+constexpr int MLP_NPARAM = MLP_B3 + 1;
+
 // Grid geometry: node counts and element strides of xi, eta, zeta.
 struct Geo {
   int n[3];
@@ -69,5 +81,24 @@ hipError_t launch_metric_outer(const Geo& g, const Phys& ph, const double* xyz, 
 hipError_t launch_reduce(const Geo& g, const Phys& ph, const double* U, const double* met, double dt,
                          double* partial, int nblocks, double* out, hipStream_t st);
 int reduce_blocks(const Geo& g);
+
+// Sensors (ocfd_sensor.hip).
+hipError_t launch_plain_flags(const Geo& g, double theta1, const double* theta, uint8_t* flags, hipStream_t st);
+hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, float* feat,
+                           hipStream_t st);
+hipError_t launch_mlp_flags(const Geo& g, const float* feat, const float* P, float tau, uint8_t* flags,
+                            hipStream_t st);
+hipError_t launch_mlp_prob(const uint16_t* X, long long S, const float* P, float* prob, hipStream_t st);
+hipError_t launch_mlp_grad(const uint16_t* X, const uint8_t* y, const float* w, const int* idx, long long nb,
+                           float Wsum, const float* P, float* partial, int nblocks, float* grad, float* Pmut,
+                           float* m, float* v, float lr, int t, hipStream_t st);
+hipError_t launch_collect_count(const Geo& g, const uint8_t* flags, uint64_t seed, uint32_t thr_pos, uint32_t thr_neg,
+                                unsigned long long* counts, int nblocks, hipStream_t st);
+hipError_t launch_collect_write(const Geo& g, const uint8_t* flags, const float* feat, uint64_t seed, uint32_t thr_pos,
+                                uint32_t thr_neg, const unsigned long long* offs, long long cap, uint16_t* X,
+                                uint8_t* y, float* w, int nblocks, hipStream_t st);
+hipError_t launch_flags_or(uint8_t* a, const uint8_t* b, long long n, hipStream_t st);
+hipError_t launch_flag_stats(const uint8_t* fa, const uint8_t* fb, long long total, unsigned long long* out,
+                             int nblocks, hipStream_t st);
 
 }  // namespace ocfd

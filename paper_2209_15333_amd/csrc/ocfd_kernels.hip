@@ -178,6 +178,8 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   __shared__ R ring[RING * SLOT];
   __shared__ double fh[(SW_S + 1) * FHS];  // fh[0]: carried flux; fh[s+1]: interface j0+s
   __shared__ double fh0[FHS];             // flux at 1/2, for node 0 of a periodic line
+  __shared__ int wl_n;                    // hybrid: WENO work list of this chunk
+  __shared__ short wl[SW_T];
 
   const int n = A.g.n[DIR];
   const int ncol = A.g.n[CD];
@@ -289,17 +291,46 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   NodeIn ahead;
   bool have = A.inviscid && gcol_ok && 4 + gs <= n + 3;
   if (have) ahead = fetch(JB + 4 + gs, gc);
+  // Reconstruction of interface j of line col into dst (WENO7 or low-dissipation stencil).
+  auto reconstruct = [&](int j, int col, bool low, double* dst) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const R* P = ring + col + q * SW_W;
+      const R* M = ring + col + (5 + q) * SW_W;
+#define RP(o) P[((j + (o)) & (RING - 1)) * SLOT]
+#define RM(o) M[((j + (o)) & (RING - 1)) * SLOT]
+      double F;
+      if (HYB && low) {
+        if (A.lowdiss == OCFD_LOWDISS_C8)
+          F = (double)c8<R>(RP(-3) + RM(-3), RP(-2) + RM(-2), RP(-1) + RM(-1), RP(0) + RM(0), RP(1) + RM(1),
+                            RP(2) + RM(2), RP(3) + RM(3), RP(4) + RM(4));
+        else
+          F = (double)ud7<R>(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3)) +
+              (double)ud7<R>(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2));
+      } else {
+        F = (double)weno7<R>(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3), eps) +
+            (double)weno7<R>(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2), eps);
+      }
+#undef RP
+#undef RM
+      dst[q * SW_W] = F;
+    }
+  };
+
   for (int c = 0; c < nchunks; ++c) {
     const int j0 = JB + c * SW_S;
     if (have) split_store(j0 + 4 + gs, gc, ahead);
+    if (HYB && t == 0) wl_n = 0;
     __syncthreads();
     have = A.inviscid && gcol_ok && c + 1 < nchunks && (c + 1) * SW_S + 4 + gs <= n + 3;
     if (have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
     const int j = j0 + rs;
-    if (A.inviscid && rcol_ok && c * SW_S + rs < n) {
-      double* dst = fh + (rs + 1) * FHS + rc;
-      bool low = false;
-      if (HYB) {
+    const bool act = A.inviscid && rcol_ok && c * SW_S + rs < n;
+    if (HYB) {
+      // Low-dissipation interfaces are done in place; WENO interfaces go to a
+      // work list so that whole waves run the WENO code (no divergence).
+      if (act) {
+        bool low;
         if (A.flags) {
           low = A.flags[DIR * N + base + (long long)rc * sc + (long long)(n >= 8 ? wrap1(j, n) : wrap(j, n)) * sd] == 0;
         } else {
@@ -308,29 +339,19 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
           for (int o = -3; o <= 4; ++o) mx = fmax(mx, ring[((j + o) & (RING - 1)) * SLOT + 10 * SW_W + rc]);
           low = mx <= (R)A.ph.theta1;
         }
+        if (low)
+          reconstruct(j, rc, true, fh + (rs + 1) * FHS + rc);
+        else
+          wl[atomicAdd(&wl_n, 1)] = (short)t;
       }
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        const R* P = ring + rc + q * SW_W;
-        const R* M = ring + rc + (5 + q) * SW_W;
-#define RP(o) P[((j + (o)) & (RING - 1)) * SLOT]
-#define RM(o) M[((j + (o)) & (RING - 1)) * SLOT]
-        double F;
-        if (HYB && low) {
-          if (A.lowdiss == OCFD_LOWDISS_C8)
-            F = (double)c8<R>(RP(-3) + RM(-3), RP(-2) + RM(-2), RP(-1) + RM(-1), RP(0) + RM(0), RP(1) + RM(1),
-                              RP(2) + RM(2), RP(3) + RM(3), RP(4) + RM(4));
-          else
-            F = (double)ud7<R>(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3)) +
-                (double)ud7<R>(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2));
-        } else {
-          F = (double)weno7<R>(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3), eps) +
-              (double)weno7<R>(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2), eps);
-        }
-#undef RP
-#undef RM
-        dst[q * SW_W] = F;
+      __syncthreads();
+      if (t < wl_n) {
+        const int tt = wl[t];
+        const int s2 = tt / SW_W, c2 = tt & (SW_W - 1);
+        reconstruct(j0 + s2, c2, false, fh + (s2 + 1) * FHS + c2);
       }
+    } else if (act) {
+      reconstruct(j, rc, false, fh + (rs + 1) * FHS + rc);
     }
     __syncthreads();
     if (c == 0 && t < 5 * SW_W) fh0[(t / SW_W) * SW_W + (t % SW_W)] = fh[FHS + (t / SW_W) * SW_W + (t % SW_W)];

@@ -1,0 +1,575 @@
+// Shock sensors of the hybrid scheme (Sec. 2.2.3, eq 42-43) and the learned
+// sensor that can replace the pressure sensor: node features, per-interface
+// flags, a 32-32-32-1 perceptron evaluated and trained with bf16 matrix-core
+// (MFMA) instructions, sample collection, calibration and audit.
+//
+// MFMA operand layout used throughout (v_mfma_f32_16x16x32_bf16, one wave):
+//   A (16 x 32): lane l holds row l%16, columns 8*(l/16) .. 8*(l/16)+7;
+//   B (32 x 16): lane l holds column l%16, rows 8*(l/16) .. 8*(l/16)+7;
+//   C (16 x 16): lane l holds column l%16, rows 4*(l/16) .. 4*(l/16)+3.
+// and for v_mfma_f32_16x16x16bf16_1k the same with 4 values per lane.
+// Activations are kept transposed (hidden unit x sample), so a layer's C
+// registers are the next layer's B operand after a fixed relabelling of the
+// hidden units: k-slot 8g+q of lane group g holds unit 4g+q (q < 4) or
+// 16+4g+q-4 (q >= 4).  The relabelling is applied to the weights instead.
+#include "ocfd_internal.h"
+
+namespace ocfd {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ int wrapn(int p, int n) {
+  while (p < 0) p += n;
+  while (p >= n) p -= n;
+  return p;
+}
+
+// Hidden unit held in k-slot q (0..7) of lane group g.
+__device__ __forceinline__ int unit_of(int g, int q) { return q < 4 ? 4 * g + q : 16 + 4 * g + (q - 4); }
+
+__device__ __forceinline__ v4f mfma32(const v8bf& a, const v8bf& b, const v4f& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ v4f mfma16(const v4bf& a, const v4bf& b, const v4f& c) {
+  v4s as, bs;
+  __builtin_memcpy(&as, &a, 8);
+  __builtin_memcpy(&bs, &b, 8);
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(as, bs, c, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Plain sensor flags: interface j+1/2 along d is low-dissipation iff the node
+// sensor theta is <= theta1 at every node j-3 .. j+4.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_plain_flags(const Geo g, double theta1, const double* __restrict__ theta,
+                                                     uint8_t* __restrict__ flags) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= g.N) return;
+  const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
+  for (int d = 0; d < 3; ++d) {
+    double mx = 0.0;
+    for (int o = -3; o <= 4; ++o) mx = fmax(mx, theta[id + (long long)(wrapn(pos[d] + o, g.n[d]) - pos[d]) * g.s[d]]);
+    flags[d * g.N + id] = mx <= theta1 ? 0 : 1;
+  }
+}
+
+hipError_t launch_plain_flags(const Geo& g, double theta1, const double* theta, uint8_t* flags, hipStream_t st) {
+  hipLaunchKernelGGL(k_plain_flags, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, theta1, theta, flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Node features: Delta div(u)/c, Delta |curl u|/c (Delta = (1/J)^(1/3)), and
+// per direction the pressure and density jumps |q+ - q-| / (q+ + q-).
+// Velocity derivatives: second-order central, chain rule with node metrics.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_features(const Geo g, const Phys ph, const double* __restrict__ U,
+                                                  const double* __restrict__ met, float* __restrict__ feat) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= g.N) return;
+  const long long N = g.N;
+  const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
+  double dvd[3][3];  // d(vel_a)/d(xi_d)
+  double jp[3], jr[3];
+  for (int d = 0; d < 3; ++d) {
+    const long long ip = id + (long long)(wrapn(pos[d] + 1, g.n[d]) - pos[d]) * g.s[d];
+    const long long im = id + (long long)(wrapn(pos[d] - 1, g.n[d]) - pos[d]) * g.s[d];
+    double vp[3], vm[3];
+    const double rp = U[ip], rm = U[im];
+    for (int a = 0; a < 3; ++a) {
+      vp[a] = U[(a + 1) * N + ip] / rp;
+      vm[a] = U[(a + 1) * N + im] / rm;
+    }
+    const double pp = ph.gm1 * (U[4 * N + ip] - 0.5 * rp * (vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2]));
+    const double pm = ph.gm1 * (U[4 * N + im] - 0.5 * rm * (vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2]));
+    for (int a = 0; a < 3; ++a) dvd[a][d] = (vp[a] - vm[a]) / (2.0 * ph.h[d]);
+    jp[d] = fabs(pp - pm) / (pp + pm);
+    jr[d] = fabs(rp - rm) / (rp + rm);
+  }
+  const double jinv = met[9 * N + id];
+  double gr[3][3];
+  for (int a = 0; a < 3; ++a)
+    for (int c = 0; c < 3; ++c) {
+      double s = 0.0;
+      for (int d = 0; d < 3; ++d) s += (met[(3 * d + c) * N + id] / jinv) * dvd[a][d];
+      gr[a][c] = s;
+    }
+  const double div = gr[0][0] + gr[1][1] + gr[2][2];
+  const double wx = gr[2][1] - gr[1][2], wy = gr[0][2] - gr[2][0], wz = gr[1][0] - gr[0][1];
+  const double vort = sqrt(wx * wx + wy * wy + wz * wz);
+  const double rho = U[id];
+  const double u = U[N + id] / rho, v = U[2 * N + id] / rho, w = U[3 * N + id] / rho;
+  const double p = ph.gm1 * (U[4 * N + id] - 0.5 * rho * (u * u + v * v + w * w));
+  const double c = sqrt(ph.gamma * p / rho);
+  const double delta = cbrt(fabs(jinv));
+  feat[id] = (float)(delta * div / c);
+  feat[N + id] = (float)(delta * vort / c);
+  for (int d = 0; d < 3; ++d) {
+    feat[(2 + 2 * d) * N + id] = (float)jp[d];
+    feat[(3 + 2 * d) * N + id] = (float)jr[d];
+  }
+}
+
+hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, float* feat,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, U, met, feat);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The perceptron
+// ---------------------------------------------------------------------------
+
+// Per-lane weight registers of one wave.
+struct MlpRegs {
+  v8bf A1[2];   // W1^T tiles: row = hidden 16m + l%16, cols = inputs 8g..8g+7
+  v8bf A2[2];   // W2^T tiles, input hidden units relabelled by unit_of
+  float b1[2][4], b2[2][4], w3[2][4];
+  float b3;
+};
+
+__device__ __forceinline__ void load_mlp(const float* __restrict__ P, MlpRegs& R) {
+  const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
+  for (int m = 0; m < 2; ++m) {
+    for (int q = 0; q < 8; ++q) {
+      R.A1[m][q] = (__bf16)P[MLP_W1 + (8 * g + q) * MLP_H + 16 * m + i];
+      R.A2[m][q] = (__bf16)P[MLP_W2 + unit_of(g, q) * MLP_H + 16 * m + i];
+    }
+    for (int r = 0; r < 4; ++r) {
+      R.b1[m][r] = P[MLP_B1 + 16 * m + 4 * g + r];
+      R.b2[m][r] = P[MLP_B2 + 16 * m + 4 * g + r];
+      R.w3[m][r] = P[MLP_W3 + 16 * m + 4 * g + r];
+    }
+  }
+  R.b3 = P[MLP_B3];
+}
+
+struct Fwd {
+  v4f a1[2], a2[2];  // pre-activations, C layout (unit 16m + 4g + r, sample l%16)
+  v8bf h1;           // relu(a1) as the B operand of layer 2
+  float z;           // output logit of sample l%16 (same in the four lane groups)
+};
+
+// Forward pass of 16 samples held as the B operand x (inputs 8g..8g+7 of sample l%16).
+__device__ __forceinline__ void mlp_forward(const MlpRegs& R, const v8bf& x, Fwd& F) {
+  const v4f zero = {0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < 2; ++m) {
+    F.a1[m] = mfma32(R.A1[m], x, zero);
+    for (int r = 0; r < 4; ++r) F.a1[m][r] += R.b1[m][r];
+  }
+  for (int q = 0; q < 8; ++q) {
+    const float a = q < 4 ? F.a1[0][q] : F.a1[1][q - 4];
+    F.h1[q] = (__bf16)fmaxf(a, 0.f);
+  }
+  float z = 0.f;
+  for (int m = 0; m < 2; ++m) {
+    F.a2[m] = mfma32(R.A2[m], F.h1, zero);
+    for (int r = 0; r < 4; ++r) {
+      F.a2[m][r] += R.b2[m][r];
+      z += R.w3[m][r] * fmaxf(F.a2[m][r], 0.f);
+    }
+  }
+  // sum over the four lane groups (hidden units) of each sample
+  z += __shfl_xor(z, 16);
+  z += __shfl_xor(z, 32);
+  F.z = z + R.b3;
+}
+
+__device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + __expf(-z)); }
+
+// Learned flags of every interface: x of interface (d, node) = features
+// (f0, f1, jump_p[d], jump_rho[d]) of the 8 nodes j-3 .. j+4 along d.
+__global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const float* __restrict__ feat,
+                                                   const float* __restrict__ P, float tau,
+                                                   uint8_t* __restrict__ flags) {
+  MlpRegs R;
+  load_mlp(P, R);
+  const int l = threadIdx.x & 63, j = l & 15, gg = l >> 4;
+  const long long N = g.N;
+  const long long tiles = (N + 15) / 16;
+  const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const long long nwaves = (long long)gridDim.x * 4;
+  for (long long T = wave; T < 3 * tiles; T += nwaves) {
+    const int d = (int)(T / tiles);
+    const long long id = (T % tiles) * 16 + j;
+    const bool ok = id < N;
+    const long long idc = ok ? id : N - 1;
+    const int pos[3] = {(int)(idc % g.n[0]), (int)((idc / g.n[0]) % g.n[1]), (int)(idc / ((long long)g.n[0] * g.n[1]))};
+    v8bf x;
+    for (int tt = 0; tt < 2; ++tt) {
+      const int t = 2 * gg + tt;
+      const long long nid = idc + (long long)(wrapn(pos[d] + t - 3, g.n[d]) - pos[d]) * g.s[d];
+      x[4 * tt + 0] = (__bf16)feat[nid];
+      x[4 * tt + 1] = (__bf16)feat[N + nid];
+      x[4 * tt + 2] = (__bf16)feat[(2 + 2 * d) * N + nid];
+      x[4 * tt + 3] = (__bf16)feat[(3 + 2 * d) * N + nid];
+    }
+    Fwd F;
+    mlp_forward(R, x, F);
+    if (ok && gg == 0) flags[d * N + id] = sigmoidf(F.z) >= tau ? 1 : 0;
+  }
+}
+
+hipError_t launch_mlp_flags(const Geo& g, const float* feat, const float* P, float tau, uint8_t* flags,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_flags, dim3(2048), dim3(256), 0, st, g, feat, P, tau, flags);
+  return hipGetLastError();
+}
+
+// Probabilities of stored samples X [S][32] (bf16 bits), in order.
+__global__ __launch_bounds__(256) void k_mlp_prob(const uint16_t* __restrict__ X, long long S,
+                                                  const float* __restrict__ P, float* __restrict__ prob) {
+  MlpRegs R;
+  load_mlp(P, R);
+  const int l = threadIdx.x & 63, j = l & 15, gg = l >> 4;
+  const long long tiles = (S + 15) / 16;
+  for (long long T = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); T < tiles; T += (long long)gridDim.x * 4) {
+    const long long s = T * 16 + j;
+    const long long sc = s < S ? s : S - 1;
+    v8bf x;
+    __builtin_memcpy(&x, X + sc * 32 + 8 * gg, 16);
+    Fwd F;
+    mlp_forward(R, x, F);
+    if (s < S && gg == 0) prob[s] = sigmoidf(F.z);
+  }
+}
+
+hipError_t launch_mlp_prob(const uint16_t* X, long long S, const float* P, float* prob, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_prob, dim3(256), dim3(256), 0, st, X, S, P, prob);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Training: gradient of the weighted binary cross-entropy over a batch
+//   L = -sum_i w_i [y_i log p_i + (1 - y_i) log(1 - p_i)] / Wsum
+// Each wave takes 16-sample tiles; weight gradients use 16x16x16 MFMAs with
+// the samples as the reduction dimension, after a transpose through LDS.
+// Every workgroup writes its partial gradient; k_mlp_reduce sums them in a
+// fixed order (deterministic).
+// ---------------------------------------------------------------------------
+constexpr int GT = 256;
+
+__global__ __launch_bounds__(GT) void k_mlp_grad(const uint16_t* __restrict__ X, const uint8_t* __restrict__ y,
+                                                 const float* __restrict__ w, const int* __restrict__ idx,
+                                                 long long nb, float Wsum, const float* __restrict__ P,
+                                                 float* __restrict__ partial) {
+  __shared__ __bf16 lds_h[4][32][17];   // per wave: relu(a1) [unit][sample]
+  __shared__ __bf16 lds_d[4][32][17];   // per wave: back-propagated pre-activation gradient [unit][sample]
+  __shared__ __bf16 lds_x[4][32][17];   // per wave: inputs [input][sample]
+  __shared__ float red[MLP_NPARAM + 1];
+  MlpRegs R;
+  load_mlp(P, R);
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, j = l & 15, gg = l >> 4;
+  for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += GT) red[k] = 0.f;
+  // W2 as the A operand of dh1 = W2 da2 (rows = input unit 16m + l%16, k-slots relabelled)
+  v8bf A2b[2];
+  for (int m = 0; m < 2; ++m)
+    for (int q = 0; q < 8; ++q) A2b[m][q] = (__bf16)P[MLP_W2 + (16 * m + j) * MLP_H + unit_of(gg, q)];
+  v4f gW1[2][2], gW2[2][2];   // [tile of output unit][tile of input] C layout: col = input, rows = output unit
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      gW1[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+      gW2[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+    }
+  float gb1[2][4] = {}, gb2[2][4] = {}, gw3[2][4] = {};
+  float gb3 = 0.f, loss = 0.f;
+  __syncthreads();
+  // Every wave runs the same number of rounds (barriers below are block-wide);
+  // a wave past the last tile works on sample 0 with zero weight.
+  const long long tiles = (nb + 15) / 16;
+  for (long long T0 = (long long)blockIdx.x * 4; T0 < tiles; T0 += (long long)gridDim.x * 4) {
+    const long long T = T0 + wv;
+    const long long s = T * 16 + j;
+    const bool ok = T < tiles && s < nb;
+    const long long si = idx[ok ? s : 0];
+    v8bf x;
+    __builtin_memcpy(&x, X + si * 32 + 8 * gg, 16);
+    Fwd F;
+    mlp_forward(R, x, F);
+    const float p = sigmoidf(F.z);
+    const float ys = (float)y[si];
+    const float ws = ok ? w[si] : 0.f;
+    const float dz = ws * (p - ys) / Wsum;
+    if (gg == 0) loss += -ws * (ys * __logf(p + 1e-12f) + (1.f - ys) * __logf(1.f - p + 1e-12f)) / Wsum;
+    // output layer and da2
+    v4f da2[2];
+    for (int m = 0; m < 2; ++m)
+      for (int r = 0; r < 4; ++r) {
+        const float h2 = fmaxf(F.a2[m][r], 0.f);
+        gw3[m][r] += dz * h2;
+        da2[m][r] = F.a2[m][r] > 0.f ? dz * R.w3[m][r] : 0.f;
+        gb2[m][r] += da2[m][r];
+      }
+    if (gg == 0) gb3 += dz;
+    // dh1 = W2 da2 (B operand: da2 relabelled like h1)
+    v8bf db;
+    for (int q = 0; q < 8; ++q) db[q] = (__bf16)(q < 4 ? da2[0][q] : da2[1][q - 4]);
+    v4f da1[2];
+    const v4f zero = {0.f, 0.f, 0.f, 0.f};
+    for (int m = 0; m < 2; ++m) {
+      const v4f dh = mfma32(A2b[m], db, zero);
+      for (int r = 0; r < 4; ++r) {
+        da1[m][r] = F.a1[m][r] > 0.f ? dh[r] : 0.f;
+        gb1[m][r] += da1[m][r];
+      }
+    }
+    // stage [unit][sample] tiles for the weight gradients
+    for (int m = 0; m < 2; ++m)
+      for (int r = 0; r < 4; ++r) {
+        const int u = 16 * m + 4 * gg + r;
+        lds_h[wv][u][j] = (__bf16)fmaxf(F.a1[m][r], 0.f);
+        lds_d[wv][u][j] = (__bf16)da2[m][r];
+      }
+    for (int q = 0; q < 8; ++q) lds_x[wv][8 * gg + q][j] = x[q];
+    __syncthreads();
+    // gW2[o][i] += sum_s da2[o][s] h1[i][s];  gW1[o][i] += sum_s da1[o][s] x[i][s]
+    for (int mo = 0; mo < 2; ++mo)
+      for (int mi = 0; mi < 2; ++mi) {
+        v4bf a, b;
+        for (int q = 0; q < 4; ++q) {
+          a[q] = lds_d[wv][16 * mo + j][4 * gg + q];
+          b[q] = lds_h[wv][16 * mi + j][4 * gg + q];
+        }
+        gW2[mo][mi] = mfma16(a, b, gW2[mo][mi]);
+      }
+    __syncthreads();
+    for (int m = 0; m < 2; ++m)
+      for (int r = 0; r < 4; ++r) lds_d[wv][16 * m + 4 * gg + r][j] = (__bf16)da1[m][r];
+    __syncthreads();
+    for (int mo = 0; mo < 2; ++mo)
+      for (int mi = 0; mi < 2; ++mi) {
+        v4bf a, b;
+        for (int q = 0; q < 4; ++q) {
+          a[q] = lds_d[wv][16 * mo + j][4 * gg + q];
+          b[q] = lds_x[wv][16 * mi + j][4 * gg + q];
+        }
+        gW1[mo][mi] = mfma16(a, b, gW1[mo][mi]);
+      }
+    __syncthreads();
+  }
+  // Reduce the lanes' partial sums into red[] in a fixed order: wave by wave.
+  for (int wave = 0; wave < 4; ++wave) {
+    if (wv == wave) {
+      for (int mo = 0; mo < 2; ++mo)
+        for (int mi = 0; mi < 2; ++mi)
+          for (int r = 0; r < 4; ++r) {
+            const int o = 16 * mo + 4 * gg + r, in = 16 * mi + j;
+            red[MLP_W1 + in * MLP_H + o] += gW1[mo][mi][r];
+            red[MLP_W2 + in * MLP_H + o] += gW2[mo][mi][r];
+          }
+      // bias and output-layer terms: sum over the 16 samples of each lane group, lane by lane
+      for (int ln = 0; ln < 64; ++ln) {
+        if (l == ln) {
+          for (int m = 0; m < 2; ++m)
+            for (int r = 0; r < 4; ++r) {
+              const int u = 16 * m + 4 * gg + r;
+              red[MLP_B1 + u] += gb1[m][r];
+              red[MLP_B2 + u] += gb2[m][r];
+              red[MLP_W3 + u] += gw3[m][r];
+            }
+          if (gg == 0) {
+            red[MLP_B3] += gb3;
+            red[MLP_NPARAM] += loss;
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += GT) partial[(long long)blockIdx.x * (MLP_NPARAM + 1) + k] = red[k];
+}
+
+// Sum the workgroups' partial gradients (fixed order) into grad[NPARAM + 1]
+// (last entry: loss), then, if lr > 0, one Adam step on the FP32 master
+// parameters (moments m, v; step count t).
+__global__ __launch_bounds__(256) void k_mlp_reduce_adam(const float* __restrict__ partial, int nblocks,
+                                                         float* __restrict__ grad, float* __restrict__ P,
+                                                         float* __restrict__ m, float* __restrict__ v, float lr,
+                                                         int t) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += 256) {
+    float s = 0.f;
+    for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * (MLP_NPARAM + 1) + k];
+    grad[k] = s;
+    if (lr > 0.f && k < MLP_NPARAM) {
+      m[k] = b1 * m[k] + (1.f - b1) * s;
+      v[k] = b2 * v[k] + (1.f - b2) * s * s;
+      const float mh = m[k] / (1.f - powf(b1, (float)t));
+      const float vh = v[k] / (1.f - powf(b2, (float)t));
+      P[k] -= lr * mh / (sqrtf(vh) + eps);
+    }
+  }
+}
+
+hipError_t launch_mlp_grad(const uint16_t* X, const uint8_t* y, const float* w, const int* idx, long long nb,
+                           float Wsum, const float* P, float* partial, int nblocks, float* grad, float* Pmut,
+                           float* m, float* v, float lr, int t, hipStream_t st) {
+  hipLaunchKernelGGL(k_mlp_grad, dim3(nblocks), dim3(GT), 0, st, X, y, w, idx, nb, Wsum, P, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_mlp_reduce_adam, dim3(1), dim3(256), 0, st, partial, nblocks, grad, Pmut, m, v, lr, t);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sample collection from the current flags: interface (d, node) is taken if
+// a counter-based hash of (seed, d, node) falls below the keep probability of
+// its class.  Two passes (count per workgroup, then write at the scanned
+// offset) keep the sample order deterministic.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t hash3(uint64_t seed, uint32_t d, uint64_t id) {
+  // SplitMix64 finaliser of a combined counter
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (id * 4 + d + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return (uint32_t)(z >> 32);
+}
+
+__device__ __forceinline__ bool keep_interface(uint64_t seed, int d, long long id, uint8_t flag, uint32_t thr_pos,
+                                               uint32_t thr_neg) {
+  const uint32_t h = hash3(seed, (uint32_t)d, (uint64_t)id);
+  return flag ? h < thr_pos : h < thr_neg;
+}
+
+constexpr int CT = 256;
+
+__global__ __launch_bounds__(CT) void k_collect_count(const Geo g, const uint8_t* __restrict__ flags, uint64_t seed,
+                                                      uint32_t thr_pos, uint32_t thr_neg,
+                                                      unsigned long long* __restrict__ counts) {
+  __shared__ unsigned long long sh[CT];
+  const long long total = 3 * g.N;
+  const long long per = (total + gridDim.x - 1) / gridDim.x;
+  const long long a = (long long)blockIdx.x * per, b = min(total, a + per);
+  unsigned long long c = 0;
+  for (long long k = a + threadIdx.x; k < b; k += CT) {
+    const int d = (int)(k / g.N);
+    const long long id = k % g.N;
+    c += keep_interface(seed, d, id, flags[k], thr_pos, thr_neg) ? 1 : 0;
+  }
+  sh[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long s = 0;
+    for (int i = 0; i < CT; ++i) s += sh[i];
+    counts[blockIdx.x] = s;
+  }
+}
+
+// Writes the kept samples of this workgroup's range, in index order, from
+// offset offs[block] (offsets beyond cap are dropped).
+__global__ __launch_bounds__(CT) void k_collect_write(const Geo g, const uint8_t* __restrict__ flags,
+                                                      const float* __restrict__ feat, uint64_t seed, uint32_t thr_pos,
+                                                      uint32_t thr_neg, const unsigned long long* __restrict__ offs,
+                                                      long long cap, uint16_t* __restrict__ X,
+                                                      uint8_t* __restrict__ y, float* __restrict__ w) {
+  __shared__ unsigned long long base;
+  __shared__ int sc[CT];
+  const long long total = 3 * g.N;
+  const long long per = (total + gridDim.x - 1) / gridDim.x;
+  const long long a = (long long)blockIdx.x * per, b = min(total, a + per);
+  if (threadIdx.x == 0) base = offs[blockIdx.x];
+  __syncthreads();
+  const long long N = g.N;
+  for (long long k0 = a; k0 < b; k0 += CT) {
+    const long long k = k0 + threadIdx.x;
+    const bool in = k < b;
+    const int d = in ? (int)(k / N) : 0;
+    const long long id = in ? k % N : 0;
+    const bool kp = in && keep_interface(seed, d, id, flags[in ? k : 0], thr_pos, thr_neg);
+    sc[threadIdx.x] = kp ? 1 : 0;
+    __syncthreads();
+    // exclusive prefix of this round (serial in one thread: 256 entries)
+    if (threadIdx.x == 0) {
+      int s = 0;
+      for (int i = 0; i < CT; ++i) {
+        const int c = sc[i];
+        sc[i] = s;
+        s += c;
+      }
+    }
+    __syncthreads();
+    if (kp) {
+      const long long o = (long long)base + sc[threadIdx.x];
+      if (o < cap) {
+        const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
+        uint16_t xs[32];
+        for (int t = 0; t < 8; ++t) {
+          const long long nid = id + (long long)(wrapn(pos[d] + t - 3, g.n[d]) - pos[d]) * g.s[d];
+          const float f[4] = {feat[nid], feat[N + nid], feat[(2 + 2 * d) * N + nid], feat[(3 + 2 * d) * N + nid]};
+          for (int q = 0; q < 4; ++q) {
+            const __bf16 bv = (__bf16)f[q];
+            __builtin_memcpy(&xs[4 * t + q], &bv, 2);
+          }
+        }
+        for (int q = 0; q < 32; ++q) X[o * 32 + q] = xs[q];
+        y[o] = flags[k];
+        w[o] = 1.f;
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x == CT - 1) base += sc[CT - 1] + (kp ? 1 : 0);
+    __syncthreads();
+  }
+}
+
+hipError_t launch_collect_count(const Geo& g, const uint8_t* flags, uint64_t seed, uint32_t thr_pos, uint32_t thr_neg,
+                                unsigned long long* counts, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_collect_count, dim3(nblocks), dim3(CT), 0, st, g, flags, seed, thr_pos, thr_neg, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_collect_write(const Geo& g, const uint8_t* flags, const float* feat, uint64_t seed, uint32_t thr_pos,
+                                uint32_t thr_neg, const unsigned long long* offs, long long cap, uint16_t* X,
+                                uint8_t* y, float* w, int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_collect_write, dim3(nblocks), dim3(CT), 0, st, g, flags, feat, seed, thr_pos, thr_neg, offs,
+                     cap, X, y, w);
+  return hipGetLastError();
+}
+
+// Class counts of a flag field: out[0] = interfaces flagged 1, out[1] = 0 (per workgroup partials).
+__global__ __launch_bounds__(CT) void k_flag_stats(const uint8_t* __restrict__ fa, const uint8_t* __restrict__ fb,
+                                                   long long total, unsigned long long* __restrict__ out) {
+  __shared__ unsigned long long sh[4][CT];
+  unsigned long long c[4] = {0, 0, 0, 0};  // a=1, a=0&b=1, a=1&b=0, a!=b
+  for (long long k = (long long)blockIdx.x * CT + threadIdx.x; k < total; k += (long long)gridDim.x * CT) {
+    const uint8_t x = fa[k];
+    c[0] += x ? 1 : 0;
+    if (fb) {
+      const uint8_t z = fb[k];
+      c[1] += (!x && z) ? 1 : 0;
+      c[2] += (x && !z) ? 1 : 0;
+      c[3] += (x != z) ? 1 : 0;
+    }
+  }
+  for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = c[q];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    unsigned long long s = 0;
+    for (int i = 0; i < CT; ++i) s += sh[threadIdx.x][i];
+    out[blockIdx.x * 4 + threadIdx.x] = s;
+  }
+}
+
+hipError_t launch_flag_stats(const uint8_t* fa, const uint8_t* fb, long long total, unsigned long long* out,
+                             int nblocks, hipStream_t st) {
+  hipLaunchKernelGGL(k_flag_stats, dim3(nblocks), dim3(CT), 0, st, fa, fb, total, out);
+  return hipGetLastError();
+}
+
+// a |= b elementwise (learned flags widened by the plain sensor's).
+__global__ __launch_bounds__(256) void k_flags_or(uint8_t* __restrict__ a, const uint8_t* __restrict__ b,
+                                                  long long n) {
+  for (long long k = (long long)blockIdx.x * 256 + threadIdx.x; k < n; k += (long long)gridDim.x * 256) a[k] |= b[k];
+}
+
+hipError_t launch_flags_or(uint8_t* a, const uint8_t* b, long long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_flags_or, dim3(2048), dim3(256), 0, st, a, b, n);
+  return hipGetLastError();
+}
+
+}  // namespace ocfd

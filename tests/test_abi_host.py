@@ -77,3 +77,26 @@ def test_workspace_and_order_errors(ocfd):
         assert L.ocfd_bind_workspace(h, None, need) == -1
     finally:
         L.ocfd_destroy(h)
+
+
+def test_sensor_host_checks(ocfd):
+    from oracle import mlp
+    L = ocfd.lib()
+    assert L.ocfd_sensor_nparams() == mlp.NPARAM == 2145
+    assert L.ocfd_sensor_sample_bytes(0) == 0
+    assert L.ocfd_sensor_sample_bytes(1000) == 1000 * 77
+    p = _params(ocfd)
+    h = ctypes.c_void_p()
+    assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == 0
+    try:
+        assert L.ocfd_sensor_set_threshold(h, ctypes.c_double(1.5)) == -1
+        assert L.ocfd_sensor_set_threshold(h, ctypes.c_double(0.25)) == 0
+        assert L.ocfd_sensor_bind_samples(h, ctypes.c_void_p(4096), 16 * 77 - 1) == -2
+        assert L.ocfd_sensor_bind_samples(h, ctypes.c_void_p(4097), 10 ** 6) == -1
+        out = (ctypes.c_double * 6)()
+        assert L.ocfd_sensor_audit(h, out) == 0 and list(out) == [0.0] * 6
+    finally:
+        L.ocfd_destroy(h)
+    bad = _params(ocfd)
+    bad.sensor = 5
+    assert L.ocfd_create(ctypes.byref(bad), None, ctypes.byref(h)) == -1

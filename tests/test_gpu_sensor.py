@@ -1,0 +1,190 @@
+"""Sensors on the GPU: plain pressure-sensor flags, the learned sensor's
+matrix-core perceptron (loss, gradient and flags against the CPU oracle on
+identical bf16 operands), and the learned hybrid end to end: samples from the
+plain sensor, training, calibration for full recall, runs with audits, and
+what the network gains over the method without a sensor."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pk(torch_cuda):
+    import paper_2209_15333_amd as pk
+    pk.lib()
+    return pk
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def _solver(pk, torch, case):
+    s = pk.Solver(pk.params_from(case))
+    s.set_grid(_dev(torch, case.xyz))
+    s.set_state(_dev(torch, case.U0))
+    return s
+
+
+def _bind_samples(pk, torch, s, cap):
+    buf = torch.empty(pk.ocfd_sensor_sample_bytes(cap), dtype=torch.uint8, device="cuda")
+    pk.ocfd_sensor_bind_samples(s.h, buf)
+    return buf
+
+
+def _hit(n=40, steps=0, seed=22093):
+    case = workloads.isotropic_turbulence(n, seed=seed)
+    case.scheme, case.lowdiss = "hybrid", "c8"
+    return case
+
+
+def _bf16_bits(x):
+    f = mlp.bf16(x).astype(np.float32)
+    return (f.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def test_mlp_loss_and_gradient_match_oracle(pk, torch_cuda):
+    case = _hit(16)
+    s = _solver(pk, torch_cuda, case)
+    _bind_samples(pk, torch_cuda, s, 4096)
+    rng = np.random.default_rng(0)
+    theta = mlp.init_params(3)
+    theta[mlp.NPARAM - 33:mlp.NPARAM - 1] *= 10.0
+    pk.ocfd_sensor_set_params(s.h, theta)
+    theta32 = theta.astype(np.float32).astype(np.float64)
+    n = 1000   # not a multiple of 16: ragged last tile
+    X = rng.normal(size=(n, 32)) * 0.5
+    Xb = _bf16_bits(X)
+    y = (rng.random(n) < 0.4).astype(np.uint8)
+    w = rng.uniform(0.5, 2.0, n).astype(np.float32)
+    g_gpu, L_gpu = pk.ocfd_sensor_grad(s.h, _dev(torch_cuda, Xb.view(np.int16)), _dev(torch_cuda, y),
+                                       _dev(torch_cuda, w))
+    L_ref, g_ref = mlp.loss_and_grad(theta32, mlp.bf16(X), y, w.astype(np.float64), round_bf16=True)
+    print("loss", L_gpu, L_ref, "grad rel", np.linalg.norm(g_gpu - g_ref) / np.linalg.norm(g_ref), flush=True)
+    assert L_gpu == pytest.approx(L_ref, rel=1e-5)
+    assert np.linalg.norm(g_gpu - g_ref) <= 2e-3 * np.linalg.norm(g_ref)
+    # every parameter block, not only the largest ones
+    o = 0
+    for name, shape in mlp.SIZES:
+        k = int(np.prod(shape))
+        blk = slice(o, o + k)
+        assert np.linalg.norm(g_gpu[blk] - g_ref[blk]) <= 5e-3 * np.linalg.norm(g_ref[blk]) + 1e-9, name
+        o += k
+
+
+def test_plain_flags_match_oracle(pk, torch_cuda, orc):
+    case = _hit(32)
+    s = _solver(pk, torch_cuda, case)
+    P = orc.params_from_case(case)
+    theta, ref = orc.sensor(P, case.U0)
+    fl = torch_cuda.zeros((3,) + case.U0.shape[1:], dtype=torch_cuda.uint8, device="cuda")
+    pk.ocfd_sensor_flags(s.h, _dev(torch_cuda, case.U0), pk.OCFD_SENSOR_PLAIN, fl)
+    got = fl.cpu().numpy()
+    diff = got != ref
+    print("plain flags: WENO fraction", ref.mean(), "disagreements", diff.sum(), flush=True)
+    assert 0.001 < ref.mean() < 0.999
+    assert np.abs(theta - case.theta1).min() > 1e-12 or diff.sum() <= 8
+    assert diff.sum() == 0 or np.abs(theta - case.theta1).min() <= 1e-12
+
+
+def test_learned_flags_match_oracle(pk, torch_cuda, orc):
+    case = _hit(24)
+    s = _solver(pk, torch_cuda, case)
+    theta = mlp.init_params(5)
+    theta[mlp.NPARAM - 33:mlp.NPARAM - 1] *= 20.0
+    pk.ocfd_sensor_set_params(s.h, theta)
+    tau = 0.5
+    pk.ocfd_sensor_set_threshold(s.h, tau)
+    fl = torch_cuda.zeros((3,) + case.U0.shape[1:], dtype=torch_cuda.uint8, device="cuda")
+    pk.ocfd_sensor_flags(s.h, _dev(torch_cuda, case.U0), pk.OCFD_SENSOR_LEARNED, fl)
+    got = fl.cpu().numpy().reshape(3, -1)
+    P = orc.params_from_case(case)
+    met = orc.metrics(P, case.xyz)
+    F = mlp.node_features(case.gamma, case.h, met, case.U0).astype(np.float32).astype(np.float64)
+    nodes = np.arange(case.N)
+    theta32 = theta.astype(np.float32).astype(np.float64)
+    for d in range(3):
+        X = mlp.interface_inputs(F, d, nodes)
+        p, _ = mlp.forward(theta32, X, round_bf16=True)
+        ref = (p >= tau).astype(np.uint8)
+        bad = got[d] != ref
+        print(f"learned flags dir {d}: WENO fraction {ref.mean():.3f}, disagreements {bad.sum()}", flush=True)
+        assert 0.01 < ref.mean() < 0.99
+        # disagreements only where the probability sits at the threshold
+        assert bad.sum() <= 1e-4 * case.N + 2
+        assert np.all(np.abs(p[bad] - tau) < 1e-3)
+
+
+def test_learned_hybrid_end_to_end(pk, torch_cuda):
+    """Samples from the plain sensor on developing isotropic turbulence, GPU
+    training (loss falls), calibration (every held-out WENO interface kept),
+    then runs with the learned sensor and audits against the plain sensor.
+    Gain over the method without a sensor: far fewer WENO interfaces, less
+    numerical dissipation than WENO7 everywhere, same solution as the plain
+    hybrid to a small tolerance."""
+    torch = torch_cuda
+    base = _hit(40)
+    s = _solver(pk, torch, base)
+    _bind_samples(pk, torch, s, 400_000)
+    total = 0
+    for snap in range(6):
+        s.advance(6, base.dt)
+        total = pk.ocfd_sensor_collect(s.h, 1000 + snap, 1.0, 0.15)
+    print("samples", total, flush=True)
+    assert total > 20_000
+    pk.ocfd_sensor_set_params(s.h, mlp.init_params(11))
+    stats = pk.ocfd_sensor_train(s.h, 15, 1024, 3e-3, 7, 0.2)
+    print("training loss first/last epoch", stats, flush=True)
+    assert stats[1] < 0.7 * stats[0]
+    cal = pk.ocfd_sensor_calibrate(s.h, 0.2, 0.5)
+    print("calibration tau, recall, fpr, held-out", cal, flush=True)
+    assert cal[1] == 1.0
+    assert cal[2] < 0.9
+    params = pk.ocfd_sensor_get_params(s.h)
+    tau = cal[0]
+    U = s.state()
+
+    def run(**kw):
+        c = _hit(40)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        r = pk.Solver(pk.params_from(c))
+        r.set_grid(_dev(torch, c.xyz))
+        r.set_state(U)
+        if c.scheme == "hybrid" and c.sensor == "learned":
+            pk.ocfd_sensor_set_params(r.h, params)
+            pk.ocfd_sensor_set_threshold(r.h, tau)
+        r.advance(30, c.dt)
+        out = r.state().cpu().numpy()
+        return out, r
+
+    plain, _ = run()
+    learned, rl = run(sensor="learned", sensor_every=1, audit_every=3)
+    weno, _ = run(scheme="weno7")
+    audit = pk.ocfd_sensor_audit(rl.h)
+    print("audit: runs, compared, plain WENO, learned WENO, missed, mismatches", audit, flush=True)
+    assert audit[0] == 10
+    frac_learned = audit[3] / audit[1]
+    frac_plain = audit[2] / audit[1]
+    assert frac_learned < 0.9                      # far fewer than WENO everywhere
+    assert audit[4] <= 0.01 * audit[2]             # misses are rare (and fall back to WENO)
+
+    def ke(u):
+        return float((0.5 * (u[1] ** 2 + u[2] ** 2 + u[3] ** 2) / u[0]).mean())
+    rel = np.linalg.norm(learned - plain) / np.linalg.norm(plain)
+    print(f"WENO fraction plain {frac_plain:.3f} learned {frac_learned:.3f}; KE weno7 {ke(weno):.6f} "
+          f"learned {ke(learned):.6f} plain {ke(plain):.6f}; |learned - plain| {rel:.2e}", flush=True)
+    assert ke(weno) < ke(learned)                  # WENO7 everywhere dissipates more
+    assert rel < 1e-3

@@ -1,0 +1,68 @@
+"""Pins of the learned-sensor oracle: the FP64 backward pass against central
+finite differences of the loss, the bfloat16 rounding against its definition,
+and the node features against closed forms."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import mlp
+
+
+def test_backward_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    theta = mlp.init_params(1)
+    theta[-34:-1] *= 10.0       # a non-trivial output layer
+    X = rng.normal(size=(64, 32))
+    y = (rng.random(64) < 0.3).astype(float)
+    w = rng.uniform(0.5, 2.0, 64)
+    L, g = mlp.loss_and_grad(theta, X, y, w)
+    h = 1e-6
+    idx = rng.choice(mlp.NPARAM, 200, replace=False)
+    for i in idx:
+        tp = theta.copy(); tp[i] += h
+        tm = theta.copy(); tm[i] -= h
+        fd = (mlp.loss_and_grad(tp, X, y, w)[0] - mlp.loss_and_grad(tm, X, y, w)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 * max(1.0, abs(g).max()), i
+
+
+def test_bf16_rounding_definition():
+    # values exactly halfway between two bfloat16 numbers round to the even one
+    one = np.float32(1.0)
+    ulp = np.float32(2.0 ** -7)
+    assert mlp.bf16(one + ulp / 2) == 1.0
+    assert mlp.bf16(one + 3 * ulp / 2) == 1.0 + 2 * ulp
+    x = np.random.default_rng(1).normal(size=1000).astype(np.float32)
+    r = mlp.bf16(x)
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8 + 1e-45)   # half an ulp of 7 stored bits
+    assert np.all((r.astype(np.float32).view(np.uint32) & 0xFFFF) == 0)
+
+
+def test_features_closed_forms():
+    """Uniform flow: zero divergence and vorticity, zero jumps.  A linear
+    shear u = a y: |curl| = a, div = 0.  A density step along x: jump
+    (r-1)/(r+1) at the two nodes beside it."""
+    case = workloads.uniform_flow((12, 10, 8), amplitude_frac=0.0)
+    import oracle
+    P = oracle.params_from_case(case)
+    met = oracle.metrics(P, case.xyz)
+    F = mlp.node_features(case.gamma, case.h, met, case.U0)
+    assert np.abs(F).max() < 1e-12
+    # shear: u = a sin(y) has curl_z = -a cos(y); second-order central difference
+    x, y, z = case.xyz
+    a = 0.3
+    rho = np.ones_like(x)
+    p = np.full_like(x, 1.0 / (1.4 * 0.25))
+    U = workloads.conserved(1.4, rho, a * np.sin(y), 0 * x, 0 * x, p)
+    F = mlp.node_features(1.4, case.h, met, U)
+    hy = case.h[1]
+    curl = a * np.cos(y) * np.sin(hy) / hy
+    c = np.sqrt(1.4 * p / rho)
+    assert np.abs(F[0]).max() < 1e-14
+    assert np.allclose(F[1], np.cbrt(met[9]) * np.abs(curl) / c, rtol=1e-12, atol=1e-15)
+    r = 3.0
+    rho = np.where(np.arange(12)[None, None, :] >= 6, r, 1.0) * np.ones_like(x)
+    U = workloads.conserved(1.4, rho, 0 * x, 0 * x, 0 * x, p)
+    F = mlp.node_features(1.4, case.h, met, U)
+    assert F[3][0, 0, 5] == pytest.approx((r - 1) / (r + 1))
+    assert F[3][0, 0, 6] == pytest.approx((r - 1) / (r + 1))
+    assert F[3][0, 0, 3] == 0.0 and np.all(F[5] == 0.0) and np.all(F[7] == 0.0)

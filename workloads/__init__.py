@@ -56,6 +56,9 @@ class Case:
     three_way: bool = False
     inflow: Optional[np.ndarray] = None
     precision: str = "fp64"              # "fp64" | "mixed" (GPU only)
+    sensor: str = "plain"                # hybrid: "plain" (pressure sensor) | "learned" (GPU only)
+    sensor_every: int = 1
+    audit_every: int = 0
 
     @property
     def N(self) -> int:
