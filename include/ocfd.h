@@ -58,6 +58,19 @@ extern "C" {
 #define OCFD_SENSOR_PLAIN 0    /* modified Jameson pressure sensor, eq 42-43 */
 #define OCFD_SENSOR_LEARNED 1  /* perceptron on local flow features (ocfd_sensor_* below) */
 
+/* Boundary kinds of the faces of a non-periodic direction (Sec. 2.4 names
+   the kinds used by the compression-ramp case).  Applied after every
+   Runge-Kutta stage, face by face in the order xi-, xi+, eta-, eta+, zeta-,
+   zeta+; a face node's dU/dt is zero, its value is set by its face:
+   INFLOW: the conserved state given by ocfd_set_inflow;
+   EXTRAP: rho, velocity and p of the first interior node;
+   WALL:   no slip, T = Tw, p of the first interior node, rho = gamma Ma^2 p / Tw;
+   NONE:   the face keeps its value. */
+#define OCFD_BC_NONE 0
+#define OCFD_BC_INFLOW 1
+#define OCFD_BC_EXTRAP 2
+#define OCFD_BC_WALL 3
+
 /* Parts of the right-hand side for ocfd_dudt (bit mask). */
 #define OCFD_PART_XI 1
 #define OCFD_PART_ETA 2
@@ -86,11 +99,14 @@ extern "C" {
    (eq 17-18): gamma, Re, Ma, Pr and the Sutherland reference temperature. */
 typedef struct ocfd_params {
   int32_t nx, ny, nz;      /* nodes per direction; each >= 1 */
-  int32_t periodic[3];     /* 1: direction xi/eta/zeta is periodic (only periodic grids are built) */
+  int32_t periodic[3];     /* 1: direction xi/eta/zeta is periodic; 0: bounded (needs >= 8 nodes) */
+  int32_t bc[6];           /* OCFD_BC_* of the faces xi-, xi+, eta-, eta+, zeta-, zeta+ of bounded
+                              directions (ignored for periodic ones); at most one INFLOW face */
   double period[3];        /* coordinate d grows by period[d] across the seam of direction d */
   double h[3];             /* computational spacing of xi, eta, zeta (> 0) */
   double gamma, Re, Ma, Pr;
   double Tref, suth;       /* Sutherland law mu = T^1.5 (1 + S)/(T + S), S = suth/Tref (eq 15) */
+  double Tw;               /* wall temperature / reference temperature (WALL faces, > 0) */
   double theta1, theta2;   /* sensor thresholds of eq 43 */
   double weno_eps;         /* epsilon of the WENO nonlinear weights */
   int32_t viscous;         /* 0: Euler; 6: sixth-order central viscous terms */
@@ -106,19 +122,20 @@ typedef struct ocfd_params {
 typedef struct ocfd_solver ocfd_solver;
 
 /* Fill *p with defaults: gamma 1.4, Pr 0.72, Tref 288.15 K, suth 110.4 K,
-   theta 0.02/0.1, eps 1e-6, periodic, WENO7, viscous order 6. */
+   Tw 1, theta 0.02/0.1, eps 1e-6, periodic, WENO7, viscous order 6. */
 int ocfd_params_default(ocfd_params* p);
 
 /* Bytes of device workspace a solver with these parameters needs (0 if the
    parameters are invalid).  The workspace holds the metrics [10][N], three
    state buffers [5][N], the right-hand side [5][N], the primitive variables
-   [4][N] and the viscous fluxes [12][N], all FP64, plus small reduction
+   [4][N] and the viscous fluxes [12][N], all FP64, the sensor and
+   learned-sensor buffers, the inflow face [5][face] and small reduction
    buffers. */
 size_t ocfd_workspace_bytes(const ocfd_params* p);
 
 /* Create a solver.  stream: a hipStream_t (NULL: the default stream).  The
    solver copies *p.  Errors: BADARG (null pointer / invalid parameter),
-   BADSIZE, UNSUPPORTED (a non-periodic direction). */
+   UNSUPPORTED (the learned sensor on a grid with a bounded direction). */
 int ocfd_create(const ocfd_params* p, void* stream, ocfd_solver** out);
 
 /* Hand the solver caller-owned device memory of at least
@@ -132,6 +149,13 @@ int ocfd_bind_workspace(ocfd_solver* s, void* workspace_dev, size_t bytes);
    1/J = det d(x,y,z)/d(xi,eta,zeta) (eq 4).  Errors: BADARG, STATE (no
    workspace). */
 int ocfd_set_grid(ocfd_solver* s, const double* xyz_dev);
+
+/* Inflow state of the INFLOW face: conserved variables inflow_dev [5][face],
+   the face indexed by its two other node indices, the lower direction fastest
+   (xi- face: j + ny*k).  Copied into the workspace.  Errors: BADARG,
+   UNSUPPORTED (no INFLOW face), STATE (no workspace).  ocfd_advance returns
+   STATE while an INFLOW face has no state. */
+int ocfd_set_inflow(ocfd_solver* s, const double* inflow_dev);
 
 /* Copy metrics [10][N] = xi_x/J, xi_y/J, xi_z/J, eta_x/J, ..., zeta_z/J, 1/J
    in or out of the solver. */
@@ -151,12 +175,13 @@ int ocfd_set_step_state(ocfd_solver* s, const double* U_dev, const double* Un_de
 
 /* Advance n substeps of eq 45 with time step dt: substep k of a step sets
    U(k) = a_k U^n + b_k (U(k-1) + dt L(U(k-1))), (a,b) = (0,1), (3/4,1/4),
-   (1/3,2/3).  Errors: BADARG (n < 0, dt not finite), STATE. */
+   (1/3,2/3), then sets the faces of bounded directions (OCFD_BC_*).
+   Errors: BADARG (n < 0, dt not finite), STATE. */
 int ocfd_advance(ocfd_solver* s, int32_t n_substeps, double dt);
 
 /* dudt_dev [5][N] = L(U_dev) = dU/dt for the parts selected by the
-   OCFD_PART_* mask, without touching the solver's state.  U_dev must not
-   alias dudt_dev. */
+   OCFD_PART_* mask, without touching the solver's state (zero on the faces of
+   bounded directions).  U_dev must not alias dudt_dev. */
 int ocfd_dudt(ocfd_solver* s, const double* U_dev, double* dudt_dev, int32_t parts);
 
 /* Global sums and extrema of the current state (entries OCFD_RED_*), written

@@ -191,3 +191,10 @@ def reduce(P: Params, met: np.ndarray, U: np.ndarray, dt: float = 0.0) -> np.nda
     out = np.zeros(9)
     _check(lib().or_reduce(ctypes.byref(P), _dp(met), _dp(U), dt, _dp(out)), "reduce")
     return out
+
+
+def apply_bc(P: Params, U: np.ndarray, inflow: Optional[np.ndarray] = None) -> np.ndarray:
+    """The state U with the faces of bounded directions set (a new array)."""
+    U = np.array(U, dtype=np.float64, order="C", copy=True)
+    _check(lib().or_apply_bc(ctypes.byref(P), _dp(U), _dp(inflow)), "apply_bc")
+    return U

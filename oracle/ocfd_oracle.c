@@ -666,8 +666,12 @@ int or_apply_bc(const or_params* P, double* U, const double* inflow) {
         prim_t qi = primitive(P, U, N, ii);
         double o[5];
         if (kind == OR_BC_INFLOW && inflow) {
-          /* inflow holds conserved variables on the face, indexed like the face nodes */
-          for (int m = 0; m < 5; ++m) o[m] = inflow[(long)m * N + id];
+          /* inflow: conserved variables on this face, [5][face], the face
+             indexed by its two other node indices, lower direction fastest */
+          int e0 = d == 0 ? 1 : 0, e1 = d == 2 ? 1 : 2;
+          long nf = (long)dim_n(P, e0) * dim_n(P, e1);
+          long fi = c[e0] + (long)dim_n(P, e0) * c[e1];
+          for (int m = 0; m < 5; ++m) o[m] = inflow[(long)m * nf + fi];
         } else if (kind == OR_BC_WALL) {
           double rho = P->gamma * P->Ma * P->Ma * qi.p / P->Tw;
           conserved(P, rho, 0.0, 0.0, 0.0, qi.p, o);

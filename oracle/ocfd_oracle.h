@@ -87,7 +87,10 @@ int or_advance(const or_params* P, const double* met, double* U, double* Un, int
 /* out[0..4] = sum of U_m/J; out[5] = max CFL number; out[6] = min p;
    out[7] = min rho; out[8] = count of non-finite values. */
 int or_reduce(const or_params* P, const double* met, const double* U, double dt, double* out);
-/* Apply the boundary conditions of the non-periodic faces to U in place. */
+/* Apply the boundary conditions of the non-periodic faces to U in place, face
+   by face (xi-, xi+, eta-, eta+, zeta-, zeta+).  inflow: conserved variables
+   [5][face] of the inflow face, the face indexed by its two other node
+   indices with the lower direction fastest (NULL if there is none). */
 int or_apply_bc(const or_params* P, double* U, const double* inflow);
 
 #ifdef __cplusplus

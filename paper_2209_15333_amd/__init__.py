@@ -24,6 +24,7 @@ OCFD_SCHEME_WENO7, OCFD_SCHEME_HYBRID = 0, 1
 OCFD_LOWDISS_UD7, OCFD_LOWDISS_C8 = 0, 1
 OCFD_PREC_FP64, OCFD_PREC_MIXED = 0, 1
 OCFD_SENSOR_PLAIN, OCFD_SENSOR_LEARNED = 0, 1
+OCFD_BC_NONE, OCFD_BC_INFLOW, OCFD_BC_EXTRAP, OCFD_BC_WALL = 0, 1, 2, 3
 OCFD_PART_XI, OCFD_PART_ETA, OCFD_PART_ZETA, OCFD_PART_VISC, OCFD_PART_ALL = 1, 2, 4, 8, 15
 OCFD_RED_COUNT = 9
 OCFD_K_COUNT = 6
@@ -34,10 +35,11 @@ class ocfd_params(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
         ("periodic", ctypes.c_int32 * 3),
+        ("bc", ctypes.c_int32 * 6),
         ("period", ctypes.c_double * 3),
         ("h", ctypes.c_double * 3),
         ("gamma", ctypes.c_double), ("Re", ctypes.c_double), ("Ma", ctypes.c_double), ("Pr", ctypes.c_double),
-        ("Tref", ctypes.c_double), ("suth", ctypes.c_double),
+        ("Tref", ctypes.c_double), ("suth", ctypes.c_double), ("Tw", ctypes.c_double),
         ("theta1", ctypes.c_double), ("theta2", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
         ("viscous", ctypes.c_int32), ("scheme", ctypes.c_int32), ("lowdiss", ctypes.c_int32),
@@ -71,7 +73,7 @@ def lib() -> ctypes.CDLL:
         L.ocfd_create.argtypes = [pp, vp, ctypes.POINTER(vp)]
         L.ocfd_bind_workspace.argtypes = [vp, vp, ctypes.c_size_t]
         for name in ("ocfd_set_grid", "ocfd_set_metrics", "ocfd_get_metrics", "ocfd_set_state", "ocfd_get_state",
-                     "ocfd_set_flags"):
+                     "ocfd_set_flags", "ocfd_set_inflow"):
             getattr(L, name).argtypes = [vp, vp]
         L.ocfd_get_step_state.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
         L.ocfd_set_step_state.argtypes = [vp, vp, vp, ctypes.c_int32]
@@ -146,6 +148,10 @@ def ocfd_bind_workspace(h, ws: torch.Tensor):
 
 def ocfd_set_grid(h, xyz: torch.Tensor):
     _check(h, lib().ocfd_set_grid(h, _ptr(xyz)), "ocfd_set_grid")
+
+
+def ocfd_set_inflow(h, inflow: torch.Tensor):
+    _check(h, lib().ocfd_set_inflow(h, _ptr(inflow)), "ocfd_set_inflow")
 
 
 def ocfd_set_metrics(h, met: torch.Tensor):
@@ -288,15 +294,18 @@ def ocfd_sensor_audit(h):
 def params_from(case, **overrides) -> ocfd_params:
     """ocfd_params from any object carrying the run attributes (sizes, period,
     h, gamma, Re, Ma, Pr, Tref, suth, theta1, theta2, eps, viscous, scheme,
-    lowdiss, periodic)."""
+    lowdiss, periodic; optionally bc, Tw, precision, sensor)."""
     p = ocfd_params_default()
     p.nx, p.ny, p.nz = case.nx, case.ny, case.nz
     for d in range(3):
         p.periodic[d] = int(case.periodic[d])
         p.period[d] = float(case.period[d])
         p.h[d] = float(case.h[d])
+    for f in range(6):
+        p.bc[f] = int(getattr(case, "bc", (0,) * 6)[f])
     p.gamma, p.Re, p.Ma, p.Pr = case.gamma, case.Re, case.Ma, case.Pr
     p.Tref, p.suth = case.Tref, case.suth
+    p.Tw = float(getattr(case, "Tw", 1.0) or 1.0)
     p.theta1, p.theta2, p.weno_eps = case.theta1, case.theta2, case.eps
     p.viscous = int(case.viscous)
     p.scheme = OCFD_SCHEME_HYBRID if case.scheme == "hybrid" else OCFD_SCHEME_WENO7
@@ -349,6 +358,9 @@ class Solver:
 
     def set_state(self, U: torch.Tensor):
         ocfd_set_state(self.h, U)
+
+    def set_inflow(self, inflow: torch.Tensor):
+        ocfd_set_inflow(self.h, inflow)
 
     def state(self) -> torch.Tensor:
         U = self.field(5)

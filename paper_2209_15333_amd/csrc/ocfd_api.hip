@@ -41,6 +41,8 @@ struct ocfd_solver {
   float* grad = nullptr;          // [NPARAM + 1]
   float* gpartial = nullptr;      // [GRAD_BLOCKS][NPARAM + 1]
   unsigned long long* cnt = nullptr;   // [COUNT_BLOCKS * 4]
+  double* inflow = nullptr;       // [5][face] of the INFLOW face
+  bool have_inflow = false;
   bool mlp_ready = false;
   double tau = 0.5;
   int adam_t = 0;
@@ -112,8 +114,44 @@ bool valid_params(const ocfd_params* p, std::string* why) {
   if (p->sensor != OCFD_SENSOR_PLAIN && p->sensor != OCFD_SENSOR_LEARNED) { *why = "unknown sensor"; return false; }
   if (p->sensor_every < 0 || p->audit_every < 0) { *why = "sensor_every and audit_every must be >= 0"; return false; }
   if (p->reserved[0] != 0) { *why = "reserved fields must be zero"; return false; }
+  int ninflow = 0;
+  const int n[3] = {p->nx, p->ny, p->nz};
+  for (int d = 0; d < 3; ++d) {
+    if (p->periodic[d] != 0 && p->periodic[d] != 1) { *why = "periodic flags must be 0 or 1"; return false; }
+    if (p->periodic[d]) continue;
+    if (n[d] < 8) {
+      snprintf(buf, sizeof(buf), "bounded direction %d has %d nodes; at least 8 needed", d, n[d]);
+      *why = buf;
+      return false;
+    }
+    for (int side = 0; side < 2; ++side) {
+      const int k = p->bc[2 * d + side];
+      if (k < OCFD_BC_NONE || k > OCFD_BC_WALL) { *why = "unknown boundary kind"; return false; }
+      if (k == OCFD_BC_INFLOW) ++ninflow;
+      if (k == OCFD_BC_WALL && !(p->Tw > 0.0 && std::isfinite(p->Tw))) {
+        *why = "a wall face needs Tw > 0";
+        return false;
+      }
+    }
+  }
+  if (ninflow > 1) { *why = "at most one inflow face"; return false; }
   return true;
 }
+
+// Face index (0..5) of the INFLOW face, or -1.
+int inflow_face(const ocfd_params& p) {
+  for (int f = 0; f < 6; ++f)
+    if (!p.periodic[f / 2] && p.bc[f] == OCFD_BC_INFLOW) return f;
+  return -1;
+}
+
+// Nodes on a face normal to direction d.
+long long face_nodes(const ocfd_params& p, int d) {
+  const long long n[3] = {p.nx, p.ny, p.nz};
+  return n[d == 0 ? 1 : 0] * n[d == 2 ? 1 : 2];
+}
+
+bool all_periodic(const ocfd_params& p) { return p.periodic[0] && p.periodic[1] && p.periodic[2]; }
 
 void setup_geo_phys(ocfd_solver* s) {
   const ocfd_params& p = s->p;
@@ -170,7 +208,8 @@ size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver
   float* grad = (float*)take((MLP_NPARAM + 1) * sizeof(float));
   float* gpart = (float*)take((size_t)GRAD_BLOCKS * (MLP_NPARAM + 1) * sizeof(float));
   unsigned long long* cnt = (unsigned long long*)take((size_t)COUNT_BLOCKS * 4 * sizeof(unsigned long long));
-  (void)p;
+  const int fin = inflow_face(*p);
+  double* inflow = fin >= 0 ? take(5 * (size_t)face_nodes(*p, fin / 2) * sizeof(double)) : nullptr;
   if (s) {
     s->met = met;
     s->Ub[0] = u0;
@@ -191,6 +230,7 @@ size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver
     s->grad = grad;
     s->gpartial = gpart;
     s->cnt = cnt;
+    s->inflow = inflow;
   }
   return off;
 }
@@ -334,6 +374,19 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
   return OCFD_OK;
 }
 
+// Faces of the bounded directions of U, in the order xi-, xi+, eta-, eta+,
+// zeta-, zeta+ (a corner node takes the value of the last face through it).
+int apply_bc(ocfd_solver* s, double* U) {
+  for (int f = 0; f < 6; ++f) {
+    const int d = f / 2;
+    if (s->p.periodic[d] || s->p.bc[f] == OCFD_BC_NONE) continue;
+    Timed tm(s, OCFD_K_OTHER);
+    hipError_t e = launch_bc(s->g, s->ph, U, d, f % 2, s->p.bc[f], s->p.Tw, s->inflow, s->st);
+    if (e != hipSuccess) return hip_fail(s, e, "boundary kernel");
+  }
+  return OCFD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -347,6 +400,7 @@ int ocfd_params_default(ocfd_params* p) {
     p->period[d] = 1.0;
     p->h[d] = 1.0;
   }
+  p->Tw = 1.0;
   p->gamma = 1.4;
   p->Re = 1600.0;
   p->Ma = 0.1;
@@ -382,11 +436,10 @@ int ocfd_create(const ocfd_params* p, void* stream, ocfd_solver** out) {
     fprintf(stderr, "ocfd_create: %s\n", why.c_str());
     return OCFD_ERR_BADARG;
   }
-  for (int d = 0; d < 3; ++d)
-    if (!p->periodic[d]) {
-      fprintf(stderr, "ocfd_create: non-periodic directions are not built\n");
-      return OCFD_ERR_UNSUPPORTED;
-    }
+  if (p->sensor == OCFD_SENSOR_LEARNED && !all_periodic(*p)) {
+    fprintf(stderr, "ocfd_create: the learned sensor is built for periodic grids only\n");
+    return OCFD_ERR_UNSUPPORTED;
+  }
   ocfd_solver* s = new (std::nothrow) ocfd_solver();
   if (!s) return OCFD_ERR_BADARG;
   s->p = *p;
@@ -407,6 +460,20 @@ int ocfd_bind_workspace(ocfd_solver* s, void* ws, size_t bytes) {
   workspace_layout(&s->p, s->g.N, reduce_blocks(s->g), s, s->ws);
   s->have_grid = false;
   s->have_state = false;
+  s->have_inflow = false;
+  return OCFD_OK;
+}
+
+int ocfd_set_inflow(ocfd_solver* s, const double* inflow) {
+  int rc;
+  if (!ready(s, &rc)) return rc;
+  if (!inflow) return fail(s, OCFD_ERR_BADARG, "null inflow");
+  const int f = inflow_face(s->p);
+  if (f < 0) return fail(s, OCFD_ERR_UNSUPPORTED, "no inflow face");
+  hipError_t e = hipMemcpyAsync(s->inflow, inflow, 5 * face_nodes(s->p, f / 2) * sizeof(double),
+                                hipMemcpyDeviceToDevice, s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "inflow copy");
+  s->have_inflow = true;
   return OCFD_OK;
 }
 
@@ -491,6 +558,7 @@ int ocfd_advance(ocfd_solver* s, int32_t n, double dt) {
   if (!ready(s, &rc)) return rc;
   if (n < 0 || !std::isfinite(dt)) return fail(s, OCFD_ERR_BADARG, "bad substep count or dt");
   if (!s->have_grid || !s->have_state) return fail(s, OCFD_ERR_STATE, "grid and state must be set first");
+  if (inflow_face(s->p) >= 0 && !s->have_inflow) return fail(s, OCFD_ERR_STATE, "inflow face without inflow state");
   static const double A[3] = {0.0, 3.0 / 4.0, 1.0 / 3.0};
   static const double B[3] = {1.0, 1.0 / 4.0, 2.0 / 3.0};
   for (int i = 0; i < n; ++i) {
@@ -499,6 +567,10 @@ int ocfd_advance(ocfd_solver* s, int32_t n, double dt) {
     double* nxt = s->Ub[(k + 1) % 3];
     rc = run_rhs(s, cur, MODE_RK, nxt, s->Ub[0], A[k], B[k], dt, OCFD_PART_ALL, true);
     if (rc) return rc;
+    if (!all_periodic(s->p)) {
+      rc = apply_bc(s, nxt);
+      if (rc) return rc;
+    }
     s->stage = (k + 1) % 3;
     s->substep += 1;
   }
@@ -612,6 +684,7 @@ int ocfd_sensor_flags(ocfd_solver* s, const double* U, int32_t which, uint8_t* f
     e = launch_sensor(s->g, s->ph, U, s->theta, s->st);
     if (e == hipSuccess) e = launch_plain_flags(s->g, s->ph.theta1, s->theta, flags, s->st);
   } else if (which == OCFD_SENSOR_LEARNED) {
+    if (!all_periodic(s->p)) return fail(s, OCFD_ERR_UNSUPPORTED, "learned sensor on a bounded grid");
     if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "no network parameters set");
     e = launch_features(s->g, s->ph, U, s->met, s->feat, s->st);
     if (e == hipSuccess) e = launch_mlp_flags(s->g, s->feat, s->mlp, (float)s->tau, flags, s->st);
@@ -643,6 +716,7 @@ int ocfd_sensor_bind_samples(ocfd_solver* s, void* dev, size_t bytes) {
 }
 
 int ocfd_sensor_collect(ocfd_solver* s, uint64_t seed, double keep_weno, double keep_low, int64_t* total) {
+  if (s && !all_periodic(s->p)) return fail(s, OCFD_ERR_UNSUPPORTED, "learned sensor on a bounded grid");
   int rc;
   if (!ready(s, &rc)) return rc;
   if (!total) return fail(s, OCFD_ERR_BADARG, "null output");

@@ -74,6 +74,9 @@ hipError_t launch_sweep(int dir, int mode, const SweepArgs& a, hipStream_t st);
 hipError_t launch_prim(const Geo& g, const Phys& ph, const double* U, double* W, hipStream_t st);
 hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const double* met, double* Fv,
                             hipStream_t st);
+// One face (d, side) of a bounded direction set by boundary kind `kind`.
+hipError_t launch_bc(const Geo& g, const Phys& ph, double* U, int d, int side, int kind, double Tw,
+                     const double* inflow, hipStream_t st);
 hipError_t launch_sensor(const Geo& g, const Phys& ph, const double* U, double* theta, hipStream_t st);
 hipError_t launch_metric_inner(const Geo& g, const Phys& ph, const double* xyz, double* inner, hipStream_t st);
 hipError_t launch_metric_outer(const Geo& g, const Phys& ph, const double* xyz, const double* inner, double* met,

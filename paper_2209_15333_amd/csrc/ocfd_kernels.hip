@@ -145,6 +145,28 @@ __device__ __forceinline__ R c8(R g0, R g1, R g2, R g3, R g4, R g5, R g6, R g7) 
   return ((R)-3 * (g0 + g7) + (R)29 * (g1 + g6) - (R)139 * (g2 + g5) + (R)533 * (g3 + g4)) * (R)(1.0 / 840.0);
 }
 
+// Fifth-order WENO at j+1/2 from a0..a4 = f_{j-2..j+2} (Table 2 scheme 2),
+// substencil r (nodes j-2+r .. j+r) given weight zero when v_r is false
+// (it would reach outside a non-periodic domain, Sec. 2.2.4) and the other
+// nonlinear weights renormalised.  Masked inputs must be finite.
+template <typename R>
+__device__ __forceinline__ R weno5m(R a0, R a1, R a2, R a3, R a4, R eps, bool v0, bool v1, bool v2) {
+  const R q0 = ((R)2 * a0 - (R)7 * a1 + (R)11 * a2) * (R)(1.0 / 6.0);
+  const R q1 = (-a1 + (R)5 * a2 + (R)2 * a3) * (R)(1.0 / 6.0);
+  const R q2 = ((R)2 * a2 + (R)5 * a3 - a4) * (R)(1.0 / 6.0);
+  const R c13 = (R)(13.0 / 12.0), c14 = (R)0.25;
+  const R s0 = a0 - (R)2 * a1 + a2, t0 = a0 - (R)4 * a1 + (R)3 * a2;
+  const R s1 = a1 - (R)2 * a2 + a3, t1 = a1 - a3;
+  const R s2 = a2 - (R)2 * a3 + a4, t2 = (R)3 * a2 - (R)4 * a3 + a4;
+  R e0 = eps + (c13 * s0 * s0 + c14 * t0 * t0);
+  R e1 = eps + (c13 * s1 * s1 + c14 * t1 * t1);
+  R e2 = eps + (c13 * s2 * s2 + c14 * t2 * t2);
+  const R w0 = v0 ? (R)0.1 / (e0 * e0) : (R)0;
+  const R w1 = v1 ? (R)0.6 / (e1 * e1) : (R)0;
+  const R w2 = v2 ? (R)0.3 / (e2 * e2) : (R)0;
+  return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
 // ---------------------------------------------------------------------------
 // Directional sweep
 // ---------------------------------------------------------------------------
@@ -199,6 +221,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   const bool rcol_ok = col0 + rc < ncol;
   const double ih = A.ph.ih[DIR];
   const R eps = (R)A.ph.eps;
+  const bool per = A.g.periodic[DIR] != 0;
 
   // Raw inputs of one node: conserved variables, row DIR of the metrics / J,
   // node sensor.  Fetched one chunk ahead so the loads overlap the
@@ -210,7 +233,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   };
   auto fetch = [&](int m, int col) {
     NodeIn r;
-    const int jm = n >= 8 ? wrap1(m, n) : wrap(m, n);
+    const int jm = !per ? m : (n >= 8 ? wrap1(m, n) : wrap(m, n));
     const long long id = base + (long long)col * sc + (long long)jm * sd;
 #pragma unroll
     for (int q = 0; q < 5; ++q) r.U[q] = A.U[q * N + id];
@@ -238,24 +261,43 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     if (HYB) slot[10 * SW_W] = (R)in.th;
   };
 
-  // Output of node j of line col from its two interface fluxes.
-  auto emit = [&](int j, int col, const double* Fr, const double* Fl) {
+  // Output of node j of line col from its two interface fluxes (inv: this
+  // node has both interfaces along DIR, i.e. it is not an end of a
+  // non-periodic line).
+  auto emit = [&](int j, int col, const double* Fr, const double* Fl, bool inv) {
     const long long id = base + (long long)col * sc + (long long)j * sd;
     double r[5];
 #pragma unroll
-    for (int q = 0; q < 5; ++q) r[q] = A.inviscid ? -(Fr[q * SW_W] - Fl[q * SW_W]) * ih : 0.0;
+    for (int q = 0; q < 5; ++q) r[q] = (A.inviscid && inv) ? -(Fr[q * SW_W] - Fl[q * SW_W]) * ih : 0.0;
     if (A.viscous) {
-      // offsets of the six neighbours along the line (wrapped at the seam)
-      auto off = [&](int k) {
-        const int p = j + k;
-        return (long long)((n >= 8 ? wrap1(p, n) : wrap(p, n)) - j) * sd;
-      };
-      const long long o1p = off(1), o1m = off(-1), o2p = off(2), o2m = off(-2), o3p = off(3), o3m = off(-3);
+      if (per) {
+        // offsets of the six neighbours along the line (wrapped at the seam)
+        auto off = [&](int k) {
+          const int p = j + k;
+          return (long long)((n >= 8 ? wrap1(p, n) : wrap(p, n)) - j) * sd;
+        };
+        const long long o1p = off(1), o1m = off(-1), o2p = off(2), o2m = off(-2), o3p = off(3), o3m = off(-3);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const double* F = A.Fv + (long long)(4 * DIR + q) * N + id;
-        const double d = 0.75 * (F[o1p] - F[o1m]) - 0.15 * (F[o2p] - F[o2m]) + (1.0 / 60.0) * (F[o3p] - F[o3m]);
-        r[q + 1] += d * ih;
+        for (int q = 0; q < 4; ++q) {
+          const double* F = A.Fv + (long long)(4 * DIR + q) * N + id;
+          const double d = 0.75 * (F[o1p] - F[o1m]) - 0.15 * (F[o2p] - F[o2m]) + (1.0 / 60.0) * (F[o3p] - F[o3m]);
+          r[q + 1] += d * ih;
+        }
+      } else if (inv) {
+        // sixth order inside, then fourth and second order toward the ends (Sec. 2.3)
+        const int dist = min(j, n - 1 - j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double* F = A.Fv + (long long)(4 * DIR + q) * N + id;
+          double d;
+          if (dist == 1)
+            d = 0.5 * (F[sd] - F[-sd]);
+          else if (dist == 2)
+            d = (2.0 / 3.0) * (F[sd] - F[-sd]) - (1.0 / 12.0) * (F[2 * sd] - F[-2 * sd]);
+          else
+            d = 0.75 * (F[sd] - F[-sd]) - 0.15 * (F[2 * sd] - F[-2 * sd]) + (1.0 / 60.0) * (F[3 * sd] - F[-3 * sd]);
+          r[q + 1] += d * ih;
+        }
       }
     }
     if (MODE == MODE_SET) {
@@ -265,10 +307,20 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
 #pragma unroll
       for (int q = 0; q < 5; ++q) A.rhs[q * N + id] += r[q];
     } else {
+      // nodes on a face of a non-periodic direction take dU/dt = 0 (their
+      // value is set by the boundary condition after the stage)
+      bool bnd = false;
+      if (!A.g.periodic[0] || !A.g.periodic[1] || !A.g.periodic[2]) {
+        const int p0 = (int)(id % A.g.n[0]), p1 = (int)((id / A.g.n[0]) % A.g.n[1]),
+                  p2 = (int)(id / ((long long)A.g.n[0] * A.g.n[1]));
+        bnd = (!A.g.periodic[0] && (p0 == 0 || p0 == A.g.n[0] - 1)) ||
+              (!A.g.periodic[1] && (p1 == 0 || p1 == A.g.n[1] - 1)) ||
+              (!A.g.periodic[2] && (p2 == 0 || p2 == A.g.n[2] - 1));
+      }
       const double ij = 1.0 / A.met[9 * N + id];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        const double L = (A.rhs[q * N + id] + r[q]) * ij;
+        const double L = bnd ? 0.0 : (A.rhs[q * N + id] + r[q]) * ij;
         if (MODE == MODE_RK)
           A.out[q * N + id] = A.a * A.Un[q * N + id] + A.b * (A.U[q * N + id] + A.dt * L);
         else
@@ -279,17 +331,21 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
 
   const int nchunks = (n + SW_S - 1) / SW_S;
   // Chunk c reconstructs interfaces JB + 16c + s (s = 0..15) and loads nodes
-  // JB + 16c + 4 .. JB + 16c + 19; with JB = -4 every load window starts on a
-  // 16-node (128-byte) boundary of the line.
-  constexpr int JB = -4;
+  // JB + 16c + 4 .. JB + 16c + 19.  Periodic lines: JB = -4, so every load
+  // window starts on a 16-node (128-byte) boundary, n interfaces.  Non-periodic
+  // lines: JB = 0, interfaces 0 .. n-2, nodes outside [0, n-1] never loaded.
+  const int JB = per ? -4 : 0;
+  const int nif = per ? n : n - 1;          // interfaces of the line
+  const int mmax = n - 1;                   // last node the chunks load (the prologue covers JB-3 .. JB+3)
   // Prologue: nodes JB-3 .. JB+3 of every line.
   if (A.inviscid && t < 7 * SW_W) {
     const int pm = (DIR == 0) ? (t % 7) : (t / SW_W);
     const int pc = (DIR == 0) ? (t / 7) : (t % SW_W);
-    if (col0 + pc < ncol) split_store(JB + pm - 3, pc, fetch(JB + pm - 3, pc));
+    const int m = JB + pm - 3;
+    if (col0 + pc < ncol && (per || (m >= 0 && m < n))) split_store(m, pc, fetch(m, pc));
   }
   NodeIn ahead;
-  bool have = A.inviscid && gcol_ok && 4 + gs <= n + 3;
+  bool have = A.inviscid && gcol_ok && JB + 4 + gs <= mmax;
   if (have) ahead = fetch(JB + 4 + gs, gc);
   // Reconstruction of interface j of line col into dst (WENO7 or low-dissipation stencil).
   auto reconstruct = [&](int j, int col, bool low, double* dst) {
@@ -300,7 +356,16 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
 #define RP(o) P[((j + (o)) & (RING - 1)) * SLOT]
 #define RM(o) M[((j + (o)) & (RING - 1)) * SLOT]
       double F;
-      if (HYB && low) {
+      if (!per && (j < 3 || j > n - 5)) {
+        // stencil leaves the domain: masked WENO5 (out-of-domain values
+        // replaced by the centre value so the masked terms stay finite)
+        auto fp = [&](int o) { const int m = j + o; return (m >= 0 && m < n) ? RP(o) : RP(0); };
+        auto fm = [&](int o) { const int m = j + o; return (m >= 0 && m < n) ? RM(o) : RM(1); };
+        auto in = [&](int o) { const int m = j + o; return m >= 0 && m < n; };
+        // f+: substencils j-2..j, j-1..j+1, j..j+2; f- (mirrored): j+3..j+1, j+2..j, j+1..j-1
+        F = (double)weno5m<R>(fp(-2), fp(-1), fp(0), fp(1), fp(2), eps, in(-2), in(-1), in(2)) +
+            (double)weno5m<R>(fm(3), fm(2), fm(1), fm(0), fm(-1), eps, in(3), in(2), in(-1));
+      } else if (HYB && low) {
         if (A.lowdiss == OCFD_LOWDISS_C8)
           F = (double)c8<R>(RP(-3) + RM(-3), RP(-2) + RM(-2), RP(-1) + RM(-1), RP(0) + RM(0), RP(1) + RM(1),
                             RP(2) + RM(2), RP(3) + RM(3), RP(4) + RM(4));
@@ -322,16 +387,18 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     if (have) split_store(j0 + 4 + gs, gc, ahead);
     if (HYB && t == 0) wl_n = 0;
     __syncthreads();
-    have = A.inviscid && gcol_ok && c + 1 < nchunks && (c + 1) * SW_S + 4 + gs <= n + 3;
+    have = A.inviscid && gcol_ok && c + 1 < nchunks && j0 + SW_S + 4 + gs <= mmax;
     if (have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
     const int j = j0 + rs;
-    const bool act = A.inviscid && rcol_ok && c * SW_S + rs < n;
+    const bool act = A.inviscid && rcol_ok && c * SW_S + rs < nif;
     if (HYB) {
       // Low-dissipation interfaces are done in place; WENO interfaces go to a
       // work list so that whole waves run the WENO code (no divergence).
       if (act) {
         bool low;
-        if (A.flags) {
+        if (!per && (j < 3 || j > n - 5)) {
+          low = false;   // boundary closure: always the WENO5 path
+        } else if (A.flags) {
           low = A.flags[DIR * N + base + (long long)rc * sc + (long long)(n >= 8 ? wrap1(j, n) : wrap(j, n)) * sd] == 0;
         } else {
           R mx = (R)0;
@@ -355,17 +422,22 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     }
     __syncthreads();
     if (c == 0 && t < 5 * SW_W) fh0[(t / SW_W) * SW_W + (t % SW_W)] = fh[FHS + (t / SW_W) * SW_W + (t % SW_W)];
-    if (gcol_ok && c * SW_S + gs < n && (c > 0 || gs > 0))
-      emit(n >= 8 ? wrap1(j0 + gs, n) : wrap(j0 + gs, n), gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc);
+    if (per) {
+      if (gcol_ok && c * SW_S + gs < n && (c > 0 || gs > 0))
+        emit(n >= 8 ? wrap1(j0 + gs, n) : wrap(j0 + gs, n), gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc, true);
+    } else {
+      const int jn = j0 + gs;
+      if (gcol_ok && jn < n) emit(jn, gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc, jn > 0 && jn < n - 1);
+    }
     __syncthreads();
     if (t < 5 * SW_W) {
-      const int last = min(SW_S, n - c * SW_S);
-      fh[(t / SW_W) * SW_W + (t % SW_W)] = fh[last * FHS + (t / SW_W) * SW_W + (t % SW_W)];
+      const int last = min(SW_S, nif - c * SW_S);
+      if (last > 0) fh[(t / SW_W) * SW_W + (t % SW_W)] = fh[last * FHS + (t / SW_W) * SW_W + (t % SW_W)];
     }
   }
   __syncthreads();
-  // The line's first node (JB) with the wrapped flux carried out of the last chunk.
-  if (gs == 0 && gcol_ok) emit(wrap(JB, n), gc, fh0 + gc, fh + gc);
+  // The periodic line's first node (JB) with the wrapped flux carried out of the last chunk.
+  if (per && gs == 0 && gcol_ok) emit(wrap(JB, n), gc, fh0 + gc, fh + gc, true);
 }
 
 template <int DIR, int MODE>
@@ -401,6 +473,28 @@ hipError_t launch_sweep(int dir, int mode, const SweepArgs& a, hipStream_t st) {
   if (dir == 0) return launch_sweep_d<0>(mode, a, st);
   if (dir == 1) return launch_sweep_d<1>(mode, a, st);
   return launch_sweep_d<2>(mode, a, st);
+}
+
+// First derivative (times h) at node position pos of a line of n nodes from
+// values val(m) = f_{pos+m}.  Periodic lines and interior nodes use the central
+// operator of half width maxhalf; toward a non-periodic end the order drops as
+// Sec. 2.3 describes: one-sided second order at the end node, then central of
+// half width 1, 2, 3 at the next nodes.
+template <class F>
+__device__ __forceinline__ double line_deriv(F val, int pos, int n, bool periodic, int maxhalf) {
+  int half = maxhalf;
+  if (!periodic) {
+    const int dist = pos < n - 1 - pos ? pos : n - 1 - pos;
+    if (dist == 0)
+      return pos == 0 ? 0.5 * (-3.0 * val(0) + 4.0 * val(1) - val(2)) : 0.5 * (3.0 * val(0) - 4.0 * val(-1) + val(-2));
+    if (dist < half) half = dist;
+  }
+  if (half == 1) return 0.5 * (val(1) - val(-1));
+  if (half == 2) return (2.0 / 3.0) * (val(1) - val(-1)) - (1.0 / 12.0) * (val(2) - val(-2));
+  if (half == 3)
+    return 0.75 * (val(1) - val(-1)) - 0.15 * (val(2) - val(-2)) + (1.0 / 60.0) * (val(3) - val(-3));
+  return 0.8 * (val(1) - val(-1)) - 0.2 * (val(2) - val(-2)) + (4.0 / 105.0) * (val(3) - val(-3)) -
+         (1.0 / 280.0) * (val(4) - val(-4));
 }
 
 // ---------------------------------------------------------------------------
@@ -460,13 +554,19 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
   const long long N = g.N;
   const long long sz = g.s[2];
   const long long colid = i + (long long)nx * j;
+  const bool px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
+  // plane index of k (wrapped when zeta is periodic, clamped otherwise: the
+  // clamped planes are loaded but never used by the boundary closure)
+  auto zi = [&](int k) { return pz ? wrap(k, nz) : min(max(k, 0), nz - 1); };
   double zw[4][7];
 #pragma unroll
   for (int o = -3; o <= 2; ++o) {
-    const long long id = colid + (long long)wrap(k0 + o, nz) * sz;
+    const long long id = colid + (long long)zi(k0 + o) * sz;
 #pragma unroll
     for (int q = 0; q < 4; ++q) zw[q][o + 3] = W[q * N + id];
   }
+  // neighbour offsets along xi and eta (periodic lines; a non-periodic line
+  // uses the closure of line_deriv with direct offsets)
   const long long xp1 = wrap(i + 1, nx) - i, xm1 = wrap(i - 1, nx) - i;
   const long long xp2 = wrap(i + 2, nx) - i, xm2 = wrap(i - 2, nx) - i;
   const long long xp3 = wrap(i + 3, nx) - i, xm3 = wrap(i - 3, nx) - i;
@@ -474,7 +574,7 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
   const long long yp2 = (long long)(wrap(j + 2, ny) - j) * nx, ym2 = (long long)(wrap(j - 2, ny) - j) * nx;
   const long long yp3 = (long long)(wrap(j + 3, ny) - j) * nx, ym3 = (long long)(wrap(j - 3, ny) - j) * nx;
   for (int k = k0; k < k1; ++k) {
-    const long long idn = colid + (long long)wrap(k + 3, nz) * sz;
+    const long long idn = colid + (long long)zi(k + 3) * sz;
 #pragma unroll
     for (int q = 0; q < 4; ++q) zw[q][6] = W[q * N + idn];
     const long long id = colid + (long long)k * sz;
@@ -482,10 +582,19 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const double* f = W + q * N + id;
-      dq[q][0] = (0.75 * (f[xp1] - f[xm1]) - 0.15 * (f[xp2] - f[xm2]) + (1.0 / 60.0) * (f[xp3] - f[xm3])) * ph.ih[0];
-      dq[q][1] = (0.75 * (f[yp1] - f[ym1]) - 0.15 * (f[yp2] - f[ym2]) + (1.0 / 60.0) * (f[yp3] - f[ym3])) * ph.ih[1];
-      dq[q][2] = (0.75 * (zw[q][4] - zw[q][2]) - 0.15 * (zw[q][5] - zw[q][1]) + (1.0 / 60.0) * (zw[q][6] - zw[q][0])) *
-                 ph.ih[2];
+      if (px)
+        dq[q][0] = (0.75 * (f[xp1] - f[xm1]) - 0.15 * (f[xp2] - f[xm2]) + (1.0 / 60.0) * (f[xp3] - f[xm3])) * ph.ih[0];
+      else
+        dq[q][0] = line_deriv([&](int m) { return f[m]; }, i, nx, false, 3) * ph.ih[0];
+      if (py)
+        dq[q][1] = (0.75 * (f[yp1] - f[ym1]) - 0.15 * (f[yp2] - f[ym2]) + (1.0 / 60.0) * (f[yp3] - f[ym3])) * ph.ih[1];
+      else
+        dq[q][1] = line_deriv([&](int m) { return f[(long long)m * nx]; }, j, ny, false, 3) * ph.ih[1];
+      if (pz)
+        dq[q][2] = (0.75 * (zw[q][4] - zw[q][2]) - 0.15 * (zw[q][5] - zw[q][1]) + (1.0 / 60.0) * (zw[q][6] - zw[q][0])) *
+                   ph.ih[2];
+      else
+        dq[q][2] = line_deriv([&](int m) { return zw[q][3 + m]; }, k, nz, false, 3) * ph.ih[2];
     }
     const double ij = 1.0 / met[9 * N + id];
     double m[9];
@@ -541,6 +650,62 @@ hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const
 }
 
 // ---------------------------------------------------------------------------
+// Boundary conditions of a face of a bounded direction.  The paper names the
+// kinds (inflow, extrapolated outflow and far field, isothermal no-slip wall)
+// without formulas; the readings: INFLOW imposes the stored state, EXTRAP
+// copies rho, velocity and p from the first interior node, WALL sets zero
+// velocity, T = Tw and p from the first interior node (rho = gamma Ma^2 p / Tw,
+// eq 16-17).  One thread per face node; the face is indexed by its two other
+// node indices, the lower direction fastest.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bc(const Geo g, const Phys ph, double* __restrict__ U, int d, int side,
+                                            int kind, double Tw, const double* __restrict__ inflow) {
+  const int e0 = d == 0 ? 1 : 0, e1 = d == 2 ? 1 : 2;
+  const long long nf = (long long)g.n[e0] * g.n[e1];
+  const long long f = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (f >= nf) return;
+  int c[3];
+  c[e0] = (int)(f % g.n[e0]);
+  c[e1] = (int)(f / g.n[e0]);
+  c[d] = side ? g.n[d] - 1 : 0;
+  const long long N = g.N;
+  const long long id = c[0] + g.s[1] * c[1] + g.s[2] * c[2];
+  double o[5];
+  if (kind == OCFD_BC_INFLOW) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) o[q] = inflow[q * nf + f];
+  } else {
+    const long long ii = id + (side ? -g.s[d] : g.s[d]);
+    const double rho = U[ii];
+    const double u = U[N + ii] / rho, v = U[2 * N + ii] / rho, w = U[3 * N + ii] / rho;
+    const double ke = 0.5 * rho * (u * u + v * v + w * w);
+    const double p = ph.gm1 * (U[4 * N + ii] - ke);
+    if (kind == OCFD_BC_WALL) {
+      o[0] = ph.gamma * ph.Ma2 * p / Tw;
+      o[1] = o[2] = o[3] = 0.0;
+      o[4] = p / ph.gm1;
+    } else {
+      o[0] = rho;
+      o[1] = rho * u;
+      o[2] = rho * v;
+      o[3] = rho * w;
+      o[4] = p / ph.gm1 + ke;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 5; ++q) U[q * N + id] = o[q];
+}
+
+hipError_t launch_bc(const Geo& g, const Phys& ph, double* U, int d, int side, int kind, double Tw,
+                     const double* inflow, hipStream_t st) {
+  const long long nf = (long long)g.n[d == 0 ? 1 : 0] * g.n[d == 2 ? 1 : 2];
+  hipLaunchKernelGGL(k_bc, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, g, ph, U, d, side, kind, Tw,
+                     inflow);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // Shock sensor (eq 42-43): theta = sum_d |-p_- + 2p - p_+| / (p_- + 2p + p_+)
 // ---------------------------------------------------------------------------
 
@@ -562,6 +727,8 @@ __global__ __launch_bounds__(256) void k_sensor(const Geo g, const Phys ph, cons
   double th = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
+    // a node at the end of a non-periodic line has no second difference there
+    if (!g.periodic[d] && (pos[d] == 0 || pos[d] == g.n[d] - 1)) continue;
     const long long im = id + (long long)(wrap(pos[d] - 1, g.n[d]) - pos[d]) * g.s[d];
     const long long ip = id + (long long)(wrap(pos[d] + 1, g.n[d]) - pos[d]) * g.s[d];
     const double pm = node_p(ph, U, g.N, im), pp = node_p(ph, U, g.N, ip);
@@ -579,25 +746,15 @@ hipError_t launch_sensor(const Geo& g, const Phys& ph, const double* U, double* 
 // Metrics (eq 2-4) in the conservative form, eighth-order central operator
 // ---------------------------------------------------------------------------
 
-// Eighth-order central derivative (times h) of coordinate `co` along d at the
-// node, the seam crossing of direction d adding period[d] to coordinate d.
-__device__ __forceinline__ double d8_coord(const Geo& g, const Phys& ph, const double* xyz, int co, long long id,
-                                           const int* pos, int d) {
-  const double C[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
-  const double* x = xyz + co * g.N;
-  double s = 0.0;
-  for (int m = 1; m <= 4; ++m) {
-    const int pp = pos[d] + m, pm = pos[d] - m;
-    const int wp = wrap(pp, g.n[d]), wm = wrap(pm, g.n[d]);
-    double xp = x[id + (long long)(wp - pos[d]) * g.s[d]];
-    double xm = x[id + (long long)(wm - pos[d]) * g.s[d]];
-    if (co == d) {
-      xp += (double)((pp - wp) / g.n[d]) * ph.period[d];
-      xm += (double)((pm - wm) / g.n[d]) * ph.period[d];
-    }
-    s += C[m - 1] * (xp - xm);
-  }
-  return s;
+// Coordinate co at node pos + m along d (linear index id at pos), unwrapped
+// across the seam of a periodic direction: coordinate d grows by period[d].
+__device__ __forceinline__ double coord_at(const Geo& g, const Phys& ph, const double* xyz, int co, long long id,
+                                           const int* pos, int d, int m) {
+  const int p = pos[d] + m;
+  const int w = g.periodic[d] ? wrap(p, g.n[d]) : p;
+  double x = xyz[co * g.N + id + (long long)(w - pos[d]) * g.s[d]];
+  if (co == d && g.periodic[d]) x += (double)((p - w) / g.n[d]) * ph.period[d];
+  return x;
 }
 
 __global__ __launch_bounds__(256) void k_metric_inner(const Geo g, const Phys ph, const double* __restrict__ xyz,
@@ -606,7 +763,10 @@ __global__ __launch_bounds__(256) void k_metric_inner(const Geo g, const Phys ph
   if (id >= g.N) return;
   const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
   for (int co = 0; co < 3; ++co)
-    for (int d = 0; d < 3; ++d) inner[(3 * co + d) * g.N + id] = d8_coord(g, ph, xyz, co, id, pos, d) * ph.ih[d];
+    for (int d = 0; d < 3; ++d) {
+      auto val = [&](int m) { return coord_at(g, ph, xyz, co, id, pos, d, m); };
+      inner[(3 * co + d) * g.N + id] = line_deriv(val, pos[d], g.n[d], g.periodic[d], 4) * ph.ih[d];
+    }
 }
 
 hipError_t launch_metric_inner(const Geo& g, const Phys& ph, const double* xyz, double* inner, hipStream_t st) {
@@ -618,15 +778,14 @@ hipError_t launch_metric_inner(const Geo& g, const Phys& ph, const double* xyz, 
 //   (r_co)/J = D_t(a_s * b) - D_s(a_t * b)
 // with (s, t) = (r+1, r+2) and (a, b) = (co+1, co+2) cyclic; for example
 // xi_x/J = (y_eta z)_zeta - (y_zeta z)_eta.  The outer derivative uses the
-// same eighth-order operator, and the coordinate b is unwrapped across a seam
-// of the derivative direction.  1/J is the determinant of the inner
-// derivatives (eq 4).
+// same eighth-order operator (with its boundary closure), and the coordinate
+// b is unwrapped across a seam of the derivative direction.  1/J is the
+// determinant of the inner derivatives (eq 4).
 __global__ __launch_bounds__(256) void k_metric_outer(const Geo g, const Phys ph, const double* __restrict__ xyz,
                                                       const double* __restrict__ inner, double* __restrict__ met) {
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= g.N) return;
   const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
-  const double C[4] = {4.0 / 5.0, -1.0 / 5.0, 4.0 / 105.0, -1.0 / 280.0};
   for (int r = 0; r < 3; ++r)
     for (int co = 0; co < 3; ++co) {
       const int s = (r + 1) % 3, t = (r + 2) % 3;
@@ -636,21 +795,12 @@ __global__ __launch_bounds__(256) void k_metric_outer(const Geo g, const Phys ph
         const int dir = pass == 0 ? t : s;
         const int inn = pass == 0 ? s : t;
         const double* ia = inner + (3 * a + inn) * g.N;
-        const double* xb = xyz + b * g.N;
-        double acc = 0.0;
-        for (int m = 1; m <= 4; ++m) {
-          const int pp = pos[dir] + m, pm = pos[dir] - m;
-          const int wp = wrap(pp, g.n[dir]), wm = wrap(pm, g.n[dir]);
-          const long long ip = id + (long long)(wp - pos[dir]) * g.s[dir];
-          const long long im = id + (long long)(wm - pos[dir]) * g.s[dir];
-          double bp = xb[ip], bm = xb[im];
-          if (b == dir) {
-            bp += (double)((pp - wp) / g.n[dir]) * ph.period[dir];
-            bm += (double)((pm - wm) / g.n[dir]) * ph.period[dir];
-          }
-          acc += C[m - 1] * (ia[ip] * bp - ia[im] * bm);
-        }
-        term[pass] = acc * ph.ih[dir];
+        auto val = [&](int m) {
+          const int p = pos[dir] + m;
+          const int w = g.periodic[dir] ? wrap(p, g.n[dir]) : p;
+          return ia[id + (long long)(w - pos[dir]) * g.s[dir]] * coord_at(g, ph, xyz, b, id, pos, dir, m);
+        };
+        term[pass] = line_deriv(val, pos[dir], g.n[dir], g.periodic[dir], 4) * ph.ih[dir];
       }
       met[(3 * r + co) * g.N + id] = term[0] - term[1];
     }

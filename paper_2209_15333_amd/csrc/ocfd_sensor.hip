@@ -52,7 +52,11 @@ __global__ __launch_bounds__(256) void k_plain_flags(const Geo g, double theta1,
   const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
   for (int d = 0; d < 3; ++d) {
     double mx = 0.0;
-    for (int o = -3; o <= 4; ++o) mx = fmax(mx, theta[id + (long long)(wrapn(pos[d] + o, g.n[d]) - pos[d]) * g.s[d]]);
+    for (int o = -3; o <= 4; ++o) {
+      const int q = pos[d] + o;
+      if (!g.periodic[d] && (q < 0 || q >= g.n[d])) continue;   // window clipped at a bounded end
+      mx = fmax(mx, theta[id + (long long)(wrapn(q, g.n[d]) - pos[d]) * g.s[d]]);
+    }
     flags[d * g.N + id] = mx <= theta1 ? 0 : 1;
   }
 }

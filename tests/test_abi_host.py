@@ -35,8 +35,10 @@ def test_header_and_binding_agree(ocfd):
 
 
 def test_params_struct_layout(ocfd):
-    # 3 + 3 int32, 3 + 3 + 9 double, 3 + 5 int32 with padding to 8 bytes
-    assert ctypes.sizeof(ocfd.ocfd_params) == 176
+    # 3 + 3 + 6 int32, 3 + 3 + 10 double, 8 int32
+    assert ctypes.sizeof(ocfd.ocfd_params) == 208
+    assert ocfd.ocfd_params.bc.offset == 24 and ocfd.ocfd_params.period.offset == 48
+    assert ocfd.ocfd_params.Tw.offset == 48 + 8 * 12 and ocfd.ocfd_params.viscous.offset == 48 + 8 * 16
 
 
 def _params(ocfd, **kw):
@@ -57,8 +59,27 @@ def test_rejects_bad_parameters(ocfd):
         p = _params(ocfd, **bad)
         assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -1, bad
         assert L.ocfd_workspace_bytes(ctypes.byref(p)) == 0
+    # bounded directions: at least 8 nodes, known face kinds, one inflow face,
+    # a positive wall temperature; the learned sensor needs a periodic grid
+    for bad in (dict(ny=4), dict(bc=3, Tw=0.0), dict(bc=7), dict(bc=1, bc2=1)):
+        p = _params(ocfd)
+        p.periodic[1] = 0
+        if "ny" in bad:
+            p.ny = bad["ny"]
+        if "bc" in bad:
+            p.bc[2] = bad["bc"]
+        if "bc2" in bad:
+            p.bc[3] = bad["bc2"]
+        if "Tw" in bad:
+            p.Tw = bad["Tw"]
+        assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -1, bad
     p = _params(ocfd)
     p.periodic[1] = 0
+    p.bc[2], p.bc[3] = 3, 2
+    assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == 0
+    assert L.ocfd_set_inflow(h, ctypes.c_void_p(4096)) == -5     # no workspace yet
+    L.ocfd_destroy(h)
+    p.sensor = 1
     assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -4
 
 

@@ -1,0 +1,161 @@
+"""Parity of the HIP library with the CPU oracle on grids with bounded
+directions: a reduced compression ramp (bounded xi and eta, periodic zeta;
+inflow, outflow, wall and top faces) and a box bounded in all three
+directions.  Same bars as the periodic parity tests: states after substeps
+within 1e-12 (relative L2 per field), dU/dt within a multiple of the
+oracle's own one-ulp sensitivity; the face kinds exactly."""
+import numpy as np
+import pytest
+
+import workloads
+from helpers import rel_errors, ulp_perturbed, assert_within_roundoff
+
+pytestmark = pytest.mark.gpu
+
+TOL_L2 = 1e-12
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def pk(torch_cuda):
+    import paper_2209_15333_amd as pk
+    pk.lib()
+    return pk
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+CASES = {
+    "ramp": lambda: workloads.compression_ramp(shape=(40, 24, 8)),
+    "box": lambda: workloads.bounded_box(shape=(36, 20, 18)),
+}
+
+
+def _solver(pk, torch, case):
+    s = pk.Solver(pk.params_from(case))
+    s.set_grid(_dev(torch, case.xyz))
+    s.set_state(_dev(torch, case.U0))
+    if case.inflow is not None:
+        s.set_inflow(_dev(torch, case.inflow))
+    return s
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_bounded_metrics_parity(pk, torch_cuda, orc, name):
+    case = CASES[name]()
+    print("case", case.name, flush=True)
+    s = _solver(pk, torch_cuda, case)
+    met = orc.metrics(orc.params_from_case(case), case.xyz)
+    got = s.metrics().cpu().numpy()
+    assert np.abs(got - met).max() <= 1e-13 * np.abs(met).max()
+
+
+PARTS = {"xi": 1, "eta": 2, "zeta": 4, "visc": 8, "all": 15}
+
+
+@pytest.mark.parametrize("part", list(PARTS))
+@pytest.mark.parametrize("name", list(CASES))
+def test_bounded_dudt_parity(pk, torch_cuda, orc, name, part):
+    case = CASES[name]()
+    print("case", case.name, part, flush=True)
+    s = _solver(pk, torch_cuda, case)
+    P = orc.params_from_case(case)
+    met = orc.metrics(P, case.xyz)
+    ref = orc.dudt(P, met, case.U0, parts=PARTS[part])
+    ref_pert = orc.dudt(P, met, ulp_perturbed(case.U0), parts=PARTS[part])
+    got = s.dudt(_dev(torch_cuda, case.U0), PARTS[part]).cpu().numpy()
+    # faces of the bounded directions: exactly zero on both sides
+    for ax in (3, 2) + ((1,) if not case.periodic[2] else ()):
+        for end in (0, -1):
+            sl = [slice(None)] * 4
+            sl[ax] = end
+            assert np.all(got[tuple(sl)] == 0.0)
+    assert_within_roundoff(got, ref, ref_pert, what=f"{case.name} {part}")
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_bounded_advance_parity(pk, torch_cuda, orc, name):
+    """Two full Runge-Kutta steps with the faces set after every stage."""
+    case = CASES[name]()
+    print("case", case.name, flush=True)
+    s = _solver(pk, torch_cuda, case)
+    s.advance(6, case.dt)
+    got = s.state().cpu().numpy()
+    P = orc.params_from_case(case)
+    met = orc.metrics(P, case.xyz)
+    ref, _, _ = orc.advance(P, met, case.U0, 6, case.dt, inflow=case.inflow)
+    l2, linf = rel_errors(got, ref)
+    print(f"{case.name}: rel L2 {l2}, rel Linf {linf}", flush=True)
+    assert np.all(l2 <= TOL_L2)
+    # wall (eta-): no slip exactly; inflow face (xi-, away from the corners) held
+    assert np.all(got[1:4, :, 0, :] == 0.0)
+    assert np.array_equal(got[:, :, 1:-1, 0], case.inflow[:, :, 1:-1])
+
+
+@pytest.mark.parametrize("lowdiss", ["c8", "ud7"])
+def test_bounded_hybrid_parity(pk, torch_cuda, orc, lowdiss):
+    """Hybrid scheme with its own pressure sensor (windows clipped at the ends)."""
+    case = CASES["ramp"]()
+    case.scheme, case.lowdiss = "hybrid", lowdiss
+    # pressure noise in a ball around the grid centre, so the sensor marks part
+    # of the domain (the initial pressure is uniform)
+    rng = np.random.default_rng(17)
+    k, j, i = np.meshgrid(*[np.arange(n) - n / 2 for n in (case.nz, case.ny, case.nx)], indexing="ij")
+    ball = np.exp(-(i * i + j * j) / (2.0 * 5.0 ** 2))
+    U0 = case.U0.copy()
+    U0[4] *= 1.0 + 0.05 * ball * rng.standard_normal(ball.shape)
+    case.U0 = U0
+    s = _solver(pk, torch_cuda, case)
+    P = orc.params_from_case(case)
+    met = orc.metrics(P, case.xyz)
+    theta, flags = orc.sensor(P, case.U0)
+    fl = torch_cuda.zeros((3,) + case.U0.shape[1:], dtype=torch_cuda.uint8, device="cuda")
+    pk.ocfd_sensor_flags(s.h, _dev(torch_cuda, case.U0), pk.OCFD_SENSOR_PLAIN, fl)
+    low = (flags == 0).mean()
+    print(f"ramp hybrid {lowdiss}: low-dissipation fraction {low:.3f}", flush=True)
+    assert 0.05 < low < 0.95
+    assert np.array_equal(fl.cpu().numpy(), flags)
+    s.advance(3, case.dt)
+    got = s.state().cpu().numpy()
+    ref, _, _ = orc.advance(P, met, case.U0, 3, case.dt, inflow=case.inflow)
+    l2, _ = rel_errors(got, ref)
+    print(f"ramp hybrid {lowdiss}: rel L2 {l2}", flush=True)
+    assert np.all(l2 <= TOL_L2)
+
+
+def test_bounded_mixed_precision_drift(pk, torch_cuda, orc):
+    """FP32 split and reconstruction on the ramp: 30 substeps stay within
+    1e-5 of the FP64 oracle."""
+    case = CASES["ramp"]()
+    case.precision = "mixed"
+    s = _solver(pk, torch_cuda, case)
+    s.advance(30, case.dt)
+    got = s.state().cpu().numpy()
+    P = orc.params_from_case(case)
+    ref, _, _ = orc.advance(P, orc.metrics(P, case.xyz), case.U0, 30, case.dt, inflow=case.inflow)
+    l2, _ = rel_errors(got, ref)
+    print(f"ramp mixed 30 substeps: rel L2 {l2}", flush=True)
+    assert np.all(l2 <= 1e-5)
+    assert np.all(got[1:4, :, 0, :] == 0.0)
+
+
+def test_bounded_call_order_errors(pk, torch_cuda):
+    case = CASES["ramp"]()
+    s = pk.Solver(pk.params_from(case))
+    s.set_grid(_dev(torch_cuda, case.xyz))
+    s.set_state(_dev(torch_cuda, case.U0))
+    with pytest.raises(pk.OcfdError, match="STATE"):
+        s.advance(1, case.dt)                       # inflow face without its state
+    per = workloads.taylor_green(shape=(16, 16, 8))
+    t = pk.Solver(pk.params_from(per))
+    with pytest.raises(pk.OcfdError, match="UNSUPPORTED"):
+        t.set_inflow(_dev(torch_cuda, np.zeros((5, 8, 16))))

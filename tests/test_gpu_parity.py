@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import workloads
-from helpers import rel_errors
+from helpers import rel_errors, ulp_perturbed as _ulp_perturbed, assert_within_roundoff as _assert_within_roundoff
 
 pytestmark = pytest.mark.gpu
 
@@ -64,32 +64,6 @@ def _local_noise(case, amp, seed):
 def _orc(orc, case):
     P = orc.params_from_case(case)
     return P, orc.metrics(P, case.xyz)
-
-
-def _ulp_perturbed(U, seed=123):
-    """U with every value moved by about one unit in the last place."""
-    rng = np.random.default_rng(seed)
-    return U * (1.0 + 2.2e-16 * rng.choice([-1.0, 1.0], size=U.shape))
-
-
-# For smooth states the WENO7 nonlinear weights make dU/dt sensitive to
-# rounding: a one-ulp change of the input moves the oracle's own dU/dt by
-# ~1e-10 of its directional terms (and far more relative to near-zero net
-# fields such as d rho/dt of a divergence-free flow).  Where the states are
-# smooth, the GPU's dU/dt is therefore held to a multiple of that measured
-# sensitivity instead of a fixed relative bound.
-ROUNDOFF_FACTOR = 30.0
-
-
-def _assert_within_roundoff(got, ref, ref_pert, what=""):
-    got = got.reshape(5, -1)
-    ref = ref.reshape(5, -1)
-    ref_pert = ref_pert.reshape(5, -1)
-    err = np.sqrt(((got - ref) ** 2).sum(axis=1))
-    noise = np.sqrt(((ref_pert - ref) ** 2).sum(axis=1))
-    floor = 1e-13 * np.sqrt((ref ** 2).sum(axis=1)).max()
-    print(f"{what}: |gpu - oracle| {err}, oracle one-ulp sensitivity {noise}", flush=True)
-    assert np.all(err <= ROUNDOFF_FACTOR * noise + floor), (what, err / np.maximum(noise, 1e-300))
 
 
 def _assert_close(got, ref, tol2=TOL_L2, tolinf=TOL_INF, what=""):

@@ -266,3 +266,104 @@ def isotropic_turbulence(n: int = 512, seed: int = 22093, k0: float = 4.0, Mt: f
                 scheme="hybrid", lowdiss="c8")
     case.taylor_microscale = lam
     return case
+
+
+def _smooth_noise(rng, shape, sigma_cells: float = 2.0):
+    """Gaussian-smoothed white noise (periodic smoothing by FFT), unit rms."""
+    w = rng.standard_normal(shape)
+    k = [np.fft.fftfreq(n) for n in shape]
+    kk = np.meshgrid(*k, indexing="ij")
+    filt = np.exp(-2.0 * (math.pi * sigma_cells) ** 2 * sum(q * q for q in kk))
+    out = np.real(np.fft.ifftn(np.fft.fftn(w) * filt))
+    return out / np.sqrt(np.mean(out * out))
+
+
+def compression_ramp(shape: Tuple[int, int, int] = (1024, 160, 128), seed: int = 22094, Ma: float = 2.9,
+                     angle_deg: float = 24.0, Re: float = 5e4, Tw: float = 2.84, dt: Optional[float] = None,
+                     nsteps: int = 100, noise: float = 0.05) -> Case:
+    """Supersonic flow over a compression ramp on a body-fitted grid (lengths in
+    units of the inflow boundary-layer thickness delta).
+
+    x in [-20, 12] uniform; wall y_w(x) = tan(angle) r ln(1 + exp(x/r)),
+    r = 0.25 (a smoothed corner at x = 0); y = y_w(x) + H s_j with H = 10 and
+    tanh clustering s_j = 1 - tanh(b (1 - j/(ny-1))) / tanh(b), b chosen so the
+    first cell is 0.002 high; z in [0, 4) periodic.  Initial state: the
+    wall-parallel velocity tanh(3 y_n) (y_n the height above the wall),
+    temperature from the Crocco-Busemann relation with wall temperature Tw
+    and recovery factor Pr^(1/2), uniform pressure 1/(gamma Ma^2), plus
+    noise * u_bar * (Gaussian-smoothed white noise, 2 cells, unit rms) on u,
+    v, w (PCG64(seed)).  Boundaries: inflow (the initial profile) at x = -20,
+    extrapolation at the outlet and the top, isothermal wall at y_w."""
+    nx, ny, nz = shape
+    g, Pr = 1.4, 0.72
+    r, H, Lz = 0.25, 10.0, 4.0
+    tan_a = math.tan(math.radians(angle_deg))
+    X = -20.0 + 32.0 * np.arange(nx) / (nx - 1)
+    # stretching parameter: H (1 - tanh(b (1 - 1/(ny-1)))/tanh(b)) = 0.002
+    lo, hi = 1e-3, 20.0
+    for _ in range(200):
+        b = 0.5 * (lo + hi)
+        first = H * (1.0 - math.tanh(b * (1.0 - 1.0 / (ny - 1))) / math.tanh(b))
+        lo, hi = (b, hi) if first > 0.002 else (lo, b)
+    s = 1.0 - np.tanh(b * (1.0 - np.arange(ny) / (ny - 1))) / math.tanh(b)
+    yw = tan_a * r * np.log1p(np.exp(X / r))
+    slope = tan_a / (1.0 + np.exp(-X / r))
+    Z = np.arange(nz) * (Lz / nz)
+    Zg, Sg, Xg = np.meshgrid(Z, s, X, indexing="ij")
+    Yw = np.broadcast_to(yw[None, None, :], Xg.shape)
+    xyz = np.ascontiguousarray(np.stack([Xg, Yw + H * Sg, Zg]).astype(np.float64))
+    yn = H * Sg
+    ub = np.tanh(3.0 * yn)
+    rf = math.sqrt(Pr)
+    Taw = 1.0 + rf * 0.5 * (g - 1.0) * Ma * Ma
+    T = Tw + (Taw - Tw) * ub - rf * 0.5 * (g - 1.0) * Ma * Ma * ub * ub
+    p = np.full_like(T, 1.0 / (g * Ma * Ma))
+    rho = g * Ma * Ma * p / T
+    phi = np.arctan(np.broadcast_to(slope[None, None, :], Xg.shape))
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = ub * np.cos(phi) + noise * ub * _smooth_noise(rng, Xg.shape)
+    v = ub * np.sin(phi) + noise * ub * _smooth_noise(rng, Xg.shape)
+    w = noise * ub * _smooth_noise(rng, Xg.shape)
+    U0 = conserved(g, rho, u, v, w, p)
+    # inflow face (i = 0), [5][nz][ny] with eta fastest
+    inflow = np.ascontiguousarray(U0[:, :, :, 0])
+    if dt is None:
+        dt = 8e-4   # set by the 0.002-high wall cell (acoustic CFL ~0.33)
+    h = (32.0 / (nx - 1), H / (ny - 1), Lz / nz)
+    return Case(name=f"ramp{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=U0, period=(0.0, 0.0, Lz), h=h,
+                dt=dt, nsteps=nsteps, periodic=(0, 0, 1), bc=(1, 2, 3, 2, 0, 0), gamma=g, Re=Re, Ma=Ma, Pr=Pr,
+                Tref=108.1, Tw=Tw, inflow=inflow)
+
+
+def bounded_box(shape: Tuple[int, int, int] = (36, 20, 18), seed: int = 22095, Ma: float = 0.5, Re: float = 500.0,
+                amplitude: float = 0.04, noise: float = 0.02) -> Case:
+    """A box bounded in all three directions on a distorted grid: unit spacing
+    nodes moved by amplitude * sin products (phases from PCG64(seed)); a smooth
+    shear flow u = 1 + 0.3 tanh(2 (y - y_mid)), v = 0.1 sin(x/2), w = 0.05 cos(z/2)
+    at Mach Ma with uniform pressure and temperature 1, plus relative noise on
+    the velocities.  Faces: inflow (the initial face) at xi-, extrapolation at
+    xi+, isothermal wall (Tw = 1) at eta-, extrapolation elsewhere."""
+    nx, ny, nz = shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    ph = rng.uniform(0.0, 2.0 * math.pi, 9)
+    K, J, I = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    a = amplitude
+    x = I + a * np.sin(0.3 * J + ph[0]) * np.sin(0.2 * K + ph[1])
+    y = J + a * np.sin(0.25 * I + ph[2]) * np.sin(0.3 * K + ph[3])
+    z = K + a * np.sin(0.2 * I + ph[4]) * np.sin(0.25 * J + ph[5])
+    xyz = np.ascontiguousarray(np.stack([x, y, z]))
+    g = 1.4
+    u = 1.0 + 0.3 * np.tanh(2.0 * (y - 0.5 * (ny - 1)))
+    v = 0.1 * np.sin(0.5 * x)
+    w = 0.05 * np.cos(0.5 * z)
+    u = u * (1.0 + noise * rng.standard_normal(u.shape))
+    v = v + noise * rng.standard_normal(v.shape)
+    w = w + noise * rng.standard_normal(w.shape)
+    p = np.full_like(u, 1.0 / (g * Ma * Ma))
+    rho = np.ones_like(u)
+    U0 = conserved(g, rho, u, v, w, p)
+    inflow = np.ascontiguousarray(U0[:, :, :, 0])
+    return Case(name=f"box{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=U0, period=(0.0, 0.0, 0.0),
+                h=(1.0, 1.0, 1.0), dt=0.05, nsteps=10, periodic=(0, 0, 0), bc=(1, 2, 3, 2, 2, 2), gamma=g, Re=Re,
+                Ma=Ma, Pr=0.72, Tw=1.0, inflow=inflow)
