@@ -134,8 +134,7 @@ int ocfd_params_default(ocfd_params* p);
 size_t ocfd_workspace_bytes(const ocfd_params* p);
 
 /* Create a solver.  stream: a hipStream_t (NULL: the default stream).  The
-   solver copies *p.  Errors: BADARG (null pointer / invalid parameter),
-   UNSUPPORTED (the learned sensor on a grid with a bounded direction). */
+   solver copies *p.  Errors: BADARG (null pointer / invalid parameter). */
 int ocfd_create(const ocfd_params* p, void* stream, ocfd_solver** out);
 
 /* Hand the solver caller-owned device memory of at least
@@ -212,7 +211,11 @@ const char* ocfd_kernel_name(int32_t kernel_class);
    Inference and training run on bf16 matrix cores with FP32 accumulation and
    FP32 master weights.  Parameters: one flat FP32 array of
    ocfd_sensor_nparams() values: W1 [32 inputs][32 units], b1 [32],
-   W2 [32][32], b2 [32], w3 [32], b3 [1]. */
+   W2 [32][32], b2 [32], w3 [32], b3 [1].
+   On a bounded line the features of an end node use a one-sided difference
+   over one spacing and zero jumps; interfaces whose 8-node window leaves the
+   grid (j < 3 or j > n-5) take the masked WENO5 closure whatever their flag:
+   their learned flag is 1 and they are neither sampled nor audited. */
 int32_t ocfd_sensor_nparams(void);
 int ocfd_sensor_set_params(ocfd_solver* s, const float* params_host);
 int ocfd_sensor_get_params(ocfd_solver* s, float* params_host);

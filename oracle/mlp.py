@@ -103,18 +103,37 @@ def loss_and_grad(theta, X, y, w, round_bf16: bool = False):
 
 # ------------------------------------------------------------------ features
 
-def node_features(gamma: float, h, met: np.ndarray, U: np.ndarray) -> np.ndarray:
+def node_features(gamma: float, h, met: np.ndarray, U: np.ndarray, periodic=(1, 1, 1)) -> np.ndarray:
     """Node features [8, nz, ny, nx]: Delta div/c, Delta |curl|/c, then for
-    xi, eta, zeta the pressure jump and the density jump.  Periodic grids."""
+    xi, eta, zeta the pressure and the density jump.  Along a bounded
+    direction an end node takes a one-sided difference over one spacing and
+    zero jumps."""
     rho = U[0]
     vel = [U[1] / rho, U[2] / rho, U[3] / rho]
     p = (gamma - 1.0) * (U[4] - 0.5 * rho * (vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2))
     c = np.sqrt(gamma * p / rho)
     jinv = met[9]
     axis = {0: 2, 1: 1, 2: 0}
-    # d(vel_a)/d(xi_d), second-order central
-    dvd = [[(np.roll(vel[a], -1, axis[d]) - np.roll(vel[a], 1, axis[d])) / (2.0 * h[d]) for d in range(3)]
-           for a in range(3)]
+
+    def plus_minus(q, d):
+        """q at the next and previous node along d, and the spacing between them."""
+        ax = axis[d]
+        if periodic[d]:
+            return np.roll(q, -1, ax), np.roll(q, 1, ax), np.full(q.shape, 2.0 * h[d])
+        n = q.shape[ax]
+        idx = np.arange(n)
+        ip, im = np.minimum(idx + 1, n - 1), np.maximum(idx - 1, 0)
+        span = ((ip - im) * h[d]).astype(np.float64)
+        shape = [1, 1, 1]
+        shape[ax] = n
+        return np.take(q, ip, axis=ax), np.take(q, im, axis=ax), np.broadcast_to(span.reshape(shape), q.shape)
+
+    # d(vel_a)/d(xi_d): central (one-sided at a bounded end)
+    dvd = [[None] * 3 for _ in range(3)]
+    for d in range(3):
+        for a in range(3):
+            vp, vm, span = plus_minus(vel[a], d)
+            dvd[a][d] = (vp - vm) / span
     grad = [[sum((met[3 * d + col] / jinv) * dvd[a][d] for d in range(3)) for col in range(3)] for a in range(3)]
     div = grad[0][0] + grad[1][1] + grad[2][2]
     wx = grad[2][1] - grad[1][2]
@@ -127,25 +146,38 @@ def node_features(gamma: float, h, met: np.ndarray, U: np.ndarray) -> np.ndarray
     F[1] = delta * vort / c
     for d in range(3):
         for k, q in enumerate((p, rho)):
-            qp = np.roll(q, -1, axis[d])
-            qm = np.roll(q, 1, axis[d])
-            F[2 + 2 * d + k] = np.abs(qp - qm) / (qp + qm)
+            qp, qm, _ = plus_minus(q, d)
+            jump = np.abs(qp - qm) / (qp + qm)
+            if not periodic[d]:
+                sl = [slice(None)] * 3
+                for end in (0, -1):
+                    sl[axis[d]] = end
+                    jump[tuple(sl)] = 0.0
+            F[2 + 2 * d + k] = jump
     return F
 
 
-def interface_inputs(F: np.ndarray, d: int, nodes: np.ndarray) -> np.ndarray:
+def interface_inputs(F: np.ndarray, d: int, nodes: np.ndarray, periodic: bool = True) -> np.ndarray:
     """Inputs [n, 32] of the interfaces (node + 1/2 along direction d) at the
-    given linear node indices: x[4t + f] = feature f of node j - 3 + t."""
+    given linear node indices: x[4t + f] = feature f of node j - 3 + t (on a
+    bounded line, positions outside are clamped to the ends; such interfaces
+    are not decided by a sensor)."""
     nz, ny, nx = F.shape[1:]
     n = (nx, ny, nz)[d]
     k, j, i = np.unravel_index(nodes, (nz, ny, nx))
     pos = (i, j, k)[d]
     X = np.zeros((len(nodes), 32))
     for t in range(8):
-        q = (pos + t - 3) % n
+        q = (pos + t - 3) % n if periodic else np.clip(pos + t - 3, 0, n - 1)
         ii, jj, kk = (q if d == 0 else i), (q if d == 1 else j), (q if d == 2 else k)
         X[:, 4 * t + 0] = F[0][kk, jj, ii]
         X[:, 4 * t + 1] = F[1][kk, jj, ii]
         X[:, 4 * t + 2] = F[2 + 2 * d][kk, jj, ii]
         X[:, 4 * t + 3] = F[3 + 2 * d][kk, jj, ii]
     return X
+
+
+def window_inside(n: int, pos, periodic: bool):
+    """Interfaces whose 8-node window stays inside the grid."""
+    pos = np.asarray(pos)
+    return np.ones(pos.shape, bool) if periodic else (pos >= 3) & (pos <= n - 5)

@@ -153,6 +153,17 @@ long long face_nodes(const ocfd_params& p, int d) {
 
 bool all_periodic(const ocfd_params& p) { return p.periodic[0] && p.periodic[1] && p.periodic[2]; }
 
+// Interfaces whose scheme a sensor decides: all of a periodic line, and on a
+// bounded line those whose 8-node window stays inside (n - 7 of them).
+long long decided_interfaces(const Geo& g) {
+  long long t = 0;
+  for (int d = 0; d < 3; ++d) {
+    const long long lines = g.N / g.n[d];
+    t += lines * (g.periodic[d] ? g.n[d] : std::max(0, g.n[d] - 7));
+  }
+  return t;
+}
+
 void setup_geo_phys(ocfd_solver* s) {
   const ocfd_params& p = s->p;
   s->g.n[0] = p.nx;
@@ -291,7 +302,7 @@ int learned_flags(ocfd_solver* s, const double* Ucur, bool count_substep) {
   if (count_substep && s->p.audit_every > 0 && k % s->p.audit_every == 0) {
     e = launch_sensor(s->g, s->ph, Ucur, s->theta, s->st);
     if (e == hipSuccess) e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
-    if (e == hipSuccess) e = launch_flag_stats(s->pflags, s->lflags, 3 * s->g.N, s->cnt, COUNT_BLOCKS, s->st);
+    if (e == hipSuccess) e = launch_flag_stats(s->g, s->pflags, s->lflags, s->cnt, COUNT_BLOCKS, s->st);
     std::vector<unsigned long long> c(COUNT_BLOCKS * 4);
     if (e == hipSuccess)
       e = hipMemcpyAsync(c.data(), s->cnt, c.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost, s->st);
@@ -305,7 +316,7 @@ int learned_flags(ocfd_solver* s, const double* Ucur, bool count_substep) {
       mism += c[4 * b + 3];
     }
     s->audit[0] += 1;
-    s->audit[1] += 3.0 * (double)s->g.N;
+    s->audit[1] += (double)decided_interfaces(s->g);
     s->audit[2] += (double)plain;
     s->audit[3] += (double)(plain - missed + extra);
     s->audit[4] += (double)missed;
@@ -435,10 +446,6 @@ int ocfd_create(const ocfd_params* p, void* stream, ocfd_solver** out) {
   if (!valid_params(p, &why)) {
     fprintf(stderr, "ocfd_create: %s\n", why.c_str());
     return OCFD_ERR_BADARG;
-  }
-  if (p->sensor == OCFD_SENSOR_LEARNED && !all_periodic(*p)) {
-    fprintf(stderr, "ocfd_create: the learned sensor is built for periodic grids only\n");
-    return OCFD_ERR_UNSUPPORTED;
   }
   ocfd_solver* s = new (std::nothrow) ocfd_solver();
   if (!s) return OCFD_ERR_BADARG;
@@ -684,7 +691,6 @@ int ocfd_sensor_flags(ocfd_solver* s, const double* U, int32_t which, uint8_t* f
     e = launch_sensor(s->g, s->ph, U, s->theta, s->st);
     if (e == hipSuccess) e = launch_plain_flags(s->g, s->ph.theta1, s->theta, flags, s->st);
   } else if (which == OCFD_SENSOR_LEARNED) {
-    if (!all_periodic(s->p)) return fail(s, OCFD_ERR_UNSUPPORTED, "learned sensor on a bounded grid");
     if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "no network parameters set");
     e = launch_features(s->g, s->ph, U, s->met, s->feat, s->st);
     if (e == hipSuccess) e = launch_mlp_flags(s->g, s->feat, s->mlp, (float)s->tau, flags, s->st);
@@ -716,7 +722,6 @@ int ocfd_sensor_bind_samples(ocfd_solver* s, void* dev, size_t bytes) {
 }
 
 int ocfd_sensor_collect(ocfd_solver* s, uint64_t seed, double keep_weno, double keep_low, int64_t* total) {
-  if (s && !all_periodic(s->p)) return fail(s, OCFD_ERR_UNSUPPORTED, "learned sensor on a bounded grid");
   int rc;
   if (!ready(s, &rc)) return rc;
   if (!total) return fail(s, OCFD_ERR_BADARG, "null output");

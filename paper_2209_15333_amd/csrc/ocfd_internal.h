@@ -101,7 +101,7 @@ hipError_t launch_collect_write(const Geo& g, const uint8_t* flags, const float*
                                 uint32_t thr_neg, const unsigned long long* offs, long long cap, uint16_t* X,
                                 uint8_t* y, float* w, int nblocks, hipStream_t st);
 hipError_t launch_flags_or(uint8_t* a, const uint8_t* b, long long n, hipStream_t st);
-hipError_t launch_flag_stats(const uint8_t* fa, const uint8_t* fb, long long total, unsigned long long* out,
+hipError_t launch_flag_stats(const Geo& g, const uint8_t* fa, const uint8_t* fb, unsigned long long* out,
                              int nblocks, hipStream_t st);
 
 }  // namespace ocfd

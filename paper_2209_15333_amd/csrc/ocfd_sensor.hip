@@ -80,8 +80,15 @@ __global__ __launch_bounds__(256) void k_features(const Geo g, const Phys ph, co
   double dvd[3][3];  // d(vel_a)/d(xi_d)
   double jp[3], jr[3];
   for (int d = 0; d < 3; ++d) {
-    const long long ip = id + (long long)(wrapn(pos[d] + 1, g.n[d]) - pos[d]) * g.s[d];
-    const long long im = id + (long long)(wrapn(pos[d] - 1, g.n[d]) - pos[d]) * g.s[d];
+    // neighbours along d; at the end of a bounded line the difference is
+    // one-sided over one spacing and the jumps are zero
+    const bool bnd = !g.periodic[d];
+    const int qp = bnd ? min(pos[d] + 1, g.n[d] - 1) : wrapn(pos[d] + 1, g.n[d]);
+    const int qm = bnd ? max(pos[d] - 1, 0) : wrapn(pos[d] - 1, g.n[d]);
+    const bool end = bnd && (pos[d] == 0 || pos[d] == g.n[d] - 1);
+    const double span = (bnd ? (double)(qp - qm) : 2.0) * ph.h[d];
+    const long long ip = id + (long long)(qp - pos[d]) * g.s[d];
+    const long long im = id + (long long)(qm - pos[d]) * g.s[d];
     double vp[3], vm[3];
     const double rp = U[ip], rm = U[im];
     for (int a = 0; a < 3; ++a) {
@@ -90,9 +97,9 @@ __global__ __launch_bounds__(256) void k_features(const Geo g, const Phys ph, co
     }
     const double pp = ph.gm1 * (U[4 * N + ip] - 0.5 * rp * (vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2]));
     const double pm = ph.gm1 * (U[4 * N + im] - 0.5 * rm * (vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2]));
-    for (int a = 0; a < 3; ++a) dvd[a][d] = (vp[a] - vm[a]) / (2.0 * ph.h[d]);
-    jp[d] = fabs(pp - pm) / (pp + pm);
-    jr[d] = fabs(rp - rm) / (rp + rm);
+    for (int a = 0; a < 3; ++a) dvd[a][d] = (vp[a] - vm[a]) / span;
+    jp[d] = end ? 0.0 : fabs(pp - pm) / (pp + pm);
+    jr[d] = end ? 0.0 : fabs(rp - rm) / (rp + rm);
   }
   const double jinv = met[9 * N + id];
   double gr[3][3];
@@ -122,6 +129,18 @@ hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const 
                            hipStream_t st) {
   hipLaunchKernelGGL(k_features, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, U, met, feat);
   return hipGetLastError();
+}
+
+// Does the 8-node window j-3 .. j+4 of interface (d, node at pos) stay inside
+// the grid?  Always on periodic lines; on a bounded line only for
+// 3 <= j <= n-5 (the other interfaces use the masked WENO5 closure whatever
+// their flag, and are neither sampled nor audited).
+__device__ __forceinline__ bool window_inside(const Geo& g, int d, int pos) {
+  return g.periodic[d] || (pos >= 3 && pos <= g.n[d] - 5);
+}
+
+__device__ __forceinline__ int node_pos(const Geo& g, long long id, int d) {
+  return d == 0 ? (int)(id % g.n[0]) : d == 1 ? (int)((id / g.n[0]) % g.n[1]) : (int)(id / ((long long)g.n[0] * g.n[1]));
 }
 
 // ---------------------------------------------------------------------------
@@ -203,10 +222,12 @@ __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const float* __r
     const bool ok = id < N;
     const long long idc = ok ? id : N - 1;
     const int pos[3] = {(int)(idc % g.n[0]), (int)((idc / g.n[0]) % g.n[1]), (int)(idc / ((long long)g.n[0] * g.n[1]))};
+    const bool inside = window_inside(g, d, pos[d]);
     v8bf x;
     for (int tt = 0; tt < 2; ++tt) {
       const int t = 2 * gg + tt;
-      const long long nid = idc + (long long)(wrapn(pos[d] + t - 3, g.n[d]) - pos[d]) * g.s[d];
+      const int q = g.periodic[d] ? wrapn(pos[d] + t - 3, g.n[d]) : min(max(pos[d] + t - 3, 0), g.n[d] - 1);
+      const long long nid = idc + (long long)(q - pos[d]) * g.s[d];
       x[4 * tt + 0] = (__bf16)feat[nid];
       x[4 * tt + 1] = (__bf16)feat[N + nid];
       x[4 * tt + 2] = (__bf16)feat[(2 + 2 * d) * N + nid];
@@ -214,7 +235,7 @@ __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const float* __r
     }
     Fwd F;
     mlp_forward(R, x, F);
-    if (ok && gg == 0) flags[d * N + id] = sigmoidf(F.z) >= tau ? 1 : 0;
+    if (ok && gg == 0) flags[d * N + id] = (!inside || sigmoidf(F.z) >= tau) ? 1 : 0;
   }
 }
 
@@ -434,8 +455,9 @@ __device__ __forceinline__ uint32_t hash3(uint64_t seed, uint32_t d, uint64_t id
   return (uint32_t)(z >> 32);
 }
 
-__device__ __forceinline__ bool keep_interface(uint64_t seed, int d, long long id, uint8_t flag, uint32_t thr_pos,
-                                               uint32_t thr_neg) {
+__device__ __forceinline__ bool keep_interface(const Geo& g, uint64_t seed, int d, long long id, uint8_t flag,
+                                               uint32_t thr_pos, uint32_t thr_neg) {
+  if (!window_inside(g, d, node_pos(g, id, d))) return false;
   const uint32_t h = hash3(seed, (uint32_t)d, (uint64_t)id);
   return flag ? h < thr_pos : h < thr_neg;
 }
@@ -453,7 +475,7 @@ __global__ __launch_bounds__(CT) void k_collect_count(const Geo g, const uint8_t
   for (long long k = a + threadIdx.x; k < b; k += CT) {
     const int d = (int)(k / g.N);
     const long long id = k % g.N;
-    c += keep_interface(seed, d, id, flags[k], thr_pos, thr_neg) ? 1 : 0;
+    c += keep_interface(g, seed, d, id, flags[k], thr_pos, thr_neg) ? 1 : 0;
   }
   sh[threadIdx.x] = c;
   __syncthreads();
@@ -484,7 +506,7 @@ __global__ __launch_bounds__(CT) void k_collect_write(const Geo g, const uint8_t
     const bool in = k < b;
     const int d = in ? (int)(k / N) : 0;
     const long long id = in ? k % N : 0;
-    const bool kp = in && keep_interface(seed, d, id, flags[in ? k : 0], thr_pos, thr_neg);
+    const bool kp = in && keep_interface(g, seed, d, id, flags[in ? k : 0], thr_pos, thr_neg);
     sc[threadIdx.x] = kp ? 1 : 0;
     __syncthreads();
     // exclusive prefix of this round (serial in one thread: 256 entries)
@@ -503,7 +525,7 @@ __global__ __launch_bounds__(CT) void k_collect_write(const Geo g, const uint8_t
         const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
         uint16_t xs[32];
         for (int t = 0; t < 8; ++t) {
-          const long long nid = id + (long long)(wrapn(pos[d] + t - 3, g.n[d]) - pos[d]) * g.s[d];
+          const long long nid = id + (long long)(wrapn(pos[d] + t - 3, g.n[d]) - pos[d]) * g.s[d];  // window inside
           const float f[4] = {feat[nid], feat[N + nid], feat[(2 + 2 * d) * N + nid], feat[(3 + 2 * d) * N + nid]};
           for (int q = 0; q < 4; ++q) {
             const __bf16 bv = (__bf16)f[q];
@@ -535,12 +557,16 @@ hipError_t launch_collect_write(const Geo& g, const uint8_t* flags, const float*
   return hipGetLastError();
 }
 
-// Class counts of a flag field: out[0] = interfaces flagged 1, out[1] = 0 (per workgroup partials).
-__global__ __launch_bounds__(CT) void k_flag_stats(const uint8_t* __restrict__ fa, const uint8_t* __restrict__ fb,
-                                                   long long total, unsigned long long* __restrict__ out) {
+// Class counts of flag fields over the interfaces whose window stays inside
+// the grid (per workgroup partials).
+__global__ __launch_bounds__(CT) void k_flag_stats(const Geo g, const uint8_t* __restrict__ fa,
+                                                   const uint8_t* __restrict__ fb, unsigned long long* __restrict__ out) {
   __shared__ unsigned long long sh[4][CT];
   unsigned long long c[4] = {0, 0, 0, 0};  // a=1, a=0&b=1, a=1&b=0, a!=b
+  const long long total = 3 * g.N;
   for (long long k = (long long)blockIdx.x * CT + threadIdx.x; k < total; k += (long long)gridDim.x * CT) {
+    const int d = (int)(k / g.N);
+    if (!window_inside(g, d, node_pos(g, k % g.N, d))) continue;
     const uint8_t x = fa[k];
     c[0] += x ? 1 : 0;
     if (fb) {
@@ -559,9 +585,9 @@ __global__ __launch_bounds__(CT) void k_flag_stats(const uint8_t* __restrict__ f
   }
 }
 
-hipError_t launch_flag_stats(const uint8_t* fa, const uint8_t* fb, long long total, unsigned long long* out,
+hipError_t launch_flag_stats(const Geo& g, const uint8_t* fa, const uint8_t* fb, unsigned long long* out,
                              int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_flag_stats, dim3(nblocks), dim3(CT), 0, st, fa, fb, total, out);
+  hipLaunchKernelGGL(k_flag_stats, dim3(nblocks), dim3(CT), 0, st, g, fa, fb, out);
   return hipGetLastError();
 }
 

@@ -60,7 +60,7 @@ def test_rejects_bad_parameters(ocfd):
         assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -1, bad
         assert L.ocfd_workspace_bytes(ctypes.byref(p)) == 0
     # bounded directions: at least 8 nodes, known face kinds, one inflow face,
-    # a positive wall temperature; the learned sensor needs a periodic grid
+    # a positive wall temperature
     for bad in (dict(ny=4), dict(bc=3, Tw=0.0), dict(bc=7), dict(bc=1, bc2=1)):
         p = _params(ocfd)
         p.periodic[1] = 0
@@ -80,7 +80,8 @@ def test_rejects_bad_parameters(ocfd):
     assert L.ocfd_set_inflow(h, ctypes.c_void_p(4096)) == -5     # no workspace yet
     L.ocfd_destroy(h)
     p.sensor = 1
-    assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -4
+    assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == 0
+    L.ocfd_destroy(h)
 
 
 def test_workspace_and_order_errors(ocfd):

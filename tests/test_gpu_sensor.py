@@ -127,6 +127,39 @@ def test_learned_flags_match_oracle(pk, torch_cuda, orc):
         assert np.all(np.abs(p[bad] - tau) < 1e-3)
 
 
+def test_learned_flags_bounded_match_oracle(pk, torch_cuda, orc):
+    """Reduced compression ramp (bounded xi, eta): one-sided features at the
+    ends, flag 1 wherever the interface window leaves the grid."""
+    case = workloads.compression_ramp(shape=(40, 24, 8))
+    case.scheme, case.sensor = "hybrid", "learned"
+    s = _solver(pk, torch_cuda, case)
+    theta = mlp.init_params(9)
+    theta[mlp.NPARAM - 33:mlp.NPARAM - 1] *= 20.0
+    pk.ocfd_sensor_set_params(s.h, theta)
+    tau = 0.5
+    pk.ocfd_sensor_set_threshold(s.h, tau)
+    fl = torch_cuda.zeros((3,) + case.U0.shape[1:], dtype=torch_cuda.uint8, device="cuda")
+    pk.ocfd_sensor_flags(s.h, _dev(torch_cuda, case.U0), pk.OCFD_SENSOR_LEARNED, fl)
+    got = fl.cpu().numpy().reshape(3, -1)
+    P = orc.params_from_case(case)
+    met = orc.metrics(P, case.xyz)
+    F = mlp.node_features(case.gamma, case.h, met, case.U0, case.periodic).astype(np.float32).astype(np.float64)
+    nodes = np.arange(case.N)
+    k, j, i = np.unravel_index(nodes, case.U0.shape[1:])
+    theta32 = theta.astype(np.float32).astype(np.float64)
+    for d in range(3):
+        n = (case.nx, case.ny, case.nz)[d]
+        inside = mlp.window_inside(n, (i, j, k)[d], bool(case.periodic[d]))
+        X = mlp.interface_inputs(F, d, nodes, bool(case.periodic[d]))
+        p, _ = mlp.forward(theta32, X, round_bf16=True)
+        ref = np.where(inside, (p >= tau).astype(np.uint8), 1)
+        bad = got[d] != ref
+        print(f"bounded learned flags dir {d}: WENO fraction {ref[inside].mean():.3f}, disagreements {bad.sum()}",
+              flush=True)
+        assert bad.sum() <= 1e-4 * case.N + 2
+        assert np.all(np.abs(p[bad] - tau) < 1e-3)
+
+
 def test_learned_hybrid_end_to_end(pk, torch_cuda):
     """Samples from the plain sensor on developing isotropic turbulence, GPU
     training (loss falls), calibration (every held-out WENO interface kept),

@@ -66,3 +66,31 @@ def test_features_closed_forms():
     assert F[3][0, 0, 5] == pytest.approx((r - 1) / (r + 1))
     assert F[3][0, 0, 6] == pytest.approx((r - 1) / (r + 1))
     assert F[3][0, 0, 3] == 0.0 and np.all(F[5] == 0.0) and np.all(F[7] == 0.0)
+
+
+def test_features_on_bounded_lines():
+    """Along a bounded direction the end nodes take a one-sided difference over
+    one spacing (exact for linear fields) and zero jumps: u = a x, v = b x
+    give div = a and |curl| = |b| at every node, ends included."""
+    import oracle
+    nx, ny, nz = 12, 9, 4
+    hh = (0.2, 0.3, 0.25)
+    K, J, I = np.meshgrid(*[np.arange(n) * s for n, s in zip((nz, ny, nx), hh[::-1])], indexing="ij")
+    xyz = np.stack([I, J, K])
+    case = workloads.Case(name="b", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=np.zeros((5, nz, ny, nx)),
+                          period=(0, 0, nz * hh[2]), h=hh, dt=1e-3, nsteps=1, periodic=(0, 0, 1))
+    met = oracle.metrics(oracle.params_from_case(case), xyz)
+    a, b = 0.2, -0.15
+    rho = 1.0 + 0.1 * J            # density varies along the bounded eta only
+    p = np.full_like(I, 2.0)
+    U = workloads.conserved(1.4, rho, a * I, b * I, 0 * I, p)
+    F = mlp.node_features(1.4, hh, met, U, periodic=(0, 0, 1))
+    c = np.sqrt(1.4 * p / rho)
+    delta = np.cbrt(met[9])
+    assert np.allclose(F[0], delta * a / c, rtol=1e-12)
+    assert np.allclose(F[1], delta * abs(b) / c, rtol=1e-12)
+    jr = F[5]                       # density jump along eta
+    inner = (0.1 * 2 * hh[1]) / (2 * (1.0 + 0.1 * J[:, 1:-1, :]))
+    assert np.allclose(jr[:, 1:-1, :], inner, rtol=1e-12)
+    assert np.all(jr[:, 0, :] == 0.0) and np.all(jr[:, -1, :] == 0.0)
+    assert mlp.window_inside(nx, np.arange(nx), False).tolist() == [False] * 3 + [True] * (nx - 7) + [False] * 4
