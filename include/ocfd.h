@@ -204,18 +204,20 @@ const char* ocfd_kernel_name(int32_t kernel_class);
 /* ---- Learned shock sensor ------------------------------------------------
    A perceptron 32 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid) maps, for interface
    j+1/2 along a direction, four features of each of the 8 nodes j-3..j+4
-   (Delta div u / c, Delta |curl u| / c with Delta = (1/J)^(1/3), and the
-   pressure and density jumps |q+ - q-|/(q+ + q-) along that direction) to the
-   probability that the interface needs WENO.  It replaces the pressure sensor
-   of eq 42-43 in the hybrid scheme: an interface takes WENO7 iff p >= tau.
-   Inference and training run on bf16 matrix cores with FP32 accumulation and
-   FP32 master weights.  Parameters: one flat FP32 array of
-   ocfd_sensor_nparams() values: W1 [32 inputs][32 units], b1 [32],
+   (Delta div u / c and Delta |curl u| / c with Delta = (1/J)^(1/3); the
+   pressure and the density jump, each the normalised second difference
+   |q- - 2q + q+| / (q- + 2q + q+) summed over the three directions and divided
+   by theta1) to the probability that the interface needs WENO.  It replaces
+   the pressure sensor of eq 42-43 in the hybrid scheme: an interface takes
+   WENO7 iff p >= tau.  Inference and training run on bf16 matrix cores with
+   FP32 accumulation and FP32 master weights.  Parameters: one flat FP32 array
+   of ocfd_sensor_nparams() values: W1 [32 inputs][32 units], b1 [32],
    W2 [32][32], b2 [32], w3 [32], b3 [1].
-   On a bounded line the features of an end node use a one-sided difference
-   over one spacing and zero jumps; interfaces whose 8-node window leaves the
-   grid (j < 3 or j > n-5) take the masked WENO5 closure whatever their flag:
-   their learned flag is 1 and they are neither sampled nor audited. */
+   On a bounded line the end nodes take a one-sided velocity difference over
+   one spacing and add no jump term along that line; interfaces whose 8-node
+   window leaves the grid (j < 3 or j > n-5) take the masked WENO5 closure
+   whatever their flag: their learned flag is 1 and they are neither sampled
+   nor audited. */
 int32_t ocfd_sensor_nparams(void);
 int ocfd_sensor_set_params(ocfd_solver* s, const float* params_host);
 int ocfd_sensor_get_params(ocfd_solver* s, float* params_host);

@@ -6,11 +6,12 @@ stencil of flow features to the probability that an interface needs the
 WENO stencil.  This module holds, in plain numpy:
 
 * the node features: Delta * div(u) / c, Delta * |curl u| / c (Delta = (1/J)^(1/3),
-  the cell size), and along each grid direction the pressure and density
-  jumps |q(j+1) - q(j-1)| / (q(j+1) + q(j-1)); velocity derivatives are
-  second-order central differences mapped to x, y, z with the node metrics;
-* the interface input: the four features (two shared, two of the interface's
-  direction) of the 8 nodes j-3 .. j+4 of the interface j+1/2, node-major;
+  the cell size), and the pressure and density jumps: normalised second
+  differences |q- - 2q + q+| / (q- + 2q + q+) summed over the three grid
+  directions, in units of the sensor threshold theta1; velocity derivatives
+  are second-order central differences mapped to x, y, z with the node metrics;
+* the interface input: the four features of the 8 nodes j-3 .. j+4 of the
+  interface j+1/2, node-major;
 * the network 32 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid), its weighted
   binary cross-entropy loss and the exact backward pass in FP64;
 * the same forward/backward with values rounded to bfloat16 at the points
@@ -103,11 +104,12 @@ def loss_and_grad(theta, X, y, w, round_bf16: bool = False):
 
 # ------------------------------------------------------------------ features
 
-def node_features(gamma: float, h, met: np.ndarray, U: np.ndarray, periodic=(1, 1, 1)) -> np.ndarray:
-    """Node features [8, nz, ny, nx]: Delta div/c, Delta |curl|/c, then for
-    xi, eta, zeta the pressure and the density jump.  Along a bounded
-    direction an end node takes a one-sided difference over one spacing and
-    zero jumps."""
+def node_features(gamma: float, h, met: np.ndarray, U: np.ndarray, periodic=(1, 1, 1),
+                  theta1: float = 0.02) -> np.ndarray:
+    """Node features [4, nz, ny, nx]: Delta div/c, Delta |curl|/c, and the
+    pressure and density jumps sum_d |q- - 2q + q+| / (q- + 2q + q+) divided
+    by theta1.  Along a bounded direction an end node takes a one-sided
+    velocity difference over one spacing and adds no jump term."""
     rho = U[0]
     vel = [U[1] / rho, U[2] / rho, U[3] / rho]
     p = (gamma - 1.0) * (U[4] - 0.5 * rho * (vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2))
@@ -116,24 +118,30 @@ def node_features(gamma: float, h, met: np.ndarray, U: np.ndarray, periodic=(1, 
     axis = {0: 2, 1: 1, 2: 0}
 
     def plus_minus(q, d):
-        """q at the next and previous node along d, and the spacing between them."""
+        """q at the next and previous node along d, the spacing between them,
+        and a mask of the end nodes of a bounded line."""
         ax = axis[d]
-        if periodic[d]:
-            return np.roll(q, -1, ax), np.roll(q, 1, ax), np.full(q.shape, 2.0 * h[d])
         n = q.shape[ax]
+        if periodic[d]:
+            return np.roll(q, -1, ax), np.roll(q, 1, ax), np.full(q.shape, 2.0 * h[d]), np.zeros(q.shape, bool)
         idx = np.arange(n)
         ip, im = np.minimum(idx + 1, n - 1), np.maximum(idx - 1, 0)
-        span = ((ip - im) * h[d]).astype(np.float64)
         shape = [1, 1, 1]
         shape[ax] = n
-        return np.take(q, ip, axis=ax), np.take(q, im, axis=ax), np.broadcast_to(span.reshape(shape), q.shape)
+        span = np.broadcast_to(((ip - im) * h[d]).astype(np.float64).reshape(shape), q.shape)
+        end = np.broadcast_to(((idx == 0) | (idx == n - 1)).reshape(shape), q.shape)
+        return np.take(q, ip, axis=ax), np.take(q, im, axis=ax), span, end
 
-    # d(vel_a)/d(xi_d): central (one-sided at a bounded end)
-    dvd = [[None] * 3 for _ in range(3)]
+    dvd = [[None] * 3 for _ in range(3)]      # d(vel_a)/d(xi_d)
+    jp = np.zeros(rho.shape)
+    jr = np.zeros(rho.shape)
     for d in range(3):
         for a in range(3):
-            vp, vm, span = plus_minus(vel[a], d)
+            vp, vm, span, _ = plus_minus(vel[a], d)
             dvd[a][d] = (vp - vm) / span
+        for q, acc in ((p, jp), (rho, jr)):
+            qp, qm, _, end = plus_minus(q, d)
+            acc += np.where(end, 0.0, np.abs(-qm + 2.0 * q - qp) / (qm + 2.0 * q + qp))
     grad = [[sum((met[3 * d + col] / jinv) * dvd[a][d] for d in range(3)) for col in range(3)] for a in range(3)]
     div = grad[0][0] + grad[1][1] + grad[2][2]
     wx = grad[2][1] - grad[1][2]
@@ -141,20 +149,7 @@ def node_features(gamma: float, h, met: np.ndarray, U: np.ndarray, periodic=(1, 
     wz = grad[1][0] - grad[0][1]
     vort = np.sqrt(wx * wx + wy * wy + wz * wz)
     delta = np.cbrt(np.abs(jinv))
-    F = np.zeros((8,) + rho.shape)
-    F[0] = delta * div / c
-    F[1] = delta * vort / c
-    for d in range(3):
-        for k, q in enumerate((p, rho)):
-            qp, qm, _ = plus_minus(q, d)
-            jump = np.abs(qp - qm) / (qp + qm)
-            if not periodic[d]:
-                sl = [slice(None)] * 3
-                for end in (0, -1):
-                    sl[axis[d]] = end
-                    jump[tuple(sl)] = 0.0
-            F[2 + 2 * d + k] = jump
-    return F
+    return np.stack([delta * div / c, delta * vort / c, jp / theta1, jr / theta1])
 
 
 def interface_inputs(F: np.ndarray, d: int, nodes: np.ndarray, periodic: bool = True) -> np.ndarray:
@@ -170,10 +165,8 @@ def interface_inputs(F: np.ndarray, d: int, nodes: np.ndarray, periodic: bool = 
     for t in range(8):
         q = (pos + t - 3) % n if periodic else np.clip(pos + t - 3, 0, n - 1)
         ii, jj, kk = (q if d == 0 else i), (q if d == 1 else j), (q if d == 2 else k)
-        X[:, 4 * t + 0] = F[0][kk, jj, ii]
-        X[:, 4 * t + 1] = F[1][kk, jj, ii]
-        X[:, 4 * t + 2] = F[2 + 2 * d][kk, jj, ii]
-        X[:, 4 * t + 3] = F[3 + 2 * d][kk, jj, ii]
+        for f in range(4):
+            X[:, 4 * t + f] = F[f][kk, jj, ii]
     return X
 
 

@@ -32,7 +32,7 @@ struct ocfd_solver {
   double* red = nullptr;
   const uint8_t* flags = nullptr;
   // learned sensor
-  float* feat = nullptr;          // [8][N] node features
+  float* feat = nullptr;          // [4][N] node features
   uint8_t* lflags = nullptr;      // [3][N] learned flags
   uint8_t* pflags = nullptr;      // [3][N] plain flags (audit, collection)
   float* mlp = nullptr;           // [NPARAM] FP32 master weights
@@ -210,7 +210,7 @@ size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver
   double* th = take(WS_THETA * fb);
   double* partial = take((size_t)nred * OCFD_RED_COUNT * sizeof(double));
   double* red = take(16 * sizeof(double));
-  float* feat = (float*)take(8 * (size_t)N * sizeof(float));
+  float* feat = (float*)take(4 * (size_t)N * sizeof(float));
   uint8_t* lflags = (uint8_t*)take(3 * (size_t)N);
   uint8_t* pflags = (uint8_t*)take(3 * (size_t)N);
   float* mlp = (float*)take(MLP_NPARAM * sizeof(float));

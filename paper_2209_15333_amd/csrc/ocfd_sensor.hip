@@ -67,9 +67,15 @@ hipError_t launch_plain_flags(const Geo& g, double theta1, const double* theta, 
 }
 
 // ---------------------------------------------------------------------------
-// Node features: Delta div(u)/c, Delta |curl u|/c (Delta = (1/J)^(1/3)), and
-// per direction the pressure and density jumps |q+ - q-| / (q+ + q-).
-// Velocity derivatives: second-order central, chain rule with node metrics.
+// Node features [4][N]: Delta div(u)/c and Delta |curl u|/c (Delta = (1/J)^(1/3),
+// the local cell size), and the pressure and density jumps: the normalised
+// second differences summed over the three directions,
+//   sum_d |q- - 2q + q+| / (q- + 2q + q+),
+// divided by the sensor threshold theta1 (so the pressure feature is the plain
+// sensor's node value in units of its threshold).  Velocity derivatives:
+// second-order central differences (one-sided over one spacing at the end of
+// a bounded line), chain rule with the node metrics.  A bounded direction adds
+// no jump term at its end nodes.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_features(const Geo g, const Phys ph, const double* __restrict__ U,
                                                   const double* __restrict__ met, float* __restrict__ feat) {
@@ -77,11 +83,12 @@ __global__ __launch_bounds__(256) void k_features(const Geo g, const Phys ph, co
   if (id >= g.N) return;
   const long long N = g.N;
   const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
+  const double rho = U[id];
+  const double u = U[N + id] / rho, v = U[2 * N + id] / rho, w = U[3 * N + id] / rho;
+  const double p = ph.gm1 * (U[4 * N + id] - 0.5 * rho * (u * u + v * v + w * w));
   double dvd[3][3];  // d(vel_a)/d(xi_d)
-  double jp[3], jr[3];
+  double jp = 0.0, jr = 0.0;
   for (int d = 0; d < 3; ++d) {
-    // neighbours along d; at the end of a bounded line the difference is
-    // one-sided over one spacing and the jumps are zero
     const bool bnd = !g.periodic[d];
     const int qp = bnd ? min(pos[d] + 1, g.n[d] - 1) : wrapn(pos[d] + 1, g.n[d]);
     const int qm = bnd ? max(pos[d] - 1, 0) : wrapn(pos[d] - 1, g.n[d]);
@@ -98,8 +105,10 @@ __global__ __launch_bounds__(256) void k_features(const Geo g, const Phys ph, co
     const double pp = ph.gm1 * (U[4 * N + ip] - 0.5 * rp * (vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2]));
     const double pm = ph.gm1 * (U[4 * N + im] - 0.5 * rm * (vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2]));
     for (int a = 0; a < 3; ++a) dvd[a][d] = (vp[a] - vm[a]) / span;
-    jp[d] = end ? 0.0 : fabs(pp - pm) / (pp + pm);
-    jr[d] = end ? 0.0 : fabs(rp - rm) / (rp + rm);
+    if (!end) {
+      jp += fabs(-pm + 2.0 * p - pp) / (pm + 2.0 * p + pp);
+      jr += fabs(-rm + 2.0 * rho - rp) / (rm + 2.0 * rho + rp);
+    }
   }
   const double jinv = met[9 * N + id];
   double gr[3][3];
@@ -112,17 +121,12 @@ __global__ __launch_bounds__(256) void k_features(const Geo g, const Phys ph, co
   const double div = gr[0][0] + gr[1][1] + gr[2][2];
   const double wx = gr[2][1] - gr[1][2], wy = gr[0][2] - gr[2][0], wz = gr[1][0] - gr[0][1];
   const double vort = sqrt(wx * wx + wy * wy + wz * wz);
-  const double rho = U[id];
-  const double u = U[N + id] / rho, v = U[2 * N + id] / rho, w = U[3 * N + id] / rho;
-  const double p = ph.gm1 * (U[4 * N + id] - 0.5 * rho * (u * u + v * v + w * w));
   const double c = sqrt(ph.gamma * p / rho);
   const double delta = cbrt(fabs(jinv));
   feat[id] = (float)(delta * div / c);
   feat[N + id] = (float)(delta * vort / c);
-  for (int d = 0; d < 3; ++d) {
-    feat[(2 + 2 * d) * N + id] = (float)jp[d];
-    feat[(3 + 2 * d) * N + id] = (float)jr[d];
-  }
+  feat[2 * N + id] = (float)(jp / ph.theta1);
+  feat[3 * N + id] = (float)(jr / ph.theta1);
 }
 
 hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, float* feat,
@@ -204,8 +208,8 @@ __device__ __forceinline__ void mlp_forward(const MlpRegs& R, const v8bf& x, Fwd
 
 __device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + __expf(-z)); }
 
-// Learned flags of every interface: x of interface (d, node) = features
-// (f0, f1, jump_p[d], jump_rho[d]) of the 8 nodes j-3 .. j+4 along d.
+// Learned flags of every interface: x of interface (d, node) = the four
+// features of the 8 nodes j-3 .. j+4 along d, node-major.
 __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const float* __restrict__ feat,
                                                    const float* __restrict__ P, float tau,
                                                    uint8_t* __restrict__ flags) {
@@ -228,10 +232,8 @@ __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const float* __r
       const int t = 2 * gg + tt;
       const int q = g.periodic[d] ? wrapn(pos[d] + t - 3, g.n[d]) : min(max(pos[d] + t - 3, 0), g.n[d] - 1);
       const long long nid = idc + (long long)(q - pos[d]) * g.s[d];
-      x[4 * tt + 0] = (__bf16)feat[nid];
-      x[4 * tt + 1] = (__bf16)feat[N + nid];
-      x[4 * tt + 2] = (__bf16)feat[(2 + 2 * d) * N + nid];
-      x[4 * tt + 3] = (__bf16)feat[(3 + 2 * d) * N + nid];
+#pragma unroll
+      for (int f = 0; f < 4; ++f) x[4 * tt + f] = (__bf16)feat[f * N + nid];
     }
     Fwd F;
     mlp_forward(R, x, F);
@@ -376,7 +378,23 @@ __global__ __launch_bounds__(GT) void k_mlp_grad(const uint16_t* __restrict__ X,
       }
     __syncthreads();
   }
-  // Reduce the lanes' partial sums into red[] in a fixed order: wave by wave.
+  // Bias, output-layer and loss terms: lane (j, gg) holds the sums over its
+  // samples for the units of lane group gg; add the 16 lanes of each group by
+  // butterfly shuffles (every lane takes part; fixed order, so deterministic).
+  for (int m = 0; m < 2; ++m)
+    for (int r = 0; r < 4; ++r)
+      for (int o = 1; o < 16; o <<= 1) {
+        gb1[m][r] += __shfl_xor(gb1[m][r], o);
+        gb2[m][r] += __shfl_xor(gb2[m][r], o);
+        gw3[m][r] += __shfl_xor(gw3[m][r], o);
+      }
+  for (int o = 1; o < 16; o <<= 1) {
+    gb3 += __shfl_xor(gb3, o);
+    loss += __shfl_xor(loss, o);
+  }
+  // Into red[], wave by wave (block barrier between waves).  Within a wave
+  // every lane writes distinct entries: the weight tiles (o, in) differ per
+  // lane, and only lane j = 0 of each group writes that group's units.
   for (int wave = 0; wave < 4; ++wave) {
     if (wv == wave) {
       for (int mo = 0; mo < 2; ++mo)
@@ -386,20 +404,17 @@ __global__ __launch_bounds__(GT) void k_mlp_grad(const uint16_t* __restrict__ X,
             red[MLP_W1 + in * MLP_H + o] += gW1[mo][mi][r];
             red[MLP_W2 + in * MLP_H + o] += gW2[mo][mi][r];
           }
-      // bias and output-layer terms: sum over the 16 samples of each lane group, lane by lane
-      for (int ln = 0; ln < 64; ++ln) {
-        if (l == ln) {
-          for (int m = 0; m < 2; ++m)
-            for (int r = 0; r < 4; ++r) {
-              const int u = 16 * m + 4 * gg + r;
-              red[MLP_B1 + u] += gb1[m][r];
-              red[MLP_B2 + u] += gb2[m][r];
-              red[MLP_W3 + u] += gw3[m][r];
-            }
-          if (gg == 0) {
-            red[MLP_B3] += gb3;
-            red[MLP_NPARAM] += loss;
+      if (j == 0) {
+        for (int m = 0; m < 2; ++m)
+          for (int r = 0; r < 4; ++r) {
+            const int u = 16 * m + 4 * gg + r;
+            red[MLP_B1 + u] += gb1[m][r];
+            red[MLP_B2 + u] += gb2[m][r];
+            red[MLP_W3 + u] += gw3[m][r];
           }
+        if (gg == 0) {
+          red[MLP_B3] += gb3;
+          red[MLP_NPARAM] += loss;
         }
       }
     }
@@ -526,7 +541,7 @@ __global__ __launch_bounds__(CT) void k_collect_write(const Geo g, const uint8_t
         uint16_t xs[32];
         for (int t = 0; t < 8; ++t) {
           const long long nid = id + (long long)(wrapn(pos[d] + t - 3, g.n[d]) - pos[d]) * g.s[d];  // window inside
-          const float f[4] = {feat[nid], feat[N + nid], feat[(2 + 2 * d) * N + nid], feat[(3 + 2 * d) * N + nid]};
+          const float f[4] = {feat[nid], feat[N + nid], feat[2 * N + nid], feat[3 * N + nid]};
           for (int q = 0; q < 4; ++q) {
             const __bf16 bv = (__bf16)f[q];
             __builtin_memcpy(&xs[4 * t + q], &bv, 2);

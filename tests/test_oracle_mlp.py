@@ -37,17 +37,17 @@ def test_bf16_rounding_definition():
     assert np.all((r.astype(np.float32).view(np.uint32) & 0xFFFF) == 0)
 
 
-def test_features_closed_forms():
-    """Uniform flow: zero divergence and vorticity, zero jumps.  A linear
-    shear u = a y: |curl| = a, div = 0.  A density step along x: jump
-    (r-1)/(r+1) at the two nodes beside it."""
+def test_features_closed_forms(orc):
+    """Uniform flow: zero divergence, vorticity and jumps.  A shear u = a sin y:
+    |curl| from the second-order difference of sin.  A density step along x:
+    the normalised second differences beside it.  The pressure feature times
+    theta1 is the plain sensor's node value (eq 42), computed independently by
+    the C oracle."""
     case = workloads.uniform_flow((12, 10, 8), amplitude_frac=0.0)
-    import oracle
-    P = oracle.params_from_case(case)
-    met = oracle.metrics(P, case.xyz)
+    P = orc.params_from_case(case)
+    met = orc.metrics(P, case.xyz)
     F = mlp.node_features(case.gamma, case.h, met, case.U0)
-    assert np.abs(F).max() < 1e-12
-    # shear: u = a sin(y) has curl_z = -a cos(y); second-order central difference
+    assert F.shape[0] == 4 and np.abs(F).max() < 1e-12
     x, y, z = case.xyz
     a = 0.3
     rho = np.ones_like(x)
@@ -62,35 +62,49 @@ def test_features_closed_forms():
     r = 3.0
     rho = np.where(np.arange(12)[None, None, :] >= 6, r, 1.0) * np.ones_like(x)
     U = workloads.conserved(1.4, rho, 0 * x, 0 * x, 0 * x, p)
-    F = mlp.node_features(1.4, case.h, met, U)
-    assert F[3][0, 0, 5] == pytest.approx((r - 1) / (r + 1))
-    assert F[3][0, 0, 6] == pytest.approx((r - 1) / (r + 1))
-    assert F[3][0, 0, 3] == 0.0 and np.all(F[5] == 0.0) and np.all(F[7] == 0.0)
+    F = mlp.node_features(1.4, case.h, met, U, theta1=0.02)
+    assert F[3][0, 0, 5] == pytest.approx((r - 1) / (r + 3) / 0.02, rel=1e-14)
+    assert F[3][0, 0, 6] == pytest.approx((r - 1) / (3 * r + 1) / 0.02, rel=1e-14)
+    assert F[3][0, 0, 3] == 0.0 and np.all(F[2] == 0.0)
+    # pressure feature = plain sensor / theta1, on a noisy state
+    rng = np.random.default_rng(4)
+    U = case.U0 * (1.0 + 0.05 * rng.standard_normal(case.U0.shape))
+    theta, _ = orc.sensor(P, U)
+    F = mlp.node_features(1.4, case.h, met, U, theta1=case.theta1)
+    assert np.allclose(F[2] * case.theta1, theta, rtol=1e-13, atol=1e-16)
 
 
-def test_features_on_bounded_lines():
+def test_features_on_bounded_lines(orc):
     """Along a bounded direction the end nodes take a one-sided difference over
-    one spacing (exact for linear fields) and zero jumps: u = a x, v = b x
-    give div = a and |curl| = |b| at every node, ends included."""
-    import oracle
+    one spacing (exact for linear fields) and add no jump term: u = a x,
+    v = b x give div = a and |curl| = |b| at every node, ends included; a
+    density quadratic in y has a known normalised second difference inside
+    and none at the eta ends; the pressure feature still equals the plain
+    sensor of the C oracle."""
     nx, ny, nz = 12, 9, 4
     hh = (0.2, 0.3, 0.25)
     K, J, I = np.meshgrid(*[np.arange(n) * s for n, s in zip((nz, ny, nx), hh[::-1])], indexing="ij")
     xyz = np.stack([I, J, K])
     case = workloads.Case(name="b", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=np.zeros((5, nz, ny, nx)),
                           period=(0, 0, nz * hh[2]), h=hh, dt=1e-3, nsteps=1, periodic=(0, 0, 1))
-    met = oracle.metrics(oracle.params_from_case(case), xyz)
+    P = orc.params_from_case(case)
+    met = orc.metrics(P, xyz)
     a, b = 0.2, -0.15
-    rho = 1.0 + 0.1 * J            # density varies along the bounded eta only
+    rho = 1.0 + 0.1 * J * J
     p = np.full_like(I, 2.0)
     U = workloads.conserved(1.4, rho, a * I, b * I, 0 * I, p)
-    F = mlp.node_features(1.4, hh, met, U, periodic=(0, 0, 1))
+    F = mlp.node_features(1.4, hh, met, U, periodic=(0, 0, 1), theta1=0.02)
     c = np.sqrt(1.4 * p / rho)
     delta = np.cbrt(met[9])
     assert np.allclose(F[0], delta * a / c, rtol=1e-12)
     assert np.allclose(F[1], delta * abs(b) / c, rtol=1e-12)
-    jr = F[5]                       # density jump along eta
-    inner = (0.1 * 2 * hh[1]) / (2 * (1.0 + 0.1 * J[:, 1:-1, :]))
-    assert np.allclose(jr[:, 1:-1, :], inner, rtol=1e-12)
-    assert np.all(jr[:, 0, :] == 0.0) and np.all(jr[:, -1, :] == 0.0)
+    y = J[:, 1:-1, :]
+    inner = 0.2 * hh[1] ** 2 / (4.0 * (1.0 + 0.1 * y * y) + 0.2 * hh[1] ** 2) / 0.02
+    assert np.allclose(F[3][:, 1:-1, :], inner, rtol=1e-10)
+    assert np.all(F[3][:, 0, :] == 0.0) and np.all(F[3][:, -1, :] == 0.0)
+    rng = np.random.default_rng(6)
+    U = U * (1.0 + 0.05 * rng.standard_normal(U.shape))
+    theta, _ = orc.sensor(P, U)
+    F = mlp.node_features(1.4, hh, met, U, periodic=(0, 0, 1), theta1=case.theta1)
+    assert np.allclose(F[2] * case.theta1, theta, rtol=1e-13, atol=1e-16)
     assert mlp.window_inside(nx, np.arange(nx), False).tolist() == [False] * 3 + [True] * (nx - 7) + [False] * 4
