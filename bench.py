@@ -66,6 +66,158 @@ def cpu_baseline(cases, threads: int):
                       f"{total_t:.1f} s"}
 
 
+def _log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _rel_l2(torch, a, b):
+    """Per-field relative L2 of a against b ([5, ...] device tensors); the
+    momentum components share the norm of the momentum vector."""
+    out = []
+    mom = float(torch.linalg.vector_norm(b[1:4]))
+    for m in range(5):
+        d = float(torch.linalg.vector_norm(a[m] - b[m]))
+        n = mom if 1 <= m <= 3 else float(torch.linalg.vector_norm(b[m]))
+        out.append(d / n if n > 0 else d)
+    return out
+
+
+def _timed_run(torch, pk, case, U, substeps, warmup=2, setup=None):
+    """A fresh solver for `case` started from state U: `warmup` substeps, then
+    the state is set again and `substeps` substeps are timed.  Returns
+    (Gpt-substeps/s, final state, solver)."""
+    s = pk.Solver(pk.params_from(case))
+    s.set_grid(torch.from_numpy(case.xyz).cuda())
+    if case.inflow is not None:
+        s.set_inflow(torch.from_numpy(case.inflow).cuda())
+    if setup:
+        setup(s)
+    s.set_state(U)
+    s.advance(warmup, case.dt)
+    s.set_state(U)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.advance(substeps, case.dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    return case.N * substeps / el / 1e9, s.state(), s
+
+
+def form_hit_learned(torch, pk, n, develop, every, substeps):
+    """Decaying isotropic turbulence (hybrid WENO7 / C8): `develop` substeps of
+    the plain FP64 hybrid with samples of the plain sensor's flags every
+    `every` substeps, GPU training and calibration of the perceptron, then
+    `substeps` substeps from the developed state with (i) WENO7 everywhere,
+    FP64, (ii) the plain FP64 hybrid, (iii) FP32 reconstruction + learned
+    sensor (re-evaluated every substep, audited every 50), (iv) the same with
+    the network re-evaluated once per Runge-Kutta step."""
+    import dataclasses
+    import workloads
+    t_all = time.perf_counter()
+    case = workloads.isotropic_turbulence(n)
+    _log(f"hit{n}: inputs ready ({time.perf_counter() - t_all:.0f} s)")
+    s = pk.Solver(pk.params_from(case))
+    s.set_grid(torch.from_numpy(case.xyz).cuda())
+    s.set_state(torch.from_numpy(case.U0).cuda())
+    cap = 8_000_000
+    buf = torch.empty(pk.ocfd_sensor_sample_bytes(cap), dtype=torch.uint8, device="cuda")
+    pk.ocfd_sensor_bind_samples(s.h, buf)
+    t0 = time.perf_counter()
+    total = 0
+    for k in range(develop // every):
+        s.advance(every, case.dt)
+        total = pk.ocfd_sensor_collect(s.h, 5000 + k, 0.05, 0.001)
+    torch.cuda.synchronize()
+    t_dev = time.perf_counter() - t0
+    _log(f"hit{n}: developed {develop} substeps in {t_dev:.1f} s, {total} samples")
+    pk.ocfd_sensor_set_params(s.h, workloads.sensor_initial_weights(11))
+    t0 = time.perf_counter()
+    stats = pk.ocfd_sensor_train(s.h, 4, 2048, 3e-3, 7, 0.1)
+    cal = pk.ocfd_sensor_calibrate(s.h, 0.1, 0.5)
+    t_train = time.perf_counter() - t0
+    params = pk.ocfd_sensor_get_params(s.h)
+    tau = cal[0]
+    _log(f"hit{n}: trained in {t_train:.1f} s, loss {stats[0]:.4f} -> {stats[1]:.4f}, tau {tau:.3g}, "
+         f"held-out recall {cal[1]}, false-positive rate {cal[2]:.4f}")
+    U = s.state()
+    del buf
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+
+    def learned(sv):
+        pk.ocfd_sensor_set_params(sv.h, params)
+        pk.ocfd_sensor_set_threshold(sv.h, tau)
+
+    res = {}
+    ref = None
+    for name, kw in (("weno7_fp64", dict(scheme="weno7")),
+                     ("hybrid_plain_fp64", dict()),
+                     ("hybrid_plain_fp32", dict(precision="mixed")),
+                     ("hybrid_learned_fp32", dict(precision="mixed", sensor="learned", sensor_every=1,
+                                                  audit_every=50)),
+                     ("hybrid_learned_fp32_every3", dict(precision="mixed", sensor="learned", sensor_every=3,
+                                                         audit_every=51))):
+        c = dataclasses.replace(case, **kw)
+        rate, Uf, sv = _timed_run(torch, pk, c, U, substeps, setup=learned if c.sensor == "learned" else None)
+        entry = {"gpt_substeps_per_s": round(rate, 4)}
+        if name == "hybrid_plain_fp64":
+            ref = Uf
+        elif ref is not None:
+            entry["rel_l2_vs_plain_fp64_hybrid"] = [float(f"{e:.3e}") for e in _rel_l2(torch, Uf, ref)]
+        if c.sensor == "learned":
+            a = pk.ocfd_sensor_audit(sv.h)
+            entry["audit"] = {"runs": int(a[0]), "plain_weno_frac": round(a[2] / max(a[1], 1), 5),
+                              "learned_weno_frac": round(a[3] / max(a[1], 1), 5),
+                              "missed_frac_of_plain_weno": round(a[4] / max(a[2], 1), 6),
+                              "mismatch_rate": round(a[5] / max(a[1], 1), 6)}
+        res[name] = entry
+        _log(f"hit{n}: {name}: {entry}")
+        sv.close()
+        del sv, Uf
+        torch.cuda.empty_cache()
+    base = res["weno7_fp64"]["gpt_substeps_per_s"]
+    plain = res["hybrid_plain_fp64"]["gpt_substeps_per_s"]
+    for k in res:
+        res[k]["speedup_vs_weno7_fp64"] = round(res[k]["gpt_substeps_per_s"] / base, 3)
+        res[k]["speedup_vs_hybrid_plain_fp64"] = round(res[k]["gpt_substeps_per_s"] / plain, 3)
+    return {"workload": f"decaying isotropic turbulence {n}^3 (k0 4, Mt 0.6, Re_lambda 100), C6 viscous, "
+                        f"state after {develop} plain FP64 hybrid substeps; {substeps} timed substeps per form",
+            "training": {"samples": total, "epochs": 4, "batch": 2048, "loss_first_last": [round(stats[0], 5),
+                         round(stats[1], 5)], "tau": tau, "heldout_recall": cal[1],
+                         "heldout_false_positive_rate": round(cal[2], 5), "train_s": round(t_train, 2)},
+            "forms": res}
+
+
+def form_ramp_mixed(torch, pk, shape, substeps):
+    """Compression ramp: WENO7 FP64 against the FP32 split/reconstruction form
+    from the same inflow state, `substeps` substeps each."""
+    import dataclasses
+    import workloads
+    case = workloads.compression_ramp(shape=shape)
+    U = torch.from_numpy(case.U0).cuda()
+    res = {}
+    ref = None
+    for name, prec in (("weno7_fp64", "fp64"), ("weno7_fp32", "mixed")):
+        c = dataclasses.replace(case, precision=prec)
+        rate, Uf, sv = _timed_run(torch, pk, c, U, substeps)
+        entry = {"gpt_substeps_per_s": round(rate, 4)}
+        if ref is None:
+            ref = Uf
+        else:
+            entry["rel_l2_vs_fp64"] = [float(f"{e:.3e}") for e in _rel_l2(torch, Uf, ref)]
+            entry["speedup_vs_fp64"] = round(rate / res["weno7_fp64"]["gpt_substeps_per_s"], 3)
+        res[name] = entry
+        _log(f"ramp: {name}: {entry}")
+        sv.close()
+        del sv
+        torch.cuda.empty_cache()
+    nx, ny, nz = shape
+    return {"workload": f"Mach 2.9 24-degree compression ramp {nx}x{ny}x{nz}, inflow/outflow/isothermal wall "
+                        f"Tw 2.84/periodic span, C6 viscous, Re_delta 5e4; {substeps} substeps from the inflow state",
+            "forms": res}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -76,6 +228,12 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="fp64: the plain path; mixed: FP32 split/reconstruction, FP64 difference and RK")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="skip the isotropic-turbulence and compression-ramp form comparisons")
+    ap.add_argument("--hit-n", type=int, default=512)
+    ap.add_argument("--hit-develop", type=int, default=500)
+    ap.add_argument("--form-substeps", type=int, default=100)
+    ap.add_argument("--ramp-shape", type=str, default="1024,160,128")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one plain 512 MiB device-to-device copy first, as the reference dispatch "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
@@ -158,6 +316,17 @@ def main():
             "avg_launch_us": {k: round(v[1] * 1e3, 1) for k, v in flops_launch.items()},
             "flops_per_launch": {k: v[0] for k, v in flops_launch.items()}}
 
+    for s in solvers:
+        s.close()
+    del solvers
+    torch.cuda.empty_cache()
+    forms = None
+    if not args.no_forms:
+        forms = {"isotropic_turbulence": form_hit_learned(torch, pk, args.hit_n, args.hit_develop, 50,
+                                                          args.form_substeps),
+                 "compression_ramp": form_ramp_mixed(torch, pk, tuple(int(v) for v in args.ramp_shape.split(",")),
+                                                     args.form_substeps)}
+
     cpu = None
     if not args.no_cpu_baseline:
         print(f"[bench] oracle baseline on {args.cpu_threads} threads", file=sys.stderr, flush=True)
@@ -181,6 +350,7 @@ def main():
                    "points_per_step": sum(c.N for c in cases), "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "forms": forms,
     }
     print(json.dumps(out), flush=True)
 

@@ -338,6 +338,7 @@ class Solver:
         if getattr(self, "h", None):
             ocfd_destroy(self.h)
             self.h = None
+        self.ws = None
 
     def __del__(self):
         try:

@@ -367,3 +367,15 @@ def bounded_box(shape: Tuple[int, int, int] = (36, 20, 18), seed: int = 22095, M
     return Case(name=f"box{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=U0, period=(0.0, 0.0, 0.0),
                 h=(1.0, 1.0, 1.0), dt=0.05, nsteps=10, periodic=(0, 0, 0), bc=(1, 2, 3, 2, 2, 2), gamma=g, Re=Re,
                 Ma=Ma, Pr=0.72, Tw=1.0, inflow=inflow)
+
+
+def sensor_initial_weights(seed: int = 0) -> np.ndarray:
+    """Initial weights of the 32-32-32-1 shock-sensor perceptron as one flat
+    array W1 [32 in][32 out], b1, W2 [32][32], b2, w3 [32], b3: He-uniform
+    hidden layers, an output layer ten times smaller, zero biases (PCG64(seed)
+    draws in that order)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    W1 = rng.uniform(-1, 1, (32, 32)) * math.sqrt(6.0 / 32)
+    W2 = rng.uniform(-1, 1, (32, 32)) * math.sqrt(6.0 / 32)
+    w3 = rng.uniform(-1, 1, 32) * math.sqrt(6.0 / 32) * 0.1
+    return np.concatenate([W1.ravel(), np.zeros(32), W2.ravel(), np.zeros(32), w3, np.zeros(1)])
