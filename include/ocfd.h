@@ -128,7 +128,7 @@ int ocfd_params_default(ocfd_params* p);
 /* Bytes of device workspace a solver with these parameters needs (0 if the
    parameters are invalid).  The workspace holds the metrics [10][N], three
    state buffers [5][N], the right-hand side [5][N], the primitive variables
-   [4][N] and the viscous fluxes [12][N], all FP64, the sensor and
+   [5][N] (u, v, w, T, p) and the viscous fluxes [12][N], all FP64, the sensor and
    learned-sensor buffers, the inflow face [5][face] and small reduction
    buffers. */
 size_t ocfd_workspace_bytes(const ocfd_params* p);

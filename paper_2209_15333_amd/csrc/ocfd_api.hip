@@ -83,7 +83,7 @@ int hip_fail(ocfd_solver* s, hipError_t e, const char* what) {
 }
 
 // Field-region sizes of the workspace, in doubles per node.
-constexpr int WS_MET = 10, WS_STATE = 5, WS_RHS = 5, WS_PRIM = 4, WS_FV = 12, WS_THETA = 1;
+constexpr int WS_MET = 10, WS_STATE = 5, WS_RHS = 5, WS_PRIM = 5, WS_FV = 12, WS_THETA = 1;
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -282,6 +282,15 @@ bool ready(ocfd_solver* s, int* rc) {
   return true;
 }
 
+// Node sensor theta of U into s->theta.  prims_fresh: W already holds the
+// primitives of U (p is its fifth field); otherwise p is computed into it.
+int plain_theta(ocfd_solver* s, const double* U, bool prims_fresh) {
+  double* P = s->W + 4 * s->g.N;
+  hipError_t e = prims_fresh ? hipSuccess : launch_pressure(s->g, s->ph, U, P, s->st);
+  if (e == hipSuccess) e = launch_sensor(s->g, P, s->theta, s->st);
+  return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "sensor kernels");
+}
+
 // Evaluate the right-hand side of U_cur.  mode MODE_RK writes the next stage
 // into out; MODE_DUDT writes dU/dt into out.
 // Flags of the learned sensor for this substep: the network is re-evaluated
@@ -300,8 +309,9 @@ int learned_flags(ocfd_solver* s, const double* Ucur, bool count_substep) {
     if (e != hipSuccess) return hip_fail(s, e, "learned sensor kernels");
   }
   if (count_substep && s->p.audit_every > 0 && k % s->p.audit_every == 0) {
-    e = launch_sensor(s->g, s->ph, Ucur, s->theta, s->st);
-    if (e == hipSuccess) e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
+    int rc = plain_theta(s, Ucur, false);
+    if (rc) return rc;
+    e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
     if (e == hipSuccess) e = launch_flag_stats(s->g, s->pflags, s->lflags, s->cnt, COUNT_BLOCKS, s->st);
     std::vector<unsigned long long> c(COUNT_BLOCKS * 4);
     if (e == hipSuccess)
@@ -353,8 +363,11 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
     flags = s->lflags;
   } else if (hyb && !flags) {
     Timed tm(s, OCFD_K_OTHER);
-    e = launch_sensor(s->g, s->ph, Ucur, s->theta, s->st);
-    if (e != hipSuccess) return hip_fail(s, e, "sensor kernel");
+    int rc = plain_theta(s, Ucur, visc);
+    if (rc) return rc;
+    e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
+    if (e != hipSuccess) return hip_fail(s, e, "sensor flags kernel");
+    flags = s->pflags;
   }
   SweepArgs A;
   memset(&A, 0, sizeof(A));
@@ -363,7 +376,6 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
   A.U = Ucur;
   A.met = s->met;
   A.Fv = visc ? s->Fv : nullptr;
-  A.theta = s->theta;
   A.flags = flags;
   A.rhs = s->rhs;
   A.Un = Un;
@@ -374,10 +386,14 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
   A.hybrid = hyb ? 1 : 0;
   A.lowdiss = s->p.lowdiss;
   A.mixed = s->p.precision == OCFD_PREC_MIXED ? 1 : 0;
-  for (int d = 0; d < 3; ++d) {
+  // zeta first (stores the sum), eta accumulates, xi last: the last sweep
+  // reads and writes the most (sum, U^n, 1/J, output), and along xi those
+  // accesses are contiguous.
+  for (int step = 0; step < 3; ++step) {
+    const int d = 2 - step;
     A.inviscid = (parts >> d) & 1;
     A.viscous = visc ? 1 : 0;
-    const int m = d == 0 ? MODE_SET : (d == 1 ? MODE_ADD : mode);
+    const int m = step == 0 ? MODE_SET : (step == 1 ? MODE_ADD : mode);
     Timed tm(s, OCFD_K_SWEEP_XI + d);
     e = launch_sweep(d, m, A, s->st);
     if (e != hipSuccess) return hip_fail(s, e, "sweep kernel");
@@ -688,8 +704,9 @@ int ocfd_sensor_flags(ocfd_solver* s, const double* U, int32_t which, uint8_t* f
   if (!s->have_grid) return fail(s, OCFD_ERR_STATE, "no grid set");
   hipError_t e;
   if (which == OCFD_SENSOR_PLAIN) {
-    e = launch_sensor(s->g, s->ph, U, s->theta, s->st);
-    if (e == hipSuccess) e = launch_plain_flags(s->g, s->ph.theta1, s->theta, flags, s->st);
+    rc = plain_theta(s, U, false);
+    if (rc) return rc;
+    e = launch_plain_flags(s->g, s->ph.theta1, s->theta, flags, s->st);
   } else if (which == OCFD_SENSOR_LEARNED) {
     if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "no network parameters set");
     e = launch_features(s->g, s->ph, U, s->met, s->feat, s->st);
@@ -732,8 +749,9 @@ int ocfd_sensor_collect(ocfd_solver* s, uint64_t seed, double keep_weno, double 
   const uint32_t tp = (uint32_t)std::min(4294967295.0, keep_weno * 4294967296.0);
   const uint32_t tl = (uint32_t)std::min(4294967295.0, keep_low * 4294967296.0);
   const double* U = s->Ub[s->stage];
-  hipError_t e = launch_sensor(s->g, s->ph, U, s->theta, s->st);
-  if (e == hipSuccess) e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
+  rc = plain_theta(s, U, false);
+  if (rc) return rc;
+  hipError_t e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
   if (e == hipSuccess) e = launch_features(s->g, s->ph, U, s->met, s->feat, s->st);
   if (e == hipSuccess) e = launch_collect_count(s->g, s->pflags, seed, tp, tl, s->cnt, COUNT_BLOCKS, s->st);
   std::vector<unsigned long long> c(COUNT_BLOCKS);

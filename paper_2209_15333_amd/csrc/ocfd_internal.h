@@ -56,8 +56,7 @@ struct SweepArgs {
   const double* U;       // state the right-hand side is evaluated from
   const double* met;     // [10][N]
   const double* Fv;      // [12][N] viscous fluxes (or null when inviscid-only / Euler)
-  const double* theta;   // [N] node sensor (hybrid, no forced flags)
-  const uint8_t* flags;  // [3][N] forced interface flags (hybrid) or null
+  const uint8_t* flags;  // [3][N] interface flags of the hybrid scheme (0: low-dissipation stencil)
   double* rhs;           // [5][N]
   const double* Un;      // RK: state at the start of the step
   double* out;           // RK: new state; DUDT: dU/dt
@@ -71,13 +70,20 @@ struct SweepArgs {
 
 // Kernel launch entry points (ocfd_kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_sweep(int dir, int mode, const SweepArgs& a, hipStream_t st);
+// One direction's sweep (instantiated in ocfd_sweep_{xi,eta,zeta}.hip).
+template <int DIR>
+hipError_t launch_sweep_d(int mode, const SweepArgs& a, hipStream_t st);
+// W [5][N] = u, v, w, T, p of U.
 hipError_t launch_prim(const Geo& g, const Phys& ph, const double* U, double* W, hipStream_t st);
 hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const double* met, double* Fv,
                             hipStream_t st);
 // One face (d, side) of a bounded direction set by boundary kind `kind`.
 hipError_t launch_bc(const Geo& g, const Phys& ph, double* U, int d, int side, int kind, double Tw,
                      const double* inflow, hipStream_t st);
-hipError_t launch_sensor(const Geo& g, const Phys& ph, const double* U, double* theta, hipStream_t st);
+// theta [N] of eq 42 from node pressures P [N].
+hipError_t launch_sensor(const Geo& g, const double* P, double* theta, hipStream_t st);
+// P [N] = pressure of U.
+hipError_t launch_pressure(const Geo& g, const Phys& ph, const double* U, double* P, hipStream_t st);
 hipError_t launch_metric_inner(const Geo& g, const Phys& ph, const double* xyz, double* inner, hipStream_t st);
 hipError_t launch_metric_outer(const Geo& g, const Phys& ph, const double* xyz, const double* inner, double* met,
                                hipStream_t st);

@@ -47,22 +47,30 @@ __device__ __forceinline__ v4f mfma16(const v4bf& a, const v4bf& b, const v4f& c
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_plain_flags(const Geo g, double theta1, const double* __restrict__ theta,
                                                      uint8_t* __restrict__ flags) {
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= g.N) return;
-  const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
+  const int pos[3] = {(int)(blockIdx.x * 64 + threadIdx.x), (int)(blockIdx.y * 4 + threadIdx.y), (int)blockIdx.z};
+  if (pos[0] >= g.n[0] || pos[1] >= g.n[1]) return;
+  const long long id = pos[0] + g.s[1] * pos[1] + g.s[2] * pos[2];
+#pragma unroll
   for (int d = 0; d < 3; ++d) {
+    const int n = g.n[d];
     double mx = 0.0;
+#pragma unroll
     for (int o = -3; o <= 4; ++o) {
-      const int q = pos[d] + o;
-      if (!g.periodic[d] && (q < 0 || q >= g.n[d])) continue;   // window clipped at a bounded end
-      mx = fmax(mx, theta[id + (long long)(wrapn(q, g.n[d]) - pos[d]) * g.s[d]]);
+      int q = pos[d] + o;
+      if (g.periodic[d]) {
+        q = n >= 8 ? q + (q < 0 ? n : 0) - (q >= n ? n : 0) : wrapn(q, n);
+      } else if (q < 0 || q >= n) {
+        continue;   // window clipped at a bounded end
+      }
+      mx = fmax(mx, theta[id + (long long)(q - pos[d]) * g.s[d]]);
     }
     flags[d * g.N + id] = mx <= theta1 ? 0 : 1;
   }
 }
 
 hipError_t launch_plain_flags(const Geo& g, double theta1, const double* theta, uint8_t* flags, hipStream_t st) {
-  hipLaunchKernelGGL(k_plain_flags, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, theta1, theta, flags);
+  const dim3 grid((unsigned)((g.n[0] + 63) / 64), (unsigned)((g.n[1] + 3) / 4), (unsigned)g.n[2]);
+  hipLaunchKernelGGL(k_plain_flags, grid, dim3(64, 4), 0, st, g, theta1, theta, flags);
   return hipGetLastError();
 }
 

@@ -1,0 +1,323 @@
+// Directional sweep kernel of the ocfd library (one Runge-Kutta substep of
+// the curvilinear compressible Navier-Stokes solver of Dang et al.,
+// arXiv:2209.15333, Section 2).  Included by one translation unit per
+// direction, each instantiating launch_sweep_d for its direction.
+#pragma once
+
+#include "ocfd_device.h"
+
+namespace ocfd {
+
+// ---------------------------------------------------------------------------
+// Directional sweep
+// ---------------------------------------------------------------------------
+//
+// A workgroup owns SW_W neighbouring grid lines along direction DIR and
+// marches along them in chunks of SW_S nodes.  Per chunk:
+//   1. each thread loads one node, recovers the primitives and splits the
+//      flux (eq 19-30) into an LDS ring of split fluxes (node m -> slot m%32);
+//   2. each thread reconstructs one interface j+1/2 (WENO7, or the hybrid's
+//      low-dissipation stencil) from the ring;
+//   3. each thread forms one node's flux difference (F(j+1/2) - F(j-1/2))/h,
+//      adds the sixth-order derivative of the viscous flux of this direction
+//      and applies the mode (store, accumulate, Runge-Kutta update, dU/dt).
+// The flux of the chunk's last interface is carried to the next chunk, so
+// every interface is reconstructed exactly once, and the first node of a
+// periodic line is finished after the last chunk with the wrapped flux.
+// BND selects the boundary code compiled in: 0 all three directions
+// periodic; 1 this direction periodic, another bounded (faces of the other
+// directions take dU/dt = 0 in the last sweep); 2 this direction bounded
+// (masked WENO5 at interfaces whose stencil leaves the line, reduced-order
+// viscous derivative toward the ends, no wrap).  Periodic lines wrap node
+// positions at load time.  The hybrid scheme reads one flag byte per
+// interface (0: low-dissipation stencil), computed beforehand by a sensor.
+
+constexpr int SW_W = 16;
+constexpr int SW_S = 16;
+constexpr int SW_T = SW_W * SW_S;
+constexpr int RING = 32;
+
+template <int DIR, int MODE, bool HYB, typename R, int BND>
+__global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
+  constexpr int CD = (DIR == 0) ? 1 : 0;  // direction across the lines of the group
+  constexpr int OD = (DIR == 2) ? 1 : 2;  // remaining direction
+  constexpr int NVAL = 10;                // f+ (5), f- (5)
+  constexpr bool per = BND != 2;          // this direction periodic
+  constexpr bool anyb = BND != 0;         // some direction bounded
+  constexpr int SLOT = NVAL * SW_W + 1;   // padded against bank conflicts
+  constexpr int FHS = 5 * SW_W + 1;
+  __shared__ R ring[RING * SLOT];
+  __shared__ double fh[(SW_S + 1) * FHS];  // fh[0]: carried flux; fh[s+1]: interface j0+s
+  __shared__ double fh0[FHS];             // flux at 1/2, for node 0 of a periodic line
+  __shared__ int wl_n;                    // hybrid: WENO work list of this chunk
+  __shared__ short wl[SW_T];
+
+  const int n = A.g.n[DIR];
+  const int ncol = A.g.n[CD];
+  const long long sd = A.g.s[DIR];
+  const long long sc = A.g.s[CD];
+  const long long N = A.g.N;
+  const int col0 = blockIdx.x * SW_W;
+  const long long base = (long long)blockIdx.y * A.g.s[OD] + (long long)col0 * sc;
+  const int t = threadIdx.x;
+  // Global-facing mapping: consecutive threads walk the contiguous index.
+  const int gs = (DIR == 0) ? (t & (SW_S - 1)) : (t / SW_W);
+  const int gc = (DIR == 0) ? (t / SW_S) : (t & (SW_W - 1));
+  // LDS-facing mapping for the reconstruction: lines fastest.
+  const int rs = t / SW_W;
+  const int rc = t & (SW_W - 1);
+  const bool gcol_ok = col0 + gc < ncol;
+  const bool rcol_ok = col0 + rc < ncol;
+  const double ih = A.ph.ih[DIR];
+  const R eps = (R)A.ph.eps;
+
+  // Raw inputs of one node: conserved variables and row DIR of the metrics / J.
+  // Fetched one chunk ahead so the loads overlap the reconstruction of the
+  // current chunk.
+  struct NodeIn {
+    double U[5];
+    double a[3];
+  };
+  auto fetch = [&](int m, int col) {
+    NodeIn r;
+    const int jm = !per ? m : (n >= 8 ? wrap1(m, n) : wrap(m, n));
+    const long long id = base + (long long)col * sc + (long long)jm * sd;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r.U[q] = A.U[q * N + id];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) r.a[q] = A.met[(3 * DIR + q) * N + id];
+    return r;
+  };
+  // Primitive recovery and Steger-Warming split of node m into the ring.
+  auto split_store = [&](int m, int col, const NodeIn& in) {
+    const double rho = in.U[0];
+    const double ir = 1.0 / rho;
+    const double u = in.U[1] * ir;
+    const double v = in.U[2] * ir;
+    const double w = in.U[3] * ir;
+    const double p = A.ph.gm1 * (in.U[4] - 0.5 * rho * (u * u + v * v + w * w));
+    R fp[5], fm[5];
+    sw_split<R>(A.ph, (R)rho, (R)ir, (R)u, (R)v, (R)w, (R)p, (R)in.a[0], (R)in.a[1], (R)in.a[2], fp, fm);
+    R* slot = ring + (m & (RING - 1)) * SLOT + col;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      slot[q * SW_W] = fp[q];
+      slot[(5 + q) * SW_W] = fm[q];
+    }
+  };
+
+  // Output of node j of line col from its two interface fluxes (inv: this
+  // node has both interfaces along DIR, i.e. it is not an end of a
+  // non-periodic line).
+  auto emit = [&](int j, int col, const double* Fr, const double* Fl, bool inv) {
+    const long long id = base + (long long)col * sc + (long long)j * sd;
+    double r[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) r[q] = (A.inviscid && inv) ? -(Fr[q * SW_W] - Fl[q * SW_W]) * ih : 0.0;
+    if (A.viscous) {
+      if (per) {
+        // offsets of the six neighbours along the line (wrapped at the seam)
+        auto off = [&](int k) {
+          const int p = j + k;
+          return (long long)((n >= 8 ? wrap1(p, n) : wrap(p, n)) - j) * sd;
+        };
+        const long long o1p = off(1), o1m = off(-1), o2p = off(2), o2m = off(-2), o3p = off(3), o3m = off(-3);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double* F = A.Fv + (long long)(4 * DIR + q) * N + id;
+          const double d = 0.75 * (F[o1p] - F[o1m]) - 0.15 * (F[o2p] - F[o2m]) + (1.0 / 60.0) * (F[o3p] - F[o3m]);
+          r[q + 1] += d * ih;
+        }
+      } else if (inv) {
+        // sixth order inside, then fourth and second order toward the ends (Sec. 2.3)
+        const int dist = min(j, n - 1 - j);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const double* F = A.Fv + (long long)(4 * DIR + q) * N + id;
+          double d;
+          if (dist == 1)
+            d = 0.5 * (F[sd] - F[-sd]);
+          else if (dist == 2)
+            d = (2.0 / 3.0) * (F[sd] - F[-sd]) - (1.0 / 12.0) * (F[2 * sd] - F[-2 * sd]);
+          else
+            d = 0.75 * (F[sd] - F[-sd]) - 0.15 * (F[2 * sd] - F[-2 * sd]) + (1.0 / 60.0) * (F[3 * sd] - F[-3 * sd]);
+          r[q + 1] += d * ih;
+        }
+      }
+    }
+    if (MODE == MODE_SET) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) A.rhs[q * N + id] = r[q];
+    } else if (MODE == MODE_ADD) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) A.rhs[q * N + id] += r[q];
+    } else {
+      // nodes on a face of a non-periodic direction take dU/dt = 0 (their
+      // value is set by the boundary condition after the stage)
+      bool bnd = false;
+      if (anyb) {
+        const int p0 = (int)(id % A.g.n[0]), p1 = (int)((id / A.g.n[0]) % A.g.n[1]),
+                  p2 = (int)(id / ((long long)A.g.n[0] * A.g.n[1]));
+        bnd = (!A.g.periodic[0] && (p0 == 0 || p0 == A.g.n[0] - 1)) ||
+              (!A.g.periodic[1] && (p1 == 0 || p1 == A.g.n[1] - 1)) ||
+              (!A.g.periodic[2] && (p2 == 0 || p2 == A.g.n[2] - 1));
+      }
+      const double ij = 1.0 / A.met[9 * N + id];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const double L = bnd ? 0.0 : (A.rhs[q * N + id] + r[q]) * ij;
+        if (MODE == MODE_RK)
+          A.out[q * N + id] = A.a * A.Un[q * N + id] + A.b * (A.U[q * N + id] + A.dt * L);
+        else
+          A.out[q * N + id] = L;
+      }
+    }
+  };
+
+  const int nchunks = (n + SW_S - 1) / SW_S;
+  // Chunk c reconstructs interfaces JB + 16c + s (s = 0..15) and loads nodes
+  // JB + 16c + 4 .. JB + 16c + 19.  Periodic lines: JB = -4, so every load
+  // window starts on a 16-node (128-byte) boundary, n interfaces.  Non-periodic
+  // lines: JB = 0, interfaces 0 .. n-2, nodes outside [0, n-1] never loaded.
+  const int JB = per ? -4 : 0;
+  const int nif = per ? n : n - 1;          // interfaces of the line
+  const int mmax = n - 1;                   // last node the chunks load (the prologue covers JB-3 .. JB+3)
+  // Prologue: nodes JB-3 .. JB+3 of every line.
+  if (A.inviscid && t < 7 * SW_W) {
+    const int pm = (DIR == 0) ? (t % 7) : (t / SW_W);
+    const int pc = (DIR == 0) ? (t / 7) : (t % SW_W);
+    const int m = JB + pm - 3;
+    if (col0 + pc < ncol && (per || (m >= 0 && m < n))) split_store(m, pc, fetch(m, pc));
+  }
+  NodeIn ahead;
+  bool have = A.inviscid && gcol_ok && JB + 4 + gs <= mmax;
+  if (have) ahead = fetch(JB + 4 + gs, gc);
+  // Reconstruction of interface j of line col into dst (WENO7 or low-dissipation stencil).
+  auto reconstruct = [&](int j, int col, bool low, double* dst) {
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      const R* P = ring + col + q * SW_W;
+      const R* M = ring + col + (5 + q) * SW_W;
+#define RP(o) P[((j + (o)) & (RING - 1)) * SLOT]
+#define RM(o) M[((j + (o)) & (RING - 1)) * SLOT]
+      double F;
+      if (!per && (j < 3 || j > n - 5)) {
+        // stencil leaves the domain: masked WENO5 (out-of-domain values
+        // replaced by the centre value so the masked terms stay finite)
+        auto fp = [&](int o) { const int m = j + o; return (m >= 0 && m < n) ? RP(o) : RP(0); };
+        auto fm = [&](int o) { const int m = j + o; return (m >= 0 && m < n) ? RM(o) : RM(1); };
+        auto in = [&](int o) { const int m = j + o; return m >= 0 && m < n; };
+        // f+: substencils j-2..j, j-1..j+1, j..j+2; f- (mirrored): j+3..j+1, j+2..j, j+1..j-1
+        F = (double)weno5m<R>(fp(-2), fp(-1), fp(0), fp(1), fp(2), eps, in(-2), in(-1), in(2)) +
+            (double)weno5m<R>(fm(3), fm(2), fm(1), fm(0), fm(-1), eps, in(3), in(2), in(-1));
+      } else if (HYB && low) {
+        if (A.lowdiss == OCFD_LOWDISS_C8)
+          F = (double)c8<R>(RP(-3) + RM(-3), RP(-2) + RM(-2), RP(-1) + RM(-1), RP(0) + RM(0), RP(1) + RM(1),
+                            RP(2) + RM(2), RP(3) + RM(3), RP(4) + RM(4));
+        else
+          F = (double)ud7<R>(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3)) +
+              (double)ud7<R>(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2));
+      } else {
+        F = (double)weno7<R>(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3), eps) +
+            (double)weno7<R>(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2), eps);
+      }
+#undef RP
+#undef RM
+      dst[q * SW_W] = F;
+    }
+  };
+
+  for (int c = 0; c < nchunks; ++c) {
+    const int j0 = JB + c * SW_S;
+    if (have) split_store(j0 + 4 + gs, gc, ahead);
+    if (HYB && t == 0) wl_n = 0;
+    __syncthreads();
+    have = A.inviscid && gcol_ok && c + 1 < nchunks && j0 + SW_S + 4 + gs <= mmax;
+    if (have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
+    const int j = j0 + rs;
+    const bool act = A.inviscid && rcol_ok && c * SW_S + rs < nif;
+    if (HYB) {
+      // Low-dissipation interfaces are done in place; WENO interfaces go to a
+      // work list so that whole waves run the WENO code (no divergence).
+      if (act) {
+        bool low;
+        if (!per && (j < 3 || j > n - 5))
+          low = false;   // boundary closure: always the WENO5 path
+        else
+          low = A.flags[DIR * N + base + (long long)rc * sc + (long long)(n >= 8 ? wrap1(j, n) : wrap(j, n)) * sd] == 0;
+        if (low)
+          reconstruct(j, rc, true, fh + (rs + 1) * FHS + rc);
+        else
+          wl[atomicAdd(&wl_n, 1)] = (short)t;
+      }
+      __syncthreads();
+      if (t < wl_n) {
+        const int tt = wl[t];
+        const int s2 = tt / SW_W, c2 = tt & (SW_W - 1);
+        reconstruct(j0 + s2, c2, false, fh + (s2 + 1) * FHS + c2);
+      }
+    } else if (act) {
+      reconstruct(j, rc, false, fh + (rs + 1) * FHS + rc);
+    }
+    __syncthreads();
+    if (c == 0 && t < 5 * SW_W) fh0[(t / SW_W) * SW_W + (t % SW_W)] = fh[FHS + (t / SW_W) * SW_W + (t % SW_W)];
+    if (per) {
+      if (gcol_ok && c * SW_S + gs < n && (c > 0 || gs > 0))
+        emit(n >= 8 ? wrap1(j0 + gs, n) : wrap(j0 + gs, n), gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc, true);
+    } else {
+      const int jn = j0 + gs;
+      if (gcol_ok && jn < n) emit(jn, gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc, jn > 0 && jn < n - 1);
+    }
+    __syncthreads();
+    if (t < 5 * SW_W) {
+      const int last = min(SW_S, nif - c * SW_S);
+      if (last > 0) fh[(t / SW_W) * SW_W + (t % SW_W)] = fh[last * FHS + (t / SW_W) * SW_W + (t % SW_W)];
+    }
+  }
+  __syncthreads();
+  // The periodic line's first node (JB) with the wrapped flux carried out of the last chunk.
+  if (per && gs == 0 && gcol_ok) emit(wrap(JB, n), gc, fh0 + gc, fh + gc, true);
+}
+
+template <int DIR, int MODE, int BND>
+static void launch_sweep_b(const SweepArgs& a, dim3 grid, hipStream_t st) {
+  if (a.mixed) {
+    if (a.hybrid)
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, float, BND>), grid, dim3(SW_T), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, float, BND>), grid, dim3(SW_T), 0, st, a);
+  } else {
+    if (a.hybrid)
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, double, BND>), grid, dim3(SW_T), 0, st, a);
+    else
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, double, BND>), grid, dim3(SW_T), 0, st, a);
+  }
+}
+
+template <int DIR, int MODE>
+static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
+  constexpr int CD = (DIR == 0) ? 1 : 0;
+  constexpr int OD = (DIR == 2) ? 1 : 2;
+  dim3 grid((a.g.n[CD] + SW_W - 1) / SW_W, a.g.n[OD]);
+  const bool all = a.g.periodic[0] && a.g.periodic[1] && a.g.periodic[2];
+  if (!a.g.periodic[DIR])
+    launch_sweep_b<DIR, MODE, 2>(a, grid, st);
+  else if (all)
+    launch_sweep_b<DIR, MODE, 0>(a, grid, st);
+  else
+    launch_sweep_b<DIR, MODE, 1>(a, grid, st);
+  return hipGetLastError();
+}
+
+template <int DIR>
+hipError_t launch_sweep_d(int mode, const SweepArgs& a, hipStream_t st) {
+  if (a.hybrid && a.inviscid && !a.flags) return hipErrorInvalidValue;   // hybrid needs interface flags
+  switch (mode) {
+    case MODE_SET: return launch_sweep_t<DIR, MODE_SET>(a, st);
+    case MODE_ADD: return launch_sweep_t<DIR, MODE_ADD>(a, st);
+    case MODE_RK: return launch_sweep_t<DIR, MODE_RK>(a, st);
+    default: return launch_sweep_t<DIR, MODE_DUDT>(a, st);
+  }
+}
+
+}  // namespace ocfd
