@@ -110,11 +110,14 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
     `substeps` substeps from the developed state with (i) WENO7 everywhere,
     FP64, (ii) the plain FP64 hybrid, (iii) FP32 reconstruction + learned
     sensor (re-evaluated every substep, audited every 50), (iv) the same with
-    the network re-evaluated once per Runge-Kutta step."""
+    the network re-evaluated once per Runge-Kutta step.  The time step is
+    twice the generator's default (CFL about 0.5), so the first 500 substeps
+    reach the formation of shocklets."""
     import dataclasses
     import workloads
     t_all = time.perf_counter()
     case = workloads.isotropic_turbulence(n)
+    case.dt *= 2.0        # acoustic CFL ~0.5 (the generator's default is ~0.25)
     _log(f"hit{n}: inputs ready ({time.perf_counter() - t_all:.0f} s)")
     s = pk.Solver(pk.params_from(case))
     s.set_grid(torch.from_numpy(case.xyz).cuda())

@@ -32,7 +32,7 @@ struct ocfd_solver {
   double* red = nullptr;
   const uint8_t* flags = nullptr;
   // learned sensor
-  float* feat = nullptr;          // [4][N] node features
+  uint16_t* feat = nullptr;       // [N][4] node features, bf16
   uint8_t* lflags = nullptr;      // [3][N] learned flags
   uint8_t* pflags = nullptr;      // [3][N] plain flags (audit, collection)
   float* mlp = nullptr;           // [NPARAM] FP32 master weights
@@ -98,6 +98,7 @@ bool valid_params(const ocfd_params* p, std::string* why) {
     *why = buf;
     return false;
   }
+  if ((long long)p->nx * p->ny * p->nz >= (1ll << 31)) { *why = "grid of 2^31 nodes or more"; return false; }
   for (int d = 0; d < 3; ++d)
     if (!(p->h[d] > 0.0) || !std::isfinite(p->h[d])) { *why = "h must be positive and finite"; return false; }
   if (!(p->gamma > 1.0)) { *why = "gamma must exceed 1"; return false; }
@@ -174,6 +175,8 @@ void setup_geo_phys(ocfd_solver* s) {
   s->g.s[2] = (long long)p.nx * p.ny;
   s->g.N = (long long)p.nx * p.ny * p.nz;
   for (int d = 0; d < 3; ++d) s->g.periodic[d] = p.periodic[d];
+  s->g.div[0] = make_fastdiv((uint32_t)p.nx);
+  s->g.div[1] = make_fastdiv((uint32_t)p.ny);
   Phys& ph = s->ph;
   ph.gamma = p.gamma;
   ph.gm1 = p.gamma - 1.0;
@@ -210,7 +213,7 @@ size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver
   double* th = take(WS_THETA * fb);
   double* partial = take((size_t)nred * OCFD_RED_COUNT * sizeof(double));
   double* red = take(16 * sizeof(double));
-  float* feat = (float*)take(4 * (size_t)N * sizeof(float));
+  uint16_t* feat = (uint16_t*)take(4 * (size_t)N * sizeof(uint16_t));
   uint8_t* lflags = (uint8_t*)take(3 * (size_t)N);
   uint8_t* pflags = (uint8_t*)take(3 * (size_t)N);
   float* mlp = (float*)take(MLP_NPARAM * sizeof(float));

@@ -20,13 +20,76 @@ constexpr int MLP_W3 = MLP_B2 + MLP_H;
 constexpr int MLP_B3 = MLP_W3 + MLP_H;
 constexpr int MLP_NPARAM = MLP_B3 + 1;
 
-// Grid geometry: node counts and element strides of xi, eta, zeta.
+// Division of 32-bit unsigned integers by an invariant divisor d >= 1:
+// x / d = (umulhi(x, mul) + x) >> shift with shift = ceil(log2 d) and
+// mul = floor(2^32 (2^shift - d) / d) + 1 (Granlund and Montgomery,
+// "Division by invariant integers using multiplication", 1994).
+struct FastDiv {
+  uint32_t mul;
+  uint32_t shift;
+};
+
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((1ull << l) < d) ++l;
+  const unsigned long long m = ((1ull << 32) * ((1ull << l) - d)) / d + 1;
+  return FastDiv{(uint32_t)m, l};
+}
+
+// Grid geometry: node counts and element strides of xi, eta, zeta (N < 2^31).
 struct Geo {
   int n[3];
   long long s[3];
   long long N;
   int periodic[3];
+  FastDiv div[2];   // by n[0] and by n[1]
 };
+
+// Column tiles for kernels that march along zeta: 64 x 4 (xi, eta) columns
+// per workgroup, zeta cut into segments so that about 2048 workgroups run;
+// tiles are numbered so that each of the 8 XCDs (which receive workgroups
+// round robin) gets a contiguous range of neighbouring tiles.
+struct ZMarch {
+  int ntx, nty, nseg, zseg;
+  unsigned blocks;
+};
+
+inline ZMarch make_zmarch(const int n[3]) {
+  ZMarch z;
+  z.ntx = (n[0] + 63) / 64;
+  z.nty = (n[1] + 3) / 4;
+  int nseg = (2048 + z.ntx * z.nty - 1) / (z.ntx * z.nty);
+  nseg = nseg < 1 ? 1 : (nseg > n[2] ? n[2] : nseg);
+  z.zseg = (n[2] + nseg - 1) / nseg;
+  z.nseg = (n[2] + z.zseg - 1) / z.zseg;
+  const long long tiles = (long long)z.ntx * z.nty * z.nseg;
+  z.blocks = (unsigned)(8 * ((tiles + 7) / 8));
+  return z;
+}
+
+// This thread's column (i, j) and zeta range [k0, k1); false if it has none.
+__device__ __forceinline__ bool zmarch_column(const ZMarch& z, const int n[3], int* i, int* j, int* k0, int* k1) {
+  const int per = gridDim.x / 8;
+  const int L = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (L >= z.ntx * z.nty * z.nseg) return false;
+  const int tx = L % z.ntx, ty = (L / z.ntx) % z.nty, zs = L / (z.ntx * z.nty);
+  *i = tx * 64 + (threadIdx.x & 63);
+  *j = ty * 4 + threadIdx.x / 64;
+  if (*i >= n[0] || *j >= n[1]) return false;
+  *k0 = zs * z.zseg;
+  *k1 = min(n[2], *k0 + z.zseg);
+  return true;
+}
+
+// Node position (i, j, k) of the linear index id (< 2^31).
+__device__ __forceinline__ void node_position(const Geo& g, long long id, int pos[3]) {
+  const uint32_t x = (uint32_t)id;
+  const uint32_t q0 = (uint32_t)(((unsigned long long)__umulhi(x, g.div[0].mul) + x) >> g.div[0].shift);
+  const uint32_t q1 = (uint32_t)(((unsigned long long)__umulhi(q0, g.div[1].mul) + q0) >> g.div[1].shift);
+  pos[0] = (int)(x - q0 * (uint32_t)g.n[0]);
+  pos[1] = (int)(q0 - q1 * (uint32_t)g.n[1]);
+  pos[2] = (int)q1;
+}
 
 // Physical constants as the kernels use them.
 struct Phys {
@@ -93,9 +156,9 @@ int reduce_blocks(const Geo& g);
 
 // Sensors (ocfd_sensor.hip).
 hipError_t launch_plain_flags(const Geo& g, double theta1, const double* theta, uint8_t* flags, hipStream_t st);
-hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, float* feat,
+hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, uint16_t* feat,
                            hipStream_t st);
-hipError_t launch_mlp_flags(const Geo& g, const float* feat, const float* P, float tau, uint8_t* flags,
+hipError_t launch_mlp_flags(const Geo& g, const uint16_t* feat, const float* P, float tau, uint8_t* flags,
                             hipStream_t st);
 hipError_t launch_mlp_prob(const uint16_t* X, long long S, const float* P, float* prob, hipStream_t st);
 hipError_t launch_mlp_grad(const uint16_t* X, const uint8_t* y, const float* w, const int* idx, long long nb,
@@ -103,7 +166,7 @@ hipError_t launch_mlp_grad(const uint16_t* X, const uint8_t* y, const float* w, 
                            float* m, float* v, float lr, int t, hipStream_t st);
 hipError_t launch_collect_count(const Geo& g, const uint8_t* flags, uint64_t seed, uint32_t thr_pos, uint32_t thr_neg,
                                 unsigned long long* counts, int nblocks, hipStream_t st);
-hipError_t launch_collect_write(const Geo& g, const uint8_t* flags, const float* feat, uint64_t seed, uint32_t thr_pos,
+hipError_t launch_collect_write(const Geo& g, const uint8_t* flags, const uint16_t* feat, uint64_t seed, uint32_t thr_pos,
                                 uint32_t thr_neg, const unsigned long long* offs, long long cap, uint16_t* X,
                                 uint8_t* y, float* w, int nblocks, hipStream_t st);
 hipError_t launch_flags_or(uint8_t* a, const uint8_t* b, long long n, hipStream_t st);

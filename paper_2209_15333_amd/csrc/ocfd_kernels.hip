@@ -244,33 +244,46 @@ hipError_t launch_bc(const Geo& g, const Phys& ph, double* U, int d, int side, i
 // Shock sensor (eq 42-43): theta = sum_d |-p_- + 2p - p_+| / (p_- + 2p + p_+)
 // ---------------------------------------------------------------------------
 
-// theta from the node pressures P[N].  One thread per node on a (64, 4)
-// block grid over (xi, eta) x zeta planes, so node positions come from the
-// launch indices (no integer division).
-__global__ __launch_bounds__(256) void k_sensor(const Geo g, const double* __restrict__ P,
+// theta from the node pressures P[N].  Each thread marches one (xi, eta)
+// column through a zeta segment with the pressures of planes k-1, k, k+1 in
+// registers; xi and eta neighbours are read from the plane (cached).
+__global__ __launch_bounds__(256) void k_sensor(const Geo g, const ZMarch zm, const double* __restrict__ P,
                                                 double* __restrict__ theta) {
-  const int pos[3] = {(int)(blockIdx.x * 64 + threadIdx.x), (int)(blockIdx.y * 4 + threadIdx.y), (int)blockIdx.z};
-  if (pos[0] >= g.n[0] || pos[1] >= g.n[1]) return;
-  const long long id = pos[0] + g.s[1] * pos[1] + g.s[2] * pos[2];
-  const double p0 = P[id];
-  double th = 0.0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
-    // a node at the end of a non-periodic line has no second difference there
-    if (!g.periodic[d] && (pos[d] == 0 || pos[d] == g.n[d] - 1)) continue;
-    const double pm = P[id + (long long)(wrap(pos[d] - 1, g.n[d]) - pos[d]) * g.s[d]];
-    const double pp = P[id + (long long)(wrap(pos[d] + 1, g.n[d]) - pos[d]) * g.s[d]];
-    th += fabs(-pm + 2.0 * p0 - pp) / (pm + 2.0 * p0 + pp);
+  int i, j, k0, k1;
+  if (!zmarch_column(zm, g.n, &i, &j, &k0, &k1)) return;
+  const int nz = g.n[2];
+  const bool pz = g.periodic[2];
+  const long long col = i + g.s[1] * j;
+  auto plane = [&](int k) { return pz ? wrap(k, nz) : min(max(k, 0), nz - 1); };
+  const long long xm = (long long)(wrap(i - 1, g.n[0]) - i), xp = (long long)(wrap(i + 1, g.n[0]) - i);
+  const long long ym = (long long)(wrap(j - 1, g.n[1]) - j) * g.s[1], yp = (long long)(wrap(j + 1, g.n[1]) - j) * g.s[1];
+  const bool xend = !g.periodic[0] && (i == 0 || i == g.n[0] - 1);
+  const bool yend = !g.periodic[1] && (j == 0 || j == g.n[1] - 1);
+  double pm = P[col + plane(k0 - 1) * g.s[2]];
+  double p0 = P[col + (long long)k0 * g.s[2]];
+  for (int k = k0; k < k1; ++k) {
+    const long long id = col + (long long)k * g.s[2];
+    const double pp = P[col + plane(k + 1) * g.s[2]];
+    double th = 0.0;
+    if (!xend) {
+      const double a = P[id + xm], b = P[id + xp];
+      th += fabs(-a + 2.0 * p0 - b) / (a + 2.0 * p0 + b);
+    }
+    if (!yend) {
+      const double a = P[id + ym], b = P[id + yp];
+      th += fabs(-a + 2.0 * p0 - b) / (a + 2.0 * p0 + b);
+    }
+    // a node at the end of a bounded line has no second difference there
+    if (pz || (k != 0 && k != nz - 1)) th += fabs(-pm + 2.0 * p0 - pp) / (pm + 2.0 * p0 + pp);
+    theta[id] = th;
+    pm = p0;
+    p0 = pp;
   }
-  theta[id] = th;
-}
-
-static dim3 node_grid(const Geo& g) {
-  return dim3((unsigned)((g.n[0] + 63) / 64), (unsigned)((g.n[1] + 3) / 4), (unsigned)g.n[2]);
 }
 
 hipError_t launch_sensor(const Geo& g, const double* P, double* theta, hipStream_t st) {
-  hipLaunchKernelGGL(k_sensor, node_grid(g), dim3(64, 4), 0, st, g, P, theta);
+  const ZMarch zm = make_zmarch(g.n);
+  hipLaunchKernelGGL(k_sensor, dim3(zm.blocks), dim3(256), 0, st, g, zm, P, theta);
   return hipGetLastError();
 }
 
@@ -293,7 +306,8 @@ __global__ __launch_bounds__(256) void k_metric_inner(const Geo g, const Phys ph
                                                       double* __restrict__ inner) {
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= g.N) return;
-  const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
+  int pos[3];
+  node_position(g, id, pos);
   for (int co = 0; co < 3; ++co)
     for (int d = 0; d < 3; ++d) {
       auto val = [&](int m) { return coord_at(g, ph, xyz, co, id, pos, d, m); };
@@ -317,7 +331,8 @@ __global__ __launch_bounds__(256) void k_metric_outer(const Geo g, const Phys ph
                                                       const double* __restrict__ inner, double* __restrict__ met) {
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= g.N) return;
-  const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
+  int pos[3];
+  node_position(g, id, pos);
   for (int r = 0; r < 3; ++r)
     for (int co = 0; co < 3; ++co) {
       const int s = (r + 1) % 3, t = (r + 2) % 3;

@@ -45,32 +45,57 @@ __device__ __forceinline__ v4f mfma16(const v4bf& a, const v4bf& b, const v4f& c
 // Plain sensor flags: interface j+1/2 along d is low-dissipation iff the node
 // sensor theta is <= theta1 at every node j-3 .. j+4.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_plain_flags(const Geo g, double theta1, const double* __restrict__ theta,
-                                                     uint8_t* __restrict__ flags) {
-  const int pos[3] = {(int)(blockIdx.x * 64 + threadIdx.x), (int)(blockIdx.y * 4 + threadIdx.y), (int)blockIdx.z};
-  if (pos[0] >= g.n[0] || pos[1] >= g.n[1]) return;
-  const long long id = pos[0] + g.s[1] * pos[1] + g.s[2] * pos[2];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) {
+// Each thread marches one (xi, eta) column through a zeta segment keeping
+// theta of planes k-3 .. k+4 in registers; the xi and eta windows are read
+// from the plane (cached).  Positions outside a bounded line count as 0
+// (theta >= 0, so the maximum is the one over the nodes that exist).
+__global__ __launch_bounds__(256) void k_plain_flags(const Geo g, const ZMarch zm, double theta1,
+                                                     const double* __restrict__ theta, uint8_t* __restrict__ flags) {
+  int i, j, k0, k1;
+  if (!zmarch_column(zm, g.n, &i, &j, &k0, &k1)) return;
+  const int nz = g.n[2];
+  const bool pz = g.periodic[2];
+  const long long col = i + g.s[1] * j;
+  auto zval = [&](int k) {
+    if (pz) return theta[col + (long long)(nz >= 8 ? k + (k < 0 ? nz : 0) - (k >= nz ? nz : 0) : wrapn(k, nz)) * g.s[2]];
+    return (k < 0 || k >= nz) ? 0.0 : theta[col + (long long)k * g.s[2]];
+  };
+  // in-plane window maximum along d (0: xi, 1: eta) at position p of n
+  auto inplane = [&](long long id, int d, int p) {
     const int n = g.n[d];
     double mx = 0.0;
 #pragma unroll
     for (int o = -3; o <= 4; ++o) {
-      int q = pos[d] + o;
+      int q = p + o;
       if (g.periodic[d]) {
         q = n >= 8 ? q + (q < 0 ? n : 0) - (q >= n ? n : 0) : wrapn(q, n);
       } else if (q < 0 || q >= n) {
-        continue;   // window clipped at a bounded end
+        continue;
       }
-      mx = fmax(mx, theta[id + (long long)(q - pos[d]) * g.s[d]]);
+      mx = fmax(mx, theta[id + (long long)(q - p) * g.s[d]]);
     }
-    flags[d * g.N + id] = mx <= theta1 ? 0 : 1;
+    return mx;
+  };
+  double w[8];
+#pragma unroll
+  for (int o = 0; o < 7; ++o) w[o] = zval(k0 - 3 + o);
+  for (int k = k0; k < k1; ++k) {
+    w[7] = zval(k + 4);
+    const long long id = col + (long long)k * g.s[2];
+    double mz = 0.0;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) mz = fmax(mz, w[o]);
+    flags[id] = inplane(id, 0, i) <= theta1 ? 0 : 1;
+    flags[g.N + id] = inplane(id, 1, j) <= theta1 ? 0 : 1;
+    flags[2 * g.N + id] = mz <= theta1 ? 0 : 1;
+#pragma unroll
+    for (int o = 0; o < 7; ++o) w[o] = w[o + 1];
   }
 }
 
 hipError_t launch_plain_flags(const Geo& g, double theta1, const double* theta, uint8_t* flags, hipStream_t st) {
-  const dim3 grid((unsigned)((g.n[0] + 63) / 64), (unsigned)((g.n[1] + 3) / 4), (unsigned)g.n[2]);
-  hipLaunchKernelGGL(k_plain_flags, grid, dim3(64, 4), 0, st, g, theta1, theta, flags);
+  const ZMarch zm = make_zmarch(g.n);
+  hipLaunchKernelGGL(k_plain_flags, dim3(zm.blocks), dim3(256), 0, st, g, zm, theta1, theta, flags);
   return hipGetLastError();
 }
 
@@ -85,61 +110,69 @@ hipError_t launch_plain_flags(const Geo& g, double theta1, const double* theta, 
 // a bounded line), chain rule with the node metrics.  A bounded direction adds
 // no jump term at its end nodes.
 // ---------------------------------------------------------------------------
+// Stored as bf16 (round to nearest even of the FP32 value), four per node
+// (node-major, 8 bytes), the operand format of the perceptron.
 __global__ __launch_bounds__(256) void k_features(const Geo g, const Phys ph, const double* __restrict__ U,
-                                                  const double* __restrict__ met, float* __restrict__ feat) {
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= g.N) return;
+                                                  const double* __restrict__ met, uint2* __restrict__ feat) {
+  const int pos[3] = {(int)(blockIdx.x * 64 + threadIdx.x), (int)(blockIdx.y * 4 + threadIdx.y), (int)blockIdx.z};
+  if (pos[0] >= g.n[0] || pos[1] >= g.n[1]) return;
+  const long long id = pos[0] + g.s[1] * pos[1] + g.s[2] * pos[2];
   const long long N = g.N;
-  const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
   const double rho = U[id];
-  const double u = U[N + id] / rho, v = U[2 * N + id] / rho, w = U[3 * N + id] / rho;
+  const double ir0 = 1.0 / rho;
+  const double u = U[N + id] * ir0, v = U[2 * N + id] * ir0, w = U[3 * N + id] * ir0;
   const double p = ph.gm1 * (U[4 * N + id] - 0.5 * rho * (u * u + v * v + w * w));
   double dvd[3][3];  // d(vel_a)/d(xi_d)
   double jp = 0.0, jr = 0.0;
   for (int d = 0; d < 3; ++d) {
     const bool bnd = !g.periodic[d];
-    const int qp = bnd ? min(pos[d] + 1, g.n[d] - 1) : wrapn(pos[d] + 1, g.n[d]);
-    const int qm = bnd ? max(pos[d] - 1, 0) : wrapn(pos[d] - 1, g.n[d]);
-    const bool end = bnd && (pos[d] == 0 || pos[d] == g.n[d] - 1);
-    const double span = (bnd ? (double)(qp - qm) : 2.0) * ph.h[d];
+    const int n = g.n[d];
+    const int qp = bnd ? min(pos[d] + 1, n - 1) : (pos[d] + 1 >= n ? pos[d] + 1 - n : pos[d] + 1);
+    const int qm = bnd ? max(pos[d] - 1, 0) : (pos[d] - 1 < 0 ? pos[d] - 1 + n : pos[d] - 1);
+    const bool end = bnd && (pos[d] == 0 || pos[d] == n - 1);
+    const double ispan = 1.0 / ((bnd ? (double)(qp - qm) : 2.0) * ph.h[d]);
     const long long ip = id + (long long)(qp - pos[d]) * g.s[d];
     const long long im = id + (long long)(qm - pos[d]) * g.s[d];
-    double vp[3], vm[3];
     const double rp = U[ip], rm = U[im];
+    const double irp = 1.0 / rp, irm = 1.0 / rm;
+    double vp[3], vm[3];
     for (int a = 0; a < 3; ++a) {
-      vp[a] = U[(a + 1) * N + ip] / rp;
-      vm[a] = U[(a + 1) * N + im] / rm;
+      vp[a] = U[(a + 1) * N + ip] * irp;
+      vm[a] = U[(a + 1) * N + im] * irm;
     }
     const double pp = ph.gm1 * (U[4 * N + ip] - 0.5 * rp * (vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2]));
     const double pm = ph.gm1 * (U[4 * N + im] - 0.5 * rm * (vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2]));
-    for (int a = 0; a < 3; ++a) dvd[a][d] = (vp[a] - vm[a]) / span;
+    for (int a = 0; a < 3; ++a) dvd[a][d] = (vp[a] - vm[a]) * ispan;
     if (!end) {
       jp += fabs(-pm + 2.0 * p - pp) / (pm + 2.0 * p + pp);
       jr += fabs(-rm + 2.0 * rho - rp) / (rm + 2.0 * rho + rp);
     }
   }
   const double jinv = met[9 * N + id];
+  const double ij = 1.0 / jinv;
   double gr[3][3];
   for (int a = 0; a < 3; ++a)
     for (int c = 0; c < 3; ++c) {
       double s = 0.0;
-      for (int d = 0; d < 3; ++d) s += (met[(3 * d + c) * N + id] / jinv) * dvd[a][d];
+      for (int d = 0; d < 3; ++d) s += (met[(3 * d + c) * N + id] * ij) * dvd[a][d];
       gr[a][c] = s;
     }
   const double div = gr[0][0] + gr[1][1] + gr[2][2];
   const double wx = gr[2][1] - gr[1][2], wy = gr[0][2] - gr[2][0], wz = gr[1][0] - gr[0][1];
   const double vort = sqrt(wx * wx + wy * wy + wz * wz);
-  const double c = sqrt(ph.gamma * p / rho);
-  const double delta = cbrt(fabs(jinv));
-  feat[id] = (float)(delta * div / c);
-  feat[N + id] = (float)(delta * vort / c);
-  feat[2 * N + id] = (float)(jp / ph.theta1);
-  feat[3 * N + id] = (float)(jr / ph.theta1);
+  const double dc = cbrt(fabs(jinv)) / sqrt(ph.gamma * p * ir0);   // Delta / c
+  const double it1 = 1.0 / ph.theta1;
+  const __bf16 f[4] = {(__bf16)(float)(dc * div), (__bf16)(float)(dc * vort), (__bf16)(float)(jp * it1),
+                       (__bf16)(float)(jr * it1)};
+  uint2 out;
+  __builtin_memcpy(&out, f, 8);
+  feat[id] = out;
 }
 
-hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, float* feat,
+hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, uint16_t* feat,
                            hipStream_t st) {
-  hipLaunchKernelGGL(k_features, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, U, met, feat);
+  const dim3 grid((unsigned)((g.n[0] + 63) / 64), (unsigned)((g.n[1] + 3) / 4), (unsigned)g.n[2]);
+  hipLaunchKernelGGL(k_features, grid, dim3(64, 4), 0, st, g, ph, U, met, (uint2*)feat);
   return hipGetLastError();
 }
 
@@ -152,7 +185,9 @@ __device__ __forceinline__ bool window_inside(const Geo& g, int d, int pos) {
 }
 
 __device__ __forceinline__ int node_pos(const Geo& g, long long id, int d) {
-  return d == 0 ? (int)(id % g.n[0]) : d == 1 ? (int)((id / g.n[0]) % g.n[1]) : (int)(id / ((long long)g.n[0] * g.n[1]));
+  int pos[3];
+  node_position(g, id, pos);
+  return pos[d];
 }
 
 // ---------------------------------------------------------------------------
@@ -218,7 +253,7 @@ __device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + __expf(
 
 // Learned flags of every interface: x of interface (d, node) = the four
 // features of the 8 nodes j-3 .. j+4 along d, node-major.
-__global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const float* __restrict__ feat,
+__global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const uint2* __restrict__ feat,
                                                    const float* __restrict__ P, float tau,
                                                    uint8_t* __restrict__ flags) {
   MlpRegs R;
@@ -228,30 +263,47 @@ __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const float* __r
   const long long tiles = (N + 15) / 16;
   const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6);
   const long long nwaves = (long long)gridDim.x * 4;
-  for (long long T = wave; T < 3 * tiles; T += nwaves) {
-    const int d = (int)(T / tiles);
-    const long long id = (T % tiles) * 16 + j;
-    const bool ok = id < N;
-    const long long idc = ok ? id : N - 1;
-    const int pos[3] = {(int)(idc % g.n[0]), (int)((idc / g.n[0]) % g.n[1]), (int)(idc / ((long long)g.n[0] * g.n[1]))};
-    const bool inside = window_inside(g, d, pos[d]);
-    v8bf x;
-    for (int tt = 0; tt < 2; ++tt) {
-      const int t = 2 * gg + tt;
-      const int q = g.periodic[d] ? wrapn(pos[d] + t - 3, g.n[d]) : min(max(pos[d] + t - 3, 0), g.n[d] - 1);
-      const long long nid = idc + (long long)(q - pos[d]) * g.s[d];
-#pragma unroll
-      for (int f = 0; f < 4; ++f) x[4 * tt + f] = (__bf16)feat[f * N + nid];
+  struct Tile {
+    uint2 xv[2];     // inputs 8gg .. 8gg+7 = the four bf16 features of window nodes 2gg, 2gg+1
+    long long id;
+    bool ok, inside;
+  };
+  for (int d = 0; d < 3; ++d) {
+    const int n = g.n[d];
+    auto gather = [&](long long T, Tile& tl) {
+      tl.id = T * 16 + j;
+      tl.ok = tl.id < N;
+      const long long idc = tl.ok ? tl.id : N - 1;
+      int pos[3];
+      node_position(g, idc, pos);
+      tl.inside = window_inside(g, d, pos[d]);
+      for (int tt = 0; tt < 2; ++tt) {
+        int q = pos[d] + 2 * gg + tt - 3;
+        if (g.periodic[d])
+          q = n >= 8 ? q + (q < 0 ? n : 0) - (q >= n ? n : 0) : wrapn(q, n);
+        else
+          q = min(max(q, 0), n - 1);
+        tl.xv[tt] = feat[idc + (long long)(q - pos[d]) * g.s[d]];
+      }
+    };
+    // the next tile's inputs are loaded while the current one is evaluated
+    Tile cur, nxt;
+    if (wave < tiles) gather(wave, cur);
+    for (long long T = wave; T < tiles; T += nwaves) {
+      if (T + nwaves < tiles) gather(T + nwaves, nxt);
+      v8bf x;
+      __builtin_memcpy(&x, cur.xv, 16);
+      Fwd F;
+      mlp_forward(R, x, F);
+      if (cur.ok && gg == 0) flags[d * N + cur.id] = (!cur.inside || sigmoidf(F.z) >= tau) ? 1 : 0;
+      cur = nxt;
     }
-    Fwd F;
-    mlp_forward(R, x, F);
-    if (ok && gg == 0) flags[d * N + id] = (!inside || sigmoidf(F.z) >= tau) ? 1 : 0;
   }
 }
 
-hipError_t launch_mlp_flags(const Geo& g, const float* feat, const float* P, float tau, uint8_t* flags,
+hipError_t launch_mlp_flags(const Geo& g, const uint16_t* feat, const float* P, float tau, uint8_t* flags,
                             hipStream_t st) {
-  hipLaunchKernelGGL(k_mlp_flags, dim3(2048), dim3(256), 0, st, g, feat, P, tau, flags);
+  hipLaunchKernelGGL(k_mlp_flags, dim3(2048), dim3(256), 0, st, g, (const uint2*)feat, P, tau, flags);
   return hipGetLastError();
 }
 
@@ -512,7 +564,7 @@ __global__ __launch_bounds__(CT) void k_collect_count(const Geo g, const uint8_t
 // Writes the kept samples of this workgroup's range, in index order, from
 // offset offs[block] (offsets beyond cap are dropped).
 __global__ __launch_bounds__(CT) void k_collect_write(const Geo g, const uint8_t* __restrict__ flags,
-                                                      const float* __restrict__ feat, uint64_t seed, uint32_t thr_pos,
+                                                      const uint2* __restrict__ feat, uint64_t seed, uint32_t thr_pos,
                                                       uint32_t thr_neg, const unsigned long long* __restrict__ offs,
                                                       long long cap, uint16_t* __restrict__ X,
                                                       uint8_t* __restrict__ y, float* __restrict__ w) {
@@ -545,17 +597,13 @@ __global__ __launch_bounds__(CT) void k_collect_write(const Geo g, const uint8_t
     if (kp) {
       const long long o = (long long)base + sc[threadIdx.x];
       if (o < cap) {
-        const int pos[3] = {(int)(id % g.n[0]), (int)((id / g.n[0]) % g.n[1]), (int)(id / ((long long)g.n[0] * g.n[1]))};
-        uint16_t xs[32];
-        for (int t = 0; t < 8; ++t) {
-          const long long nid = id + (long long)(wrapn(pos[d] + t - 3, g.n[d]) - pos[d]) * g.s[d];  // window inside
-          const float f[4] = {feat[nid], feat[N + nid], feat[2 * N + nid], feat[3 * N + nid]};
-          for (int q = 0; q < 4; ++q) {
-            const __bf16 bv = (__bf16)f[q];
-            __builtin_memcpy(&xs[4 * t + q], &bv, 2);
-          }
-        }
-        for (int q = 0; q < 32; ++q) X[o * 32 + q] = xs[q];
+        int pos[3];
+        node_position(g, id, pos);
+        uint2 xs[8];
+        for (int t = 0; t < 8; ++t)
+          xs[t] = feat[id + (long long)(wrapn(pos[d] + t - 3, g.n[d]) - pos[d]) * g.s[d]];  // window inside
+        uint2* dst = (uint2*)(X + o * 32);
+        for (int t = 0; t < 8; ++t) dst[t] = xs[t];
         y[o] = flags[k];
         w[o] = 1.f;
       }
@@ -572,10 +620,11 @@ hipError_t launch_collect_count(const Geo& g, const uint8_t* flags, uint64_t see
   return hipGetLastError();
 }
 
-hipError_t launch_collect_write(const Geo& g, const uint8_t* flags, const float* feat, uint64_t seed, uint32_t thr_pos,
+hipError_t launch_collect_write(const Geo& g, const uint8_t* flags, const uint16_t* feat, uint64_t seed, uint32_t thr_pos,
                                 uint32_t thr_neg, const unsigned long long* offs, long long cap, uint16_t* X,
                                 uint8_t* y, float* w, int nblocks, hipStream_t st) {
-  hipLaunchKernelGGL(k_collect_write, dim3(nblocks), dim3(CT), 0, st, g, flags, feat, seed, thr_pos, thr_neg, offs,
+  hipLaunchKernelGGL(k_collect_write, dim3(nblocks), dim3(CT), 0, st, g, flags, (const uint2*)feat, seed, thr_pos,
+                     thr_neg, offs,
                      cap, X, y, w);
   return hipGetLastError();
 }

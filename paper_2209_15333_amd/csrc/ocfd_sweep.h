@@ -156,8 +156,9 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
       // value is set by the boundary condition after the stage)
       bool bnd = false;
       if (anyb) {
-        const int p0 = (int)(id % A.g.n[0]), p1 = (int)((id / A.g.n[0]) % A.g.n[1]),
-                  p2 = (int)(id / ((long long)A.g.n[0] * A.g.n[1]));
+        int pq[3];
+        node_position(A.g, id, pq);
+        const int p0 = pq[0], p1 = pq[1], p2 = pq[2];
         bnd = (!A.g.periodic[0] && (p0 == 0 || p0 == A.g.n[0] - 1)) ||
               (!A.g.periodic[1] && (p1 == 0 || p1 == A.g.n[1] - 1)) ||
               (!A.g.periodic[2] && (p2 == 0 || p2 == A.g.n[2] - 1));
