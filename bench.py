@@ -106,13 +106,14 @@ def _timed_run(torch, pk, case, U, substeps, warmup=2, setup=None):
 def form_hit_learned(torch, pk, n, develop, every, substeps):
     """Decaying isotropic turbulence (hybrid WENO7 / C8): `develop` substeps of
     the plain FP64 hybrid with samples of the plain sensor's flags every
-    `every` substeps, GPU training and calibration of the perceptron, then
+    `every` substeps over its last 40%, GPU training and calibration of the
+    perceptron, then
     `substeps` substeps from the developed state with (i) WENO7 everywhere,
     FP64, (ii) the plain FP64 hybrid, (iii) FP32 reconstruction + learned
     sensor (re-evaluated every substep, audited every 50), (iv) the same with
     the network re-evaluated once per Runge-Kutta step.  The time step is
-    twice the generator's default (CFL about 0.5), so the first 500 substeps
-    reach the formation of shocklets."""
+    twice the generator's default (CFL about 0.5); shocklets form after
+    t ~ 0.3, about 850 substeps at 512^3."""
     import dataclasses
     import workloads
     t_all = time.perf_counter()
@@ -127,9 +128,11 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
     pk.ocfd_sensor_bind_samples(s.h, buf)
     t0 = time.perf_counter()
     total = 0
+    first = int(0.6 * develop)     # shocklets form late: sample the last 40% of the development
     for k in range(develop // every):
         s.advance(every, case.dt)
-        total = pk.ocfd_sensor_collect(s.h, 5000 + k, 0.05, 0.001)
+        if (k + 1) * every > first:
+            total = pk.ocfd_sensor_collect(s.h, 5000 + k, 0.1, 0.001)
     torch.cuda.synchronize()
     t_dev = time.perf_counter() - t0
     _log(f"hit{n}: developed {develop} substeps in {t_dev:.1f} s, {total} samples")
@@ -234,7 +237,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the isotropic-turbulence and compression-ramp form comparisons")
     ap.add_argument("--hit-n", type=int, default=512)
-    ap.add_argument("--hit-develop", type=int, default=500)
+    ap.add_argument("--hit-develop", type=int, default=1250,
+                    help="plain FP64 hybrid substeps before the forms are timed (t ~ 0.45 at 512^3)")
     ap.add_argument("--form-substeps", type=int, default=100)
     ap.add_argument("--ramp-shape", type=str, default="1024,160,128")
     ap.add_argument("--calibration-copy", action="store_true",

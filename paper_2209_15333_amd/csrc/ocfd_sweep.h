@@ -91,7 +91,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   // Primitive recovery and Steger-Warming split of node m into the ring.
   auto split_store = [&](int m, int col, const NodeIn& in) {
     const double rho = in.U[0];
-    const double ir = 1.0 / rho;
+    const double ir = rcp_r<double>(rho);
     const double u = in.U[1] * ir;
     const double v = in.U[2] * ir;
     const double w = in.U[3] * ir;
@@ -176,13 +176,17 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   };
 
   const int nchunks = (n + SW_S - 1) / SW_S;
-  // Chunk c reconstructs interfaces JB + 16c + s (s = 0..15) and loads nodes
-  // JB + 16c + 4 .. JB + 16c + 19.  Periodic lines: JB = -4, so every load
-  // window starts on a 16-node (128-byte) boundary, n interfaces.  Non-periodic
-  // lines: JB = 0, interfaces 0 .. n-2, nodes outside [0, n-1] never loaded.
-  const int JB = per ? -4 : 0;
-  const int nif = per ? n : n - 1;          // interfaces of the line
-  const int mmax = n - 1;                   // last node the chunks load (the prologue covers JB-3 .. JB+3)
+  // Chunk c reconstructs interfaces JB + 16c + s (s = 0..15), loads nodes
+  // JB + 16c + 4 .. JB + 16c + 19 and finishes nodes JB + 16c .. JB + 16c + 15.
+  // Periodic lines choose JB so that the wider of the two access streams
+  // starts on a 16-node (128-byte) boundary along xi: the finishing accesses
+  // (sum, U^n, U, 1/J, output) in the last sweep along xi (JB = 0), the
+  // loads otherwise (JB = -4); n interfaces.  Bounded lines: JB = 0,
+  // interfaces 0 .. n-2, nodes outside [0, n-1] never loaded.
+  constexpr int JBP = (DIR == 0 && (MODE == MODE_RK || MODE == MODE_DUDT)) ? 0 : -4;
+  const int JB = per ? JBP : 0;
+  const int nif = per ? n : n - 1;             // interfaces of the line
+  const int mmax = per ? JB + n + 3 : n - 1;   // last node the chunks load (the prologue covers JB-3 .. JB+3)
   // Prologue: nodes JB-3 .. JB+3 of every line.
   if (A.inviscid && t < 7 * SW_W) {
     const int pm = (DIR == 0) ? (t % 7) : (t / SW_W);
