@@ -42,7 +42,8 @@ extern "C" {
 
 /* Inviscid schemes (Sec. 2.2.3, Table 2). */
 #define OCFD_SCHEME_WENO7 0   /* seventh-order WENO at every interface */
-#define OCFD_SCHEME_HYBRID 1  /* sensor-selected low-dissipation / WENO7 (eq 41-43) */
+#define OCFD_SCHEME_HYBRID 1  /* sensor-selected low-dissipation / WENO7 (eq 41-43); with
+                                 three_way, WENO5 above theta2 */
 /* Low-dissipation stencil of the hybrid scheme. */
 #define OCFD_LOWDISS_UD7 0    /* seventh-order upwind, eq 41 */
 #define OCFD_LOWDISS_C8 1     /* eighth-order central */
@@ -116,7 +117,8 @@ typedef struct ocfd_params {
   int32_t sensor;          /* hybrid only: OCFD_SENSOR_PLAIN (eq 42-43) or OCFD_SENSOR_LEARNED */
   int32_t sensor_every;    /* learned sensor: re-evaluate the flags every this many substeps (>= 1) */
   int32_t audit_every;     /* learned sensor: compare with the plain sensor every this many substeps (0: never) */
-  int32_t reserved[1];     /* must be zero */
+  int32_t three_way;       /* hybrid with the plain sensor: interfaces with max theta > theta2 take
+                              fifth-order WENO (eq 43, Table 2), 0 or 1 */
 } ocfd_params;
 
 typedef struct ocfd_solver ocfd_solver;
@@ -189,8 +191,8 @@ int ocfd_dudt(ocfd_solver* s, const double* U_dev, double* dudt_dev, int32_t par
 int ocfd_reduce(ocfd_solver* s, double dt, double* out_host);
 
 /* Per-interface scheme flags flags_dev [3][N] (byte: 0 low-dissipation,
-   1 WENO7) used by the hybrid scheme instead of the sensor, or NULL to go back
-   to the sensor. */
+   1 WENO7, 2 WENO5) used by the hybrid scheme instead of the sensor, or NULL
+   to go back to the sensor.  The caller keeps the buffer alive while set. */
 int ocfd_set_flags(ocfd_solver* s, const uint8_t* flags_dev);
 
 /* Kernel timing: when enabled, every launch is bracketed by HIP events on the
@@ -223,8 +225,9 @@ int ocfd_sensor_set_params(ocfd_solver* s, const float* params_host);
 int ocfd_sensor_get_params(ocfd_solver* s, float* params_host);
 /* Decision threshold tau (default 0.5; ocfd_sensor_calibrate sets it). */
 int ocfd_sensor_set_threshold(ocfd_solver* s, double tau);
-/* Flags [3][N] (1 = WENO7) of the state U_dev by the plain sensor or by the
-   network, written to flags_dev.  Errors: STATE (network not set). */
+/* Flags [3][N] of the state U_dev by the plain sensor (0 low-dissipation,
+   1 WENO7, 2 WENO5 when three_way) or by the network (0 / 1), written to
+   flags_dev.  Errors: STATE (network not set). */
 int ocfd_sensor_flags(ocfd_solver* s, const double* U_dev, int32_t which, uint8_t* flags_dev);
 /* Caller-owned device buffer for training samples: each sample is 32 bf16
    inputs, a label, a weight and bookkeeping, ocfd_sensor_sample_bytes(cap)

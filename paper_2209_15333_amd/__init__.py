@@ -45,7 +45,7 @@ class ocfd_params(ctypes.Structure):
         ("viscous", ctypes.c_int32), ("scheme", ctypes.c_int32), ("lowdiss", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("sensor", ctypes.c_int32), ("sensor_every", ctypes.c_int32), ("audit_every", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 1),
+        ("three_way", ctypes.c_int32),
     ]
 
 
@@ -314,6 +314,7 @@ def params_from(case, **overrides) -> ocfd_params:
     p.sensor = OCFD_SENSOR_LEARNED if getattr(case, "sensor", "plain") == "learned" else OCFD_SENSOR_PLAIN
     p.sensor_every = int(getattr(case, "sensor_every", 1))
     p.audit_every = int(getattr(case, "audit_every", 0))
+    p.three_way = int(bool(getattr(case, "three_way", False)))
     for k, v in overrides.items():
         setattr(p, k, v)
     return p

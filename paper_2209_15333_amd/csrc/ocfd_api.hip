@@ -114,7 +114,8 @@ bool valid_params(const ocfd_params* p, std::string* why) {
   if (p->precision != OCFD_PREC_FP64 && p->precision != OCFD_PREC_MIXED) { *why = "unknown precision"; return false; }
   if (p->sensor != OCFD_SENSOR_PLAIN && p->sensor != OCFD_SENSOR_LEARNED) { *why = "unknown sensor"; return false; }
   if (p->sensor_every < 0 || p->audit_every < 0) { *why = "sensor_every and audit_every must be >= 0"; return false; }
-  if (p->reserved[0] != 0) { *why = "reserved fields must be zero"; return false; }
+  if (p->three_way != 0 && p->three_way != 1) { *why = "three_way must be 0 or 1"; return false; }
+  if (p->three_way && !(p->theta2 >= p->theta1)) { *why = "three_way needs theta2 >= theta1"; return false; }
   int ninflow = 0;
   const int n[3] = {p->nx, p->ny, p->nz};
   for (int d = 0; d < 3; ++d) {
@@ -188,6 +189,8 @@ void setup_geo_phys(ocfd_solver* s) {
   ph.suth = p.viscous ? p.suth / p.Tref : 0.0;
   ph.eps = p.weno_eps;
   ph.theta1 = p.theta1;
+  ph.theta2 = p.theta2;
+  ph.three_way = p.three_way;
   for (int d = 0; d < 3; ++d) {
     ph.h[d] = p.h[d];
     ph.ih[d] = 1.0 / p.h[d];
@@ -314,7 +317,7 @@ int learned_flags(ocfd_solver* s, const double* Ucur, bool count_substep) {
   if (count_substep && s->p.audit_every > 0 && k % s->p.audit_every == 0) {
     int rc = plain_theta(s, Ucur, false);
     if (rc) return rc;
-    e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
+    e = launch_plain_flags(s->g, s->ph, s->theta, s->pflags, s->st);
     if (e == hipSuccess) e = launch_flag_stats(s->g, s->pflags, s->lflags, s->cnt, COUNT_BLOCKS, s->st);
     std::vector<unsigned long long> c(COUNT_BLOCKS * 4);
     if (e == hipSuccess)
@@ -368,7 +371,7 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
     Timed tm(s, OCFD_K_OTHER);
     int rc = plain_theta(s, Ucur, visc);
     if (rc) return rc;
-    e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
+    e = launch_plain_flags(s->g, s->ph, s->theta, s->pflags, s->st);
     if (e != hipSuccess) return hip_fail(s, e, "sensor flags kernel");
     flags = s->pflags;
   }
@@ -709,7 +712,7 @@ int ocfd_sensor_flags(ocfd_solver* s, const double* U, int32_t which, uint8_t* f
   if (which == OCFD_SENSOR_PLAIN) {
     rc = plain_theta(s, U, false);
     if (rc) return rc;
-    e = launch_plain_flags(s->g, s->ph.theta1, s->theta, flags, s->st);
+    e = launch_plain_flags(s->g, s->ph, s->theta, flags, s->st);
   } else if (which == OCFD_SENSOR_LEARNED) {
     if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "no network parameters set");
     e = launch_features(s->g, s->ph, U, s->met, s->feat, s->st);
@@ -754,7 +757,7 @@ int ocfd_sensor_collect(ocfd_solver* s, uint64_t seed, double keep_weno, double 
   const double* U = s->Ub[s->stage];
   rc = plain_theta(s, U, false);
   if (rc) return rc;
-  hipError_t e = launch_plain_flags(s->g, s->ph.theta1, s->theta, s->pflags, s->st);
+  hipError_t e = launch_plain_flags(s->g, s->ph, s->theta, s->pflags, s->st);
   if (e == hipSuccess) e = launch_features(s->g, s->ph, U, s->met, s->feat, s->st);
   if (e == hipSuccess) e = launch_collect_count(s->g, s->pflags, seed, tp, tl, s->cnt, COUNT_BLOCKS, s->st);
   std::vector<unsigned long long> c(COUNT_BLOCKS);

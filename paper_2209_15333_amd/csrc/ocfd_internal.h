@@ -100,7 +100,8 @@ struct Phys {
   double kcoef;             // 1 / ((gamma-1) Ma^2 Pr Re): heat conductivity per unit mu (eq 14)
   double suth;              // Sutherland constant / Tref (eq 15)
   double eps;               // WENO epsilon
-  double theta1;            // sensor threshold (eq 43)
+  double theta1, theta2;    // sensor thresholds (eq 43)
+  int three_way;            // plain sensor marks max theta > theta2 with flag 2 (WENO5)
   double h[3], ih[3];       // computational spacing and its inverse
   double period[3];
 };
@@ -155,7 +156,9 @@ hipError_t launch_reduce(const Geo& g, const Phys& ph, const double* U, const do
 int reduce_blocks(const Geo& g);
 
 // Sensors (ocfd_sensor.hip).
-hipError_t launch_plain_flags(const Geo& g, double theta1, const double* theta, uint8_t* flags, hipStream_t st);
+// Interface flags from theta: 0 low-dissipation (max theta over the 8-node
+// window <= theta1), 1 WENO7, 2 WENO5 (three_way and max theta > theta2).
+hipError_t launch_plain_flags(const Geo& g, const Phys& ph, const double* theta, uint8_t* flags, hipStream_t st);
 hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, uint16_t* feat,
                            hipStream_t st);
 hipError_t launch_mlp_flags(const Geo& g, const uint16_t* feat, const float* P, float tau, uint8_t* flags,

@@ -43,14 +43,16 @@ __device__ __forceinline__ v4f mfma16(const v4bf& a, const v4bf& b, const v4f& c
 
 // ---------------------------------------------------------------------------
 // Plain sensor flags: interface j+1/2 along d is low-dissipation iff the node
-// sensor theta is <= theta1 at every node j-3 .. j+4.
+// sensor theta is <= theta1 at every node j-3 .. j+4; otherwise WENO7, or
+// WENO5 in the three-way hybrid when the window maximum exceeds theta2.
 // ---------------------------------------------------------------------------
 // Each thread marches one (xi, eta) column through a zeta segment keeping
 // theta of planes k-3 .. k+4 in registers; the xi and eta windows are read
 // from the plane (cached).  Positions outside a bounded line count as 0
 // (theta >= 0, so the maximum is the one over the nodes that exist).
-__global__ __launch_bounds__(256) void k_plain_flags(const Geo g, const ZMarch zm, double theta1,
-                                                     const double* __restrict__ theta, uint8_t* __restrict__ flags) {
+__global__ __launch_bounds__(256) void k_plain_flags(const Geo g, const ZMarch zm, double theta1, double theta2,
+                                                     int three_way, const double* __restrict__ theta,
+                                                     uint8_t* __restrict__ flags) {
   int i, j, k0, k1;
   if (!zmarch_column(zm, g.n, &i, &j, &k0, &k1)) return;
   const int nz = g.n[2];
@@ -85,17 +87,19 @@ __global__ __launch_bounds__(256) void k_plain_flags(const Geo g, const ZMarch z
     double mz = 0.0;
 #pragma unroll
     for (int o = 0; o < 8; ++o) mz = fmax(mz, w[o]);
-    flags[id] = inplane(id, 0, i) <= theta1 ? 0 : 1;
-    flags[g.N + id] = inplane(id, 1, j) <= theta1 ? 0 : 1;
-    flags[2 * g.N + id] = mz <= theta1 ? 0 : 1;
+    auto flag = [&](double mx) -> uint8_t { return mx <= theta1 ? 0 : ((three_way && mx > theta2) ? 2 : 1); };
+    flags[id] = flag(inplane(id, 0, i));
+    flags[g.N + id] = flag(inplane(id, 1, j));
+    flags[2 * g.N + id] = flag(mz);
 #pragma unroll
     for (int o = 0; o < 7; ++o) w[o] = w[o + 1];
   }
 }
 
-hipError_t launch_plain_flags(const Geo& g, double theta1, const double* theta, uint8_t* flags, hipStream_t st) {
+hipError_t launch_plain_flags(const Geo& g, const Phys& ph, const double* theta, uint8_t* flags, hipStream_t st) {
   const ZMarch zm = make_zmarch(g.n);
-  hipLaunchKernelGGL(k_plain_flags, dim3(zm.blocks), dim3(256), 0, st, g, zm, theta1, theta, flags);
+  hipLaunchKernelGGL(k_plain_flags, dim3(zm.blocks), dim3(256), 0, st, g, zm, ph.theta1, ph.theta2, ph.three_way,
+                     theta, flags);
   return hipGetLastError();
 }
 
@@ -604,7 +608,7 @@ __global__ __launch_bounds__(CT) void k_collect_write(const Geo g, const uint8_t
           xs[t] = feat[id + (long long)(wrapn(pos[d] + t - 3, g.n[d]) - pos[d]) * g.s[d]];  // window inside
         uint2* dst = (uint2*)(X + o * 32);
         for (int t = 0; t < 8; ++t) dst[t] = xs[t];
-        y[o] = flags[k];
+        y[o] = flags[k] ? 1 : 0;
         w[o] = 1.f;
       }
     }
@@ -645,7 +649,7 @@ __global__ __launch_bounds__(CT) void k_flag_stats(const Geo g, const uint8_t* _
       const uint8_t z = fb[k];
       c[1] += (!x && z) ? 1 : 0;
       c[2] += (x && !z) ? 1 : 0;
-      c[3] += (x != z) ? 1 : 0;
+      c[3] += ((x != 0) != (z != 0)) ? 1 : 0;
     }
   }
   for (int q = 0; q < 4; ++q) sh[q][threadIdx.x] = c[q];

@@ -197,8 +197,9 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   NodeIn ahead;
   bool have = A.inviscid && gcol_ok && JB + 4 + gs <= mmax;
   if (have) ahead = fetch(JB + 4 + gs, gc);
-  // Reconstruction of interface j of line col into dst (WENO7 or low-dissipation stencil).
-  auto reconstruct = [&](int j, int col, bool low, double* dst) {
+  // Reconstruction of interface j of line col into dst: kind 0 the
+  // low-dissipation stencil, 1 WENO7, 2 WENO5 (three-way hybrid).
+  auto reconstruct = [&](int j, int col, int kind, double* dst) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       const R* P = ring + col + q * SW_W;
@@ -215,13 +216,16 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
         // f+: substencils j-2..j, j-1..j+1, j..j+2; f- (mirrored): j+3..j+1, j+2..j, j+1..j-1
         F = (double)weno5m<R>(fp(-2), fp(-1), fp(0), fp(1), fp(2), eps, in(-2), in(-1), in(2)) +
             (double)weno5m<R>(fm(3), fm(2), fm(1), fm(0), fm(-1), eps, in(3), in(2), in(-1));
-      } else if (HYB && low) {
+      } else if (HYB && kind == 0) {
         if (A.lowdiss == OCFD_LOWDISS_C8)
           F = (double)c8<R>(RP(-3) + RM(-3), RP(-2) + RM(-2), RP(-1) + RM(-1), RP(0) + RM(0), RP(1) + RM(1),
                             RP(2) + RM(2), RP(3) + RM(3), RP(4) + RM(4));
         else
           F = (double)ud7<R>(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3)) +
               (double)ud7<R>(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2));
+      } else if (HYB && kind == 2) {
+        F = (double)weno5m<R>(RP(-2), RP(-1), RP(0), RP(1), RP(2), eps, true, true, true) +
+            (double)weno5m<R>(RM(3), RM(2), RM(1), RM(0), RM(-1), eps, true, true, true);
       } else {
         F = (double)weno7<R>(RP(-3), RP(-2), RP(-1), RP(0), RP(1), RP(2), RP(3), eps) +
             (double)weno7<R>(RM(4), RM(3), RM(2), RM(1), RM(0), RM(-1), RM(-2), eps);
@@ -245,24 +249,24 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
       // Low-dissipation interfaces are done in place; WENO interfaces go to a
       // work list so that whole waves run the WENO code (no divergence).
       if (act) {
-        bool low;
+        int kind;
         if (!per && (j < 3 || j > n - 5))
-          low = false;   // boundary closure: always the WENO5 path
+          kind = 1;   // boundary closure: always the masked WENO5 path
         else
-          low = A.flags[DIR * N + base + (long long)rc * sc + (long long)(n >= 8 ? wrap1(j, n) : wrap(j, n)) * sd] == 0;
-        if (low)
-          reconstruct(j, rc, true, fh + (rs + 1) * FHS + rc);
+          kind = A.flags[DIR * N + base + (long long)rc * sc + (long long)(n >= 8 ? wrap1(j, n) : wrap(j, n)) * sd];
+        if (kind == 0)
+          reconstruct(j, rc, 0, fh + (rs + 1) * FHS + rc);
         else
-          wl[atomicAdd(&wl_n, 1)] = (short)t;
+          wl[atomicAdd(&wl_n, 1)] = (short)(t | (kind == 2 ? 512 : 0));
       }
       __syncthreads();
       if (t < wl_n) {
-        const int tt = wl[t];
+        const int tt = wl[t] & 511;
         const int s2 = tt / SW_W, c2 = tt & (SW_W - 1);
-        reconstruct(j0 + s2, c2, false, fh + (s2 + 1) * FHS + c2);
+        reconstruct(j0 + s2, c2, (wl[t] & 512) ? 2 : 1, fh + (s2 + 1) * FHS + c2);
       }
     } else if (act) {
-      reconstruct(j, rc, false, fh + (rs + 1) * FHS + rc);
+      reconstruct(j, rc, 1, fh + (rs + 1) * FHS + rc);
     }
     __syncthreads();
     if (c == 0 && t < 5 * SW_W) fh0[(t / SW_W) * SW_W + (t % SW_W)] = fh[FHS + (t / SW_W) * SW_W + (t % SW_W)];

@@ -271,3 +271,26 @@ def test_full_size_conservation(pk, torch_cuda):
     assert abs(r1[0] - r0[0]) <= 1e-13 * abs(r0[0])
     assert abs(r1[4] - r0[4]) <= 1e-13 * abs(r0[4])
     assert r1[8] == 0.0
+
+
+def test_three_way_hybrid(pk, torch_cuda, orc):
+    """Three-way hybrid (eq 43): low-dissipation, WENO7, and WENO5 where the
+    window maximum of theta exceeds theta2; the GPU's own flags and two full
+    Runge-Kutta steps against the oracle."""
+    case = workloads.taylor_green(shape=(40, 24, 20), distorted=True)
+    case.scheme, case.lowdiss, case.three_way = "hybrid", "c8", True
+    case.U0 = _local_noise(case, 0.08, 5)
+    P, met = _orc(orc, case)
+    theta, ref_flags = orc.sensor(P, case.U0)
+    frac = [(ref_flags == v).mean() for v in (0, 1, 2)]
+    print("three-way flag fractions (low, WENO7, WENO5)", frac, flush=True)
+    assert min(frac) > 0.01
+    s = _solver(pk, torch_cuda, case)
+    fl = torch_cuda.zeros((3,) + case.U0.shape[1:], dtype=torch_cuda.uint8, device="cuda")
+    pk.ocfd_sensor_flags(s.h, _dev(torch_cuda, case.U0), pk.OCFD_SENSOR_PLAIN, fl)
+    got = fl.cpu().numpy()
+    near = (np.abs(theta - case.theta1) < 1e-12) | (np.abs(theta - case.theta2) < 1e-12)
+    assert np.array_equal(got, ref_flags) or near.any()
+    s.advance(6, case.dt)
+    ref, _, _ = orc.advance(P, met, case.U0, 6, case.dt)
+    _assert_close(s.state().cpu().numpy(), ref, what="three-way hybrid 6 substeps")
