@@ -46,11 +46,20 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   constexpr bool anyb = BND != 0;         // some direction bounded
   constexpr int SLOT = NVAL * SW_W + 1;   // padded against bank conflicts
   constexpr int FHS = 5 * SW_W + 1;
+  constexpr int FVS = 4 * SW_W + 1;
+  // Viscous-flux neighbours staged in an LDS ring (16.6 KB per workgroup):
+  // pays where the sweep is bound by memory latency (FP32 reconstruction,
+  // hybrid); the FP64 WENO7 sweep keeps three workgroups per CU instead and
+  // reads them from memory.
+  constexpr bool FVR = HYB || sizeof(R) == 4;
   __shared__ R ring[RING * SLOT];
   __shared__ double fh[(SW_S + 1) * FHS];  // fh[0]: carried flux; fh[s+1]: interface j0+s
   __shared__ double fh0[FHS];             // flux at 1/2, for node 0 of a periodic line
   __shared__ int wl_n;                    // hybrid: WENO work list of this chunk
   __shared__ short wl[SW_T];
+  // the viscous flux of direction DIR of every ring node (FVR kernels in
+  // viscous runs: [RING][4 * SW_W + 1] doubles, dynamic; zero bytes otherwise)
+  extern __shared__ double fvr[];
 
   const int n = A.g.n[DIR];
   const int ncol = A.g.n[CD];
@@ -77,6 +86,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   struct NodeIn {
     double U[5];
     double a[3];
+    double fv[4];
   };
   auto fetch = [&](int m, int col) {
     NodeIn r;
@@ -86,63 +96,99 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     for (int q = 0; q < 5; ++q) r.U[q] = A.U[q * N + id];
 #pragma unroll
     for (int q = 0; q < 3; ++q) r.a[q] = A.met[(3 * DIR + q) * N + id];
+    if (FVR && A.viscous) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r.fv[q] = A.Fv[(long long)(4 * DIR + q) * N + id];
+    }
     return r;
   };
   // Primitive recovery and Steger-Warming split of node m into the ring.
   auto split_store = [&](int m, int col, const NodeIn& in) {
-    const double rho = in.U[0];
-    const double ir = rcp_r<double>(rho);
-    const double u = in.U[1] * ir;
-    const double v = in.U[2] * ir;
-    const double w = in.U[3] * ir;
-    const double p = A.ph.gm1 * (in.U[4] - 0.5 * rho * (u * u + v * v + w * w));
-    R fp[5], fm[5];
-    sw_split<R>(A.ph, (R)rho, (R)ir, (R)u, (R)v, (R)w, (R)p, (R)in.a[0], (R)in.a[1], (R)in.a[2], fp, fm);
-    R* slot = ring + (m & (RING - 1)) * SLOT + col;
+    if (A.inviscid) {
+      const double rho = in.U[0];
+      const double ir = rcp_r<double>(rho);
+      const double u = in.U[1] * ir;
+      const double v = in.U[2] * ir;
+      const double w = in.U[3] * ir;
+      const double p = A.ph.gm1 * (in.U[4] - 0.5 * rho * (u * u + v * v + w * w));
+      R fp[5], fm[5];
+      sw_split<R>(A.ph, (R)rho, (R)ir, (R)u, (R)v, (R)w, (R)p, (R)in.a[0], (R)in.a[1], (R)in.a[2], fp, fm);
+      R* slot = ring + (m & (RING - 1)) * SLOT + col;
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      slot[q * SW_W] = fp[q];
-      slot[(5 + q) * SW_W] = fm[q];
+      for (int q = 0; q < 5; ++q) {
+        slot[q * SW_W] = fp[q];
+        slot[(5 + q) * SW_W] = fm[q];
+      }
     }
+    if (FVR && A.viscous) {
+      double* fs = fvr + (m & (RING - 1)) * FVS + col;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fs[q * SW_W] = in.fv[q];
+    }
+  };
+
+  // What the finishing step of a node reads besides the fluxes: the sum of
+  // the previous sweeps, U^n, U and 1/J as the mode needs them.  Loaded at the
+  // start of the chunk so that the loads overlap the split and the
+  // reconstruction (barriers wait for LDS only, not for global loads).
+  struct EmitIn {
+    double s[5];
+    double un[5];
+    double u[5];
+    double ij;
+  };
+  auto emit_load = [&](int j, int col) {
+    EmitIn e;
+    const long long id = base + (long long)col * sc + (long long)j * sd;
+    if (MODE != MODE_SET) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) e.s[q] = A.rhs[q * N + id];
+    }
+    if (MODE == MODE_RK) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        e.un[q] = A.Un[q * N + id];
+        e.u[q] = A.U[q * N + id];
+      }
+    }
+    if (MODE == MODE_RK || MODE == MODE_DUDT) e.ij = A.met[9 * N + id];
+    return e;
   };
 
   // Output of node j of line col from its two interface fluxes (inv: this
   // node has both interfaces along DIR, i.e. it is not an end of a
   // non-periodic line).
-  auto emit = [&](int j, int col, const double* Fr, const double* Fl, bool inv) {
+  // jr: the node's unwrapped position, which indexes the rings; ringfv: its
+  // viscous-flux neighbours are in the LDS ring (false only for the first node
+  // of a periodic line, finished after the last chunk, which reads them from
+  // memory).
+  auto emit = [&](int j, int jr, int col, const double* Fr, const double* Fl, bool inv, bool ringfv,
+                  const EmitIn& e) {
     const long long id = base + (long long)col * sc + (long long)j * sd;
     double r[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) r[q] = (A.inviscid && inv) ? -(Fr[q * SW_W] - Fl[q * SW_W]) * ih : 0.0;
-    if (A.viscous) {
-      if (per) {
-        // offsets of the six neighbours along the line (wrapped at the seam)
-        auto off = [&](int k) {
-          const int p = j + k;
-          return (long long)((n >= 8 ? wrap1(p, n) : wrap(p, n)) - j) * sd;
-        };
-        const long long o1p = off(1), o1m = off(-1), o2p = off(2), o2m = off(-2), o3p = off(3), o3m = off(-3);
+    if (A.viscous && inv) {
+      // F(q, k): component q of the viscous flux at node jr + k
+      auto F = [&](int q, int k) {
+        if (ringfv) return fvr[((jr + k) & (RING - 1)) * FVS + q * SW_W + col];
+        const int p = j + k;
+        const int w = per ? (n >= 8 ? wrap1(p, n) : wrap(p, n)) : p;
+        return A.Fv[(long long)(4 * DIR + q) * N + id + (long long)(w - j) * sd];
+      };
+      // sixth order inside, then fourth and second order toward the ends of a
+      // bounded line (Sec. 2.3)
+      const int dist = per ? 3 : min(j, n - 1 - j);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double* F = A.Fv + (long long)(4 * DIR + q) * N + id;
-          const double d = 0.75 * (F[o1p] - F[o1m]) - 0.15 * (F[o2p] - F[o2m]) + (1.0 / 60.0) * (F[o3p] - F[o3m]);
-          r[q + 1] += d * ih;
-        }
-      } else if (inv) {
-        // sixth order inside, then fourth and second order toward the ends (Sec. 2.3)
-        const int dist = min(j, n - 1 - j);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const double* F = A.Fv + (long long)(4 * DIR + q) * N + id;
-          double d;
-          if (dist == 1)
-            d = 0.5 * (F[sd] - F[-sd]);
-          else if (dist == 2)
-            d = (2.0 / 3.0) * (F[sd] - F[-sd]) - (1.0 / 12.0) * (F[2 * sd] - F[-2 * sd]);
-          else
-            d = 0.75 * (F[sd] - F[-sd]) - 0.15 * (F[2 * sd] - F[-2 * sd]) + (1.0 / 60.0) * (F[3 * sd] - F[-3 * sd]);
-          r[q + 1] += d * ih;
-        }
+      for (int q = 0; q < 4; ++q) {
+        double d;
+        if (dist == 1)
+          d = 0.5 * (F(q, 1) - F(q, -1));
+        else if (dist == 2)
+          d = (2.0 / 3.0) * (F(q, 1) - F(q, -1)) - (1.0 / 12.0) * (F(q, 2) - F(q, -2));
+        else
+          d = 0.75 * (F(q, 1) - F(q, -1)) - 0.15 * (F(q, 2) - F(q, -2)) + (1.0 / 60.0) * (F(q, 3) - F(q, -3));
+        r[q + 1] += d * ih;
       }
     }
     if (MODE == MODE_SET) {
@@ -150,7 +196,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
       for (int q = 0; q < 5; ++q) A.rhs[q * N + id] = r[q];
     } else if (MODE == MODE_ADD) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) A.rhs[q * N + id] += r[q];
+      for (int q = 0; q < 5; ++q) A.rhs[q * N + id] = e.s[q] + r[q];
     } else {
       // nodes on a face of a non-periodic direction take dU/dt = 0 (their
       // value is set by the boundary condition after the stage)
@@ -163,12 +209,12 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
               (!A.g.periodic[1] && (p1 == 0 || p1 == A.g.n[1] - 1)) ||
               (!A.g.periodic[2] && (p2 == 0 || p2 == A.g.n[2] - 1));
       }
-      const double ij = 1.0 / A.met[9 * N + id];
+      const double ij = 1.0 / e.ij;
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        const double L = bnd ? 0.0 : (A.rhs[q * N + id] + r[q]) * ij;
+        const double L = bnd ? 0.0 : (e.s[q] + r[q]) * ij;
         if (MODE == MODE_RK)
-          A.out[q * N + id] = A.a * A.Un[q * N + id] + A.b * (A.U[q * N + id] + A.dt * L);
+          A.out[q * N + id] = A.a * e.un[q] + A.b * (e.u[q] + A.dt * L);
         else
           A.out[q * N + id] = L;
       }
@@ -188,14 +234,15 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   const int nif = per ? n : n - 1;             // interfaces of the line
   const int mmax = per ? JB + n + 3 : n - 1;   // last node the chunks load (the prologue covers JB-3 .. JB+3)
   // Prologue: nodes JB-3 .. JB+3 of every line.
-  if (A.inviscid && t < 7 * SW_W) {
+  const bool load = A.inviscid || A.viscous;   // the rings are filled for either part
+  if (load && t < 7 * SW_W) {
     const int pm = (DIR == 0) ? (t % 7) : (t / SW_W);
     const int pc = (DIR == 0) ? (t / 7) : (t % SW_W);
     const int m = JB + pm - 3;
     if (col0 + pc < ncol && (per || (m >= 0 && m < n))) split_store(m, pc, fetch(m, pc));
   }
   NodeIn ahead;
-  bool have = A.inviscid && gcol_ok && JB + 4 + gs <= mmax;
+  bool have = load && gcol_ok && JB + 4 + gs <= mmax;
   if (have) ahead = fetch(JB + 4 + gs, gc);
   // Reconstruction of interface j of line col into dst: kind 0 the
   // low-dissipation stencil, 1 WENO7, 2 WENO5 (three-way hybrid).
@@ -238,10 +285,17 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
 
   for (int c = 0; c < nchunks; ++c) {
     const int j0 = JB + c * SW_S;
+    // the node this thread finishes in this chunk (periodic: node JB is
+    // finished after the last chunk), and its inputs
+    const int jraw = j0 + gs;
+    const bool fin = gcol_ok && (per ? (c * SW_S + gs < n && (c > 0 || gs > 0)) : jraw < n);
+    const int jfin = per ? (n >= 8 ? wrap1(jraw, n) : wrap(jraw, n)) : jraw;
+    EmitIn ein;
+    if (fin) ein = emit_load(jfin, gc);
     if (have) split_store(j0 + 4 + gs, gc, ahead);
     if (HYB && t == 0) wl_n = 0;
     __syncthreads();
-    have = A.inviscid && gcol_ok && c + 1 < nchunks && j0 + SW_S + 4 + gs <= mmax;
+    have = load && gcol_ok && c + 1 < nchunks && j0 + SW_S + 4 + gs <= mmax;
     if (have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
     const int j = j0 + rs;
     const bool act = A.inviscid && rcol_ok && c * SW_S + rs < nif;
@@ -270,13 +324,9 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     }
     __syncthreads();
     if (c == 0 && t < 5 * SW_W) fh0[(t / SW_W) * SW_W + (t % SW_W)] = fh[FHS + (t / SW_W) * SW_W + (t % SW_W)];
-    if (per) {
-      if (gcol_ok && c * SW_S + gs < n && (c > 0 || gs > 0))
-        emit(n >= 8 ? wrap1(j0 + gs, n) : wrap(j0 + gs, n), gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc, true);
-    } else {
-      const int jn = j0 + gs;
-      if (gcol_ok && jn < n) emit(jn, gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc, jn > 0 && jn < n - 1);
-    }
+    if (fin)
+      emit(jfin, jraw, gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc, per || (jraw > 0 && jraw < n - 1), FVR,
+           ein);
     __syncthreads();
     if (t < 5 * SW_W) {
       const int last = min(SW_S, nif - c * SW_S);
@@ -285,21 +335,26 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   }
   __syncthreads();
   // The periodic line's first node (JB) with the wrapped flux carried out of the last chunk.
-  if (per && gs == 0 && gcol_ok) emit(wrap(JB, n), gc, fh0 + gc, fh + gc, true);
+  if (per && gs == 0 && gcol_ok) {
+    const int j = wrap(JB, n);
+    emit(j, JB, gc, fh0 + gc, fh + gc, true, false, emit_load(j, gc));
+  }
 }
 
+// Dynamic LDS: the viscous-flux ring of the FP32 and hybrid kernels.
 template <int DIR, int MODE, int BND>
 static void launch_sweep_b(const SweepArgs& a, dim3 grid, hipStream_t st) {
+  const size_t lds = (a.viscous && (a.mixed || a.hybrid)) ? (size_t)RING * (4 * SW_W + 1) * sizeof(double) : 0;
   if (a.mixed) {
     if (a.hybrid)
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, float, BND>), grid, dim3(SW_T), 0, st, a);
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, float, BND>), grid, dim3(SW_T), lds, st, a);
     else
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, float, BND>), grid, dim3(SW_T), 0, st, a);
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, float, BND>), grid, dim3(SW_T), lds, st, a);
   } else {
     if (a.hybrid)
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, double, BND>), grid, dim3(SW_T), 0, st, a);
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, double, BND>), grid, dim3(SW_T), lds, st, a);
     else
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, double, BND>), grid, dim3(SW_T), 0, st, a);
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, double, BND>), grid, dim3(SW_T), lds, st, a);
   }
 }
 
