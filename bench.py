@@ -132,7 +132,7 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
     for k in range(develop // every):
         s.advance(every, case.dt)
         if (k + 1) * every > first:
-            total = pk.ocfd_sensor_collect(s.h, 5000 + k, 0.1, 0.001)
+            total = pk.ocfd_sensor_collect(s.h, 5000 + k, 1.0, 0.001)
     torch.cuda.synchronize()
     t_dev = time.perf_counter() - t0
     _log(f"hit{n}: developed {develop} substeps in {t_dev:.1f} s, {total} samples")

@@ -241,7 +241,9 @@ int ocfd_sensor_bind_samples(ocfd_solver* s, void* samples_dev, size_t bytes);
 int ocfd_sensor_collect(ocfd_solver* s, uint64_t seed, double keep_weno, double keep_low, int64_t* total_host);
 /* Train on the first (1 - holdout) of the stored samples: `epochs` passes of
    mini-batches of `batch` samples in a seeded random order, Adam with
-   learning rate lr.  stats_host[4] = loss of the first and of the last
+   learning rate lr, weighted binary cross-entropy with class balance (each
+   WENO sample weighs n_low / n_weno, at most 1000; the weights are written
+   into the sample buffer).  stats_host[4] = loss of the first and of the last
    epoch, number of steps, training samples.  Synchronises. */
 int ocfd_sensor_train(ocfd_solver* s, int32_t epochs, int32_t batch, float lr, uint64_t seed, double holdout,
                       double* stats_host);

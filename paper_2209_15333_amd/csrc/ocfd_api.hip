@@ -803,10 +803,22 @@ int ocfd_sensor_train(ocfd_solver* s, int32_t epochs, int32_t batch, float lr, u
   const long long C = s->smp_cap;
   const long long ntrain = (long long)((1.0 - holdout) * (double)s->smp_n);
   if (ntrain < batch) return fail(s, OCFD_ERR_STATE, "%lld training samples, fewer than one batch", ntrain);
-  std::vector<float> hw(ntrain);
-  hipError_t e = hipMemcpyAsync(hw.data(), s->smp + smp_off_w(C), ntrain * sizeof(float), hipMemcpyDeviceToHost, s->st);
+  // Class balance: WENO samples are rare (a fraction of a percent of the
+  // interfaces of a resolved flow), so each class gets the same total weight
+  // (WENO samples weigh n_low / n_weno, at most 1000; low-dissipation ones 1).
+  std::vector<uint8_t> hy(ntrain);
+  hipError_t e = hipMemcpyAsync(hy.data(), s->smp + smp_off_y(C), ntrain, hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-  if (e != hipSuccess) return hip_fail(s, e, "weight download");
+  if (e != hipSuccess) return hip_fail(s, e, "label download");
+  long long npos = 0;
+  for (long long k = 0; k < ntrain; ++k) npos += hy[k] ? 1 : 0;
+  const long long nneg = ntrain - npos;
+  const float wpos = (npos > 0 && nneg > 0) ? (float)std::min(1000.0, (double)nneg / (double)npos) : 1.f;
+  std::vector<float> hw(ntrain);
+  for (long long k = 0; k < ntrain; ++k) hw[k] = hy[k] ? wpos : 1.f;
+  e = hipMemcpyAsync(s->smp + smp_off_w(C), hw.data(), ntrain * sizeof(float), hipMemcpyHostToDevice, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "weight upload");
   std::vector<int> perm(ntrain);
   std::mt19937_64 rng(seed);
   int* didx = (int*)(s->smp + smp_off_idx(C));
