@@ -116,67 +116,101 @@ hipError_t launch_plain_flags(const Geo& g, const Phys& ph, const double* theta,
 // ---------------------------------------------------------------------------
 // Stored as bf16 (round to nearest even of the FP32 value), four per node
 // (node-major, 8 bytes), the operand format of the perceptron.
-__global__ __launch_bounds__(256) void k_features(const Geo g, const Phys ph, const double* __restrict__ U,
-                                                  const double* __restrict__ met, uint2* __restrict__ feat) {
-  const int pos[3] = {(int)(blockIdx.x * 64 + threadIdx.x), (int)(blockIdx.y * 4 + threadIdx.y), (int)blockIdx.z};
-  if (pos[0] >= g.n[0] || pos[1] >= g.n[1]) return;
-  const long long id = pos[0] + g.s[1] * pos[1] + g.s[2] * pos[2];
-  const long long N = g.N;
+// Primitives (rho, u, v, w, p) of node id.
+__device__ __forceinline__ void prim5(const Phys& ph, const double* __restrict__ U, long long N, long long id,
+                                      double q[5]) {
   const double rho = U[id];
-  const double ir0 = 1.0 / rho;
-  const double u = U[N + id] * ir0, v = U[2 * N + id] * ir0, w = U[3 * N + id] * ir0;
-  const double p = ph.gm1 * (U[4 * N + id] - 0.5 * rho * (u * u + v * v + w * w));
-  double dvd[3][3];  // d(vel_a)/d(xi_d)
-  double jp = 0.0, jr = 0.0;
-  for (int d = 0; d < 3; ++d) {
-    const bool bnd = !g.periodic[d];
-    const int n = g.n[d];
-    const int qp = bnd ? min(pos[d] + 1, n - 1) : (pos[d] + 1 >= n ? pos[d] + 1 - n : pos[d] + 1);
-    const int qm = bnd ? max(pos[d] - 1, 0) : (pos[d] - 1 < 0 ? pos[d] - 1 + n : pos[d] - 1);
-    const bool end = bnd && (pos[d] == 0 || pos[d] == n - 1);
-    const double ispan = 1.0 / ((bnd ? (double)(qp - qm) : 2.0) * ph.h[d]);
-    const long long ip = id + (long long)(qp - pos[d]) * g.s[d];
-    const long long im = id + (long long)(qm - pos[d]) * g.s[d];
-    const double rp = U[ip], rm = U[im];
-    const double irp = 1.0 / rp, irm = 1.0 / rm;
-    double vp[3], vm[3];
+  const double ir = 1.0 / rho;
+  q[0] = rho;
+  q[1] = U[N + id] * ir;
+  q[2] = U[2 * N + id] * ir;
+  q[3] = U[3 * N + id] * ir;
+  q[4] = ph.gm1 * (U[4 * N + id] - 0.5 * rho * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]));
+}
+
+// Each thread marches one (xi, eta) column through a zeta segment with the
+// primitives of planes k-1, k, k+1 in registers; xi and eta neighbours are
+// read from the plane.
+__global__ __launch_bounds__(256) void k_features(const Geo g, const ZMarch zm, const Phys ph,
+                                                  const double* __restrict__ U, const double* __restrict__ met,
+                                                  uint2* __restrict__ feat) {
+  int i, j, k0, k1;
+  if (!zmarch_column(zm, g.n, &i, &j, &k0, &k1)) return;
+  const long long N = g.N;
+  const int nz = g.n[2];
+  const bool pz = g.periodic[2];
+  const long long col = i + g.s[1] * j;
+  auto plane = [&](int k) { return pz ? wrapn(k, nz) : min(max(k, 0), nz - 1); };
+  // xi and eta neighbour positions (clamped at a bounded end) and spacings
+  int qpx, qmx, qpy, qmy;
+  {
+    const bool bx = !g.periodic[0], by = !g.periodic[1];
+    const int nx = g.n[0], ny = g.n[1];
+    qpx = bx ? min(i + 1, nx - 1) : wrapn(i + 1, nx);
+    qmx = bx ? max(i - 1, 0) : wrapn(i - 1, nx);
+    qpy = by ? min(j + 1, ny - 1) : wrapn(j + 1, ny);
+    qmy = by ? max(j - 1, 0) : wrapn(j - 1, ny);
+  }
+  const double isx = 1.0 / ((!g.periodic[0] ? (double)(qpx - qmx) : 2.0) * ph.h[0]);
+  const double isy = 1.0 / ((!g.periodic[1] ? (double)(qpy - qmy) : 2.0) * ph.h[1]);
+  const bool endx = !g.periodic[0] && (i == 0 || i == g.n[0] - 1);
+  const bool endy = !g.periodic[1] && (j == 0 || j == g.n[1] - 1);
+  const long long oxp = qpx - i, oxm = qmx - i, oyp = (long long)(qpy - j) * g.s[1], oym = (long long)(qmy - j) * g.s[1];
+  const double it1 = 1.0 / ph.theta1;
+  double zm1[5], z0[5], zp1[5];
+  prim5(ph, U, N, col + (long long)plane(k0 - 1) * g.s[2], zm1);
+  prim5(ph, U, N, col + (long long)k0 * g.s[2], z0);
+  for (int k = k0; k < k1; ++k) {
+    const long long id = col + (long long)k * g.s[2];
+    prim5(ph, U, N, col + (long long)plane(k + 1) * g.s[2], zp1);
+    const int kp = plane(k + 1), km = plane(k - 1);
+    const bool endz = !pz && (k == 0 || k == nz - 1);
+    const double isz = 1.0 / ((pz ? 2.0 : (double)(kp - km)) * ph.h[2]);
+    double xp[5], xm[5], yp[5], ym[5];
+    prim5(ph, U, N, id + oxp, xp);
+    prim5(ph, U, N, id + oxm, xm);
+    prim5(ph, U, N, id + oyp, yp);
+    prim5(ph, U, N, id + oym, ym);
+    double dvd[3][3];   // d(vel_a)/d(xi_d)
     for (int a = 0; a < 3; ++a) {
-      vp[a] = U[(a + 1) * N + ip] * irp;
-      vm[a] = U[(a + 1) * N + im] * irm;
+      dvd[a][0] = (xp[a + 1] - xm[a + 1]) * isx;
+      dvd[a][1] = (yp[a + 1] - ym[a + 1]) * isy;
+      dvd[a][2] = (zp1[a + 1] - zm1[a + 1]) * isz;
     }
-    const double pp = ph.gm1 * (U[4 * N + ip] - 0.5 * rp * (vp[0] * vp[0] + vp[1] * vp[1] + vp[2] * vp[2]));
-    const double pm = ph.gm1 * (U[4 * N + im] - 0.5 * rm * (vm[0] * vm[0] + vm[1] * vm[1] + vm[2] * vm[2]));
-    for (int a = 0; a < 3; ++a) dvd[a][d] = (vp[a] - vm[a]) * ispan;
-    if (!end) {
-      jp += fabs(-pm + 2.0 * p - pp) / (pm + 2.0 * p + pp);
-      jr += fabs(-rm + 2.0 * rho - rp) / (rm + 2.0 * rho + rp);
+    auto jump = [](double m, double c, double pl) { return fabs(-m + 2.0 * c - pl) / (m + 2.0 * c + pl); };
+    double jp = 0.0, jr = 0.0;
+    if (!endx) { jp += jump(xm[4], z0[4], xp[4]); jr += jump(xm[0], z0[0], xp[0]); }
+    if (!endy) { jp += jump(ym[4], z0[4], yp[4]); jr += jump(ym[0], z0[0], yp[0]); }
+    if (!endz) { jp += jump(zm1[4], z0[4], zp1[4]); jr += jump(zm1[0], z0[0], zp1[0]); }
+    const double jinv = met[9 * N + id];
+    const double ij = 1.0 / jinv;
+    double gr[3][3];
+    for (int a = 0; a < 3; ++a)
+      for (int c = 0; c < 3; ++c) {
+        double sum = 0.0;
+        for (int d = 0; d < 3; ++d) sum += (met[(3 * d + c) * N + id] * ij) * dvd[a][d];
+        gr[a][c] = sum;
+      }
+    const double div = gr[0][0] + gr[1][1] + gr[2][2];
+    const double wx = gr[2][1] - gr[1][2], wy = gr[0][2] - gr[2][0], wz = gr[1][0] - gr[0][1];
+    const double vort = sqrt(wx * wx + wy * wy + wz * wz);
+    const double dc = cbrt(fabs(jinv)) / sqrt(ph.gamma * z0[4] / z0[0]);   // Delta / c
+    const __bf16 f[4] = {(__bf16)(float)(dc * div), (__bf16)(float)(dc * vort), (__bf16)(float)(jp * it1),
+                         (__bf16)(float)(jr * it1)};
+    uint2 out;
+    __builtin_memcpy(&out, f, 8);
+    feat[id] = out;
+    for (int q = 0; q < 5; ++q) {
+      zm1[q] = z0[q];
+      z0[q] = zp1[q];
     }
   }
-  const double jinv = met[9 * N + id];
-  const double ij = 1.0 / jinv;
-  double gr[3][3];
-  for (int a = 0; a < 3; ++a)
-    for (int c = 0; c < 3; ++c) {
-      double s = 0.0;
-      for (int d = 0; d < 3; ++d) s += (met[(3 * d + c) * N + id] * ij) * dvd[a][d];
-      gr[a][c] = s;
-    }
-  const double div = gr[0][0] + gr[1][1] + gr[2][2];
-  const double wx = gr[2][1] - gr[1][2], wy = gr[0][2] - gr[2][0], wz = gr[1][0] - gr[0][1];
-  const double vort = sqrt(wx * wx + wy * wy + wz * wz);
-  const double dc = cbrt(fabs(jinv)) / sqrt(ph.gamma * p * ir0);   // Delta / c
-  const double it1 = 1.0 / ph.theta1;
-  const __bf16 f[4] = {(__bf16)(float)(dc * div), (__bf16)(float)(dc * vort), (__bf16)(float)(jp * it1),
-                       (__bf16)(float)(jr * it1)};
-  uint2 out;
-  __builtin_memcpy(&out, f, 8);
-  feat[id] = out;
 }
 
 hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, uint16_t* feat,
                            hipStream_t st) {
-  const dim3 grid((unsigned)((g.n[0] + 63) / 64), (unsigned)((g.n[1] + 3) / 4), (unsigned)g.n[2]);
-  hipLaunchKernelGGL(k_features, grid, dim3(64, 4), 0, st, g, ph, U, met, (uint2*)feat);
+  const ZMarch zm = make_zmarch(g.n);
+  hipLaunchKernelGGL(k_features, dim3(zm.blocks), dim3(256), 0, st, g, zm, ph, U, met, (uint2*)feat);
   return hipGetLastError();
 }
 
