@@ -112,8 +112,9 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
     FP64, (ii) the plain FP64 hybrid, (iii) FP32 reconstruction + learned
     sensor (re-evaluated every substep, audited every 50), (iv) the same with
     the network re-evaluated once per Runge-Kutta step.  The time step is
-    twice the generator's default (CFL about 0.5); shocklets form after
-    t ~ 0.3, about 850 substeps at 512^3."""
+    twice the generator's default (CFL about 0.5).  At 512^3 the plain
+    sensor marks its first interfaces near t = 0.5 (1400 substeps) and about
+    0.24% of them at t = 0.9 (2500 substeps), where the forms are timed."""
     import dataclasses
     import workloads
     t_all = time.perf_counter()
@@ -132,7 +133,7 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
     for k in range(develop // every):
         s.advance(every, case.dt)
         if (k + 1) * every > first:
-            total = pk.ocfd_sensor_collect(s.h, 5000 + k, 1.0, 0.001)
+            total = pk.ocfd_sensor_collect(s.h, 5000 + k, 0.25, 0.0005)
     torch.cuda.synchronize()
     t_dev = time.perf_counter() - t0
     _log(f"hit{n}: developed {develop} substeps in {t_dev:.1f} s, {total} samples")
@@ -237,8 +238,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the isotropic-turbulence and compression-ramp form comparisons")
     ap.add_argument("--hit-n", type=int, default=512)
-    ap.add_argument("--hit-develop", type=int, default=1250,
-                    help="plain FP64 hybrid substeps before the forms are timed (t ~ 0.45 at 512^3)")
+    ap.add_argument("--hit-develop", type=int, default=2500,
+                    help="plain FP64 hybrid substeps before the forms are timed (t ~ 0.9 at 512^3)")
     ap.add_argument("--form-substeps", type=int, default=100)
     ap.add_argument("--ramp-shape", type=str, default="1024,160,128")
     ap.add_argument("--calibration-copy", action="store_true",
