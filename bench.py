@@ -39,6 +39,14 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 HBM_PEAK_GBS = 8000.0
 
+# HBM counters of the dominant kernel in the default configuration (FP64,
+# 256^3), per launch averaged over both runs, from the rocprofv3 --pmc runs
+# summarised in profiles/fp64_weno7_headline_256cube.md.  A 512 MiB device copy
+# reads FETCH_SIZE = 256 MiB and WRITE_SIZE = 512 MiB, so bytes fetched are
+# 2 x FETCH_SIZE.  Valid for the kernel as committed with that file; other
+# configurations report null.
+PMC_TRAFFIC = {"sweep_xi": {"fetch_kib": 2252489, "write_kib": 665600}}
+
 
 def sweep_flops(mode: str, viscous: bool) -> int:
     return FLOPS_PRIM + FLOPS_SW + FLOPS_IFACE + FLOPS_DIFF + (FLOPS_VDIV if viscous else 0) + FLOPS_MODE[mode]
@@ -196,6 +204,41 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
             "forms": res}
 
 
+def learned_overhead(torch, pk, n, substeps):
+    """Cost of the learned sensor on the Taylor-Green n^3 distorted run: FP32
+    hybrid with the perceptron evaluated every substep, the output bias set to
+    -30 so every interface takes the low-dissipation stencil (the sensor's own
+    kernels are then the only difference from the plain hybrid)."""
+    import dataclasses
+    import workloads
+    base = workloads.taylor_green(n, distorted=True)
+    c = dataclasses.replace(base, scheme="hybrid", precision="mixed", sensor="learned", sensor_every=1)
+    w = workloads.sensor_initial_weights(3)
+    w[-1] = -30.0
+
+    def setup(sv):
+        pk.ocfd_sensor_set_params(sv.h, w)
+        pk.ocfd_sensor_set_threshold(sv.h, 0.5)
+    U = torch.from_numpy(base.U0).cuda()
+    s = pk.Solver(pk.params_from(c))
+    s.set_grid(torch.from_numpy(c.xyz).cuda())
+    setup(s)
+    s.set_state(U)
+    s.advance(2, c.dt)
+    torch.cuda.synchronize()
+    pk.ocfd_profile(s.h, True)
+    t0 = time.perf_counter()
+    s.advance(substeps, c.dt)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    prof = pk.ocfd_profile_read(s.h)
+    pk.ocfd_profile(s.h, False)
+    s.close()
+    return {"workload": f"Taylor-Green {n}^3 distorted, FP32 hybrid, network every substep, all flags low",
+            "gpt_substeps_per_s": round(c.N * substeps / el / 1e9, 4),
+            "avg_launch_us": {k: round(v[0] / v[1] * 1e3, 1) for k, v in prof.items() if v[1]}}
+
+
 def form_ramp_mixed(torch, pk, shape, substeps):
     """Compression ramp: WENO7 FP64 against the FP32 split/reconstruction form
     from the same inflow state, `substeps` substeps each."""
@@ -235,6 +278,8 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="fp64: the plain path; mixed: FP32 split/reconstruction, FP64 difference and RK")
+    ap.add_argument("--learned-overhead", action="store_true",
+                    help="also time the learned sensor's kernels on the 256^3 Taylor-Green run")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the isotropic-turbulence and compression-ramp form comparisons")
     ap.add_argument("--hit-n", type=int, default=512)
@@ -319,8 +364,12 @@ def main():
     # The mixed form does the split and reconstruction (nearly all of a sweep's
     # flops) in FP32, so it is measured against the FP32 vector peak.
     peak = FP32_PEAK_TFLOPS if args.precision == "mixed" else FP64_PEAK_TFLOPS
+    traffic = None
+    if args.precision == "fp64" and args.n == 256 and dom in PMC_TRAFFIC:
+        t = PMC_TRAFFIC[dom]
+        traffic = 2 * t["fetch_kib"] * 1024 + t["write_kib"] * 1024
     roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
             "avg_launch_us": {k: round(v[1] * 1e3, 1) for k, v in flops_launch.items()},
             "flops_per_launch": {k: v[0] for k, v in flops_launch.items()}}
 
@@ -328,6 +377,7 @@ def main():
         s.close()
     del solvers
     torch.cuda.empty_cache()
+    overhead = learned_overhead(torch, pk, args.n, args.steps) if args.learned_overhead else None
     forms = None
     if not args.no_forms:
         forms = {"isotropic_turbulence": form_hit_learned(torch, pk, args.hit_n, args.hit_develop, 50,
@@ -360,6 +410,8 @@ def main():
         "cpu_baseline": cpu,
         "forms": forms,
     }
+    if overhead is not None:
+        out["learned_overhead"] = overhead
     print(json.dumps(out), flush=True)
 
 
