@@ -131,10 +131,12 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
       else
         dq[q][2] = line_deriv([&](int m) { return zw[q][3 + m]; }, k, nz, false, 3) * ph.ih[2];
     }
-    const double ij = 1.0 / met[9 * N + id];
+    // metrics are read once and the fluxes written once: non-temporal, so
+    // they do not push the planes of u, v, w, T (re-read as neighbours) out of L2
+    const double ij = 1.0 / __builtin_nontemporal_load(met + 9 * N + id);
     double m[9];
 #pragma unroll
-    for (int r = 0; r < 9; ++r) m[r] = met[r * N + id];
+    for (int r = 0; r < 9; ++r) m[r] = __builtin_nontemporal_load(met + r * N + id);
     double gr[4][3];
 #pragma unroll
     for (int q = 0; q < 4; ++q)
@@ -159,8 +161,9 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
     for (int d = 0; d < 3; ++d) {
       const double m0 = m[3 * d], m1 = m[3 * d + 1], m2 = m[3 * d + 2];
 #pragma unroll
-      for (int b = 0; b < 3; ++b) Fv[(4 * d + b) * N + id] = m0 * tau[0][b] + m1 * tau[1][b] + m2 * tau[2][b];
-      Fv[(4 * d + 3) * N + id] = m0 * th[0] + m1 * th[1] + m2 * th[2];
+      for (int b = 0; b < 3; ++b)
+        __builtin_nontemporal_store(m0 * tau[0][b] + m1 * tau[1][b] + m2 * tau[2][b], Fv + (4 * d + b) * N + id);
+      __builtin_nontemporal_store(m0 * th[0] + m1 * th[1] + m2 * th[2], Fv + (4 * d + 3) * N + id);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q)

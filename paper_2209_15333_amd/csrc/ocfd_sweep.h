@@ -140,18 +140,20 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   auto emit_load = [&](int j, int col) {
     EmitIn e;
     const long long id = base + (long long)col * sc + (long long)j * sd;
+    // the sum, U^n and 1/J are read once per sweep: non-temporal loads keep
+    // them from displacing reused lines (the load windows, U) in L2
     if (MODE != MODE_SET) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) e.s[q] = A.rhs[q * N + id];
+      for (int q = 0; q < 5; ++q) e.s[q] = __builtin_nontemporal_load(A.rhs + q * N + id);
     }
     if (MODE == MODE_RK) {
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        e.un[q] = A.Un[q * N + id];
+        e.un[q] = __builtin_nontemporal_load(A.Un + q * N + id);
         e.u[q] = A.U[q * N + id];
       }
     }
-    if (MODE == MODE_RK || MODE == MODE_DUDT) e.ij = A.met[9 * N + id];
+    if (MODE == MODE_RK || MODE == MODE_DUDT) e.ij = __builtin_nontemporal_load(A.met + 9 * N + id);
     return e;
   };
 
@@ -191,12 +193,13 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
         r[q + 1] += d * ih;
       }
     }
+    // outputs are written once per sweep: non-temporal stores
     if (MODE == MODE_SET) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) A.rhs[q * N + id] = r[q];
+      for (int q = 0; q < 5; ++q) __builtin_nontemporal_store(r[q], A.rhs + q * N + id);
     } else if (MODE == MODE_ADD) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) A.rhs[q * N + id] = e.s[q] + r[q];
+      for (int q = 0; q < 5; ++q) __builtin_nontemporal_store(e.s[q] + r[q], A.rhs + q * N + id);
     } else {
       // nodes on a face of a non-periodic direction take dU/dt = 0 (their
       // value is set by the boundary condition after the stage)
@@ -214,9 +217,9 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
       for (int q = 0; q < 5; ++q) {
         const double L = bnd ? 0.0 : (e.s[q] + r[q]) * ij;
         if (MODE == MODE_RK)
-          A.out[q * N + id] = A.a * e.un[q] + A.b * (e.u[q] + A.dt * L);
+          __builtin_nontemporal_store(A.a * e.un[q] + A.b * (e.u[q] + A.dt * L), A.out + q * N + id);
         else
-          A.out[q * N + id] = L;
+          __builtin_nontemporal_store(L, A.out + q * N + id);
       }
     }
   };
