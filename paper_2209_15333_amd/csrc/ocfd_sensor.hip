@@ -114,8 +114,6 @@ hipError_t launch_plain_flags(const Geo& g, const Phys& ph, const double* theta,
 // a bounded line), chain rule with the node metrics.  A bounded direction adds
 // no jump term at its end nodes.
 // ---------------------------------------------------------------------------
-// Stored as bf16 (round to nearest even of the FP32 value), four per node
-// (node-major, 8 bytes), the operand format of the perceptron.
 // Primitives (rho, u, v, w, p) of node id.
 __device__ __forceinline__ void prim5(const Phys& ph, const double* __restrict__ U, long long N, long long id,
                                       double q[5]) {
@@ -128,9 +126,11 @@ __device__ __forceinline__ void prim5(const Phys& ph, const double* __restrict__
   q[4] = ph.gm1 * (U[4 * N + id] - 0.5 * rho * (q[1] * q[1] + q[2] * q[2] + q[3] * q[3]));
 }
 
-// Each thread marches one (xi, eta) column through a zeta segment with the
-// primitives of planes k-1, k, k+1 in registers; xi and eta neighbours are
-// read from the plane.
+// Stored as bf16 (round to nearest even of the FP32 value), four per node
+// (node-major, 8 bytes), the operand format of the perceptron.  Each thread
+// marches one (xi, eta) column through a zeta segment with the primitives of
+// planes k-1, k, k+1 in registers; xi and eta neighbours are read from the
+// plane.
 __global__ __launch_bounds__(256) void k_features(const Geo g, const ZMarch zm, const Phys ph,
                                                   const double* __restrict__ U, const double* __restrict__ met,
                                                   uint2* __restrict__ feat) {
@@ -308,12 +308,25 @@ __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const uint2* __r
   };
   for (int d = 0; d < 3; ++d) {
     const int n = g.n[d];
+    // When nx is a multiple of 16 a tile is 16 consecutive nodes of one
+    // xi row: its position comes from the (wave-uniform) tile index in scalar
+    // registers and only the xi position differs between lanes.
+    const bool rows = (g.n[0] & 15) == 0;
+    const int sd = (int)g.s[d];
     auto gather = [&](long long T, Tile& tl) {
-      tl.id = T * 16 + j;
-      tl.ok = tl.id < N;
-      const long long idc = tl.ok ? tl.id : N - 1;
       int pos[3];
-      node_position(g, idc, pos);
+      if (rows) {
+        const int b = (int)(T * 16);
+        node_position(g, b, pos);
+        pos[0] += j;
+        tl.id = b + j;
+        tl.ok = true;
+      } else {
+        tl.id = T * 16 + j;
+        tl.ok = tl.id < N;
+        node_position(g, tl.ok ? tl.id : N - 1, pos);
+      }
+      const int idc = tl.ok ? (int)tl.id : (int)(N - 1);
       tl.inside = window_inside(g, d, pos[d]);
       for (int tt = 0; tt < 2; ++tt) {
         int q = pos[d] + 2 * gg + tt - 3;
@@ -321,7 +334,7 @@ __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const uint2* __r
           q = n >= 8 ? q + (q < 0 ? n : 0) - (q >= n ? n : 0) : wrapn(q, n);
         else
           q = min(max(q, 0), n - 1);
-        tl.xv[tt] = feat[idc + (long long)(q - pos[d]) * g.s[d]];
+        tl.xv[tt] = feat[idc + (q - pos[d]) * sd];
       }
     };
     // the next tile's inputs are loaded while the current one is evaluated
