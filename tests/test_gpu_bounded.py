@@ -161,3 +161,30 @@ def test_bounded_call_order_errors(pk, torch_cuda):
     t = pk.Solver(pk.params_from(per))
     with pytest.raises(pk.OcfdError, match="UNSUPPORTED"):
         t.set_inflow(_dev(torch_cuda, np.zeros((5, 8, 16))))
+
+
+def test_ramp_full_size_sampled(pk, torch_cuda, orc):
+    """The compression ramp at the benchmark's size (1024 x 160 x 128) in its
+    launch configuration: dU/dt at sampled nodes, a third of them within six
+    nodes of the inflow, outflow, wall and top faces, against the oracle
+    evaluated node by node."""
+    case = workloads.compression_ramp()
+    print("case", case.name, flush=True)
+    s = _solver(pk, torch_cuda, case)
+    got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy().reshape(5, -1)
+    del s
+    rng = np.random.default_rng(7)
+    nx, ny, nz = case.nx, case.ny, case.nz
+    edge = np.r_[0:6, nx - 6:nx]
+    wall = np.r_[0:6, ny - 6:ny]
+    near = []
+    for _ in range(40):
+        i = rng.choice(edge) if rng.random() < 0.5 else rng.integers(nx)
+        j = rng.choice(wall) if rng.random() < 0.5 or i not in edge else rng.integers(ny)
+        near.append(i + nx * (j + ny * rng.integers(nz)))
+    nodes = np.unique(np.r_[rng.choice(case.N, 80, replace=False), near]).astype(np.int64)
+    P = orc.params_from_case(case, nthreads=0)
+    met = orc.metrics(P, case.xyz)
+    ref = orc.dudt_points(P, met, case.U0, nodes).T
+    ref_pert = orc.dudt_points(P, met, ulp_perturbed(case.U0), nodes).T
+    assert_within_roundoff(got[:, nodes], ref, ref_pert, what=f"{case.name} sampled dU/dt ({len(nodes)} nodes)")
