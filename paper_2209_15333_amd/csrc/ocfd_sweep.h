@@ -55,6 +55,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   __shared__ R ring[RING * SLOT];
   __shared__ double fh[(SW_S + 1) * FHS];  // fh[0]: carried flux; fh[s+1]: interface j0+s
   __shared__ double fh0[FHS];             // flux at 1/2, for node 0 of a periodic line
+  __shared__ double cyb[FHS];             // carried flux of odd chunks (even chunks: fh[0])
   __shared__ int wl_n;                    // hybrid: WENO work list of this chunk
   __shared__ short wl[SW_T];
   // the viscous flux of direction DIR of every ring node (FVR kernels in
@@ -327,20 +328,27 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     }
     __syncthreads();
     if (c == 0 && t < 5 * SW_W) fh0[(t / SW_W) * SW_W + (t % SW_W)] = fh[FHS + (t / SW_W) * SW_W + (t % SW_W)];
+    // The flux carried into chunk c (its interface j0 - 1) alternates between
+    // fh[0] and cyb, so the carry for chunk c + 1 can be written while other
+    // threads still finish chunk c's nodes: no barrier is needed between the
+    // finishing step and the next chunk, except where the next chunk's
+    // viscous-flux ring stores overwrite slots the finishing step still reads.
+    double* const cy_in = (c & 1) ? cyb : fh;
+    double* const cy_out = (c & 1) ? fh : cyb;
     if (fin)
-      emit(jfin, jraw, gc, fh + (gs + 1) * FHS + gc, fh + gs * FHS + gc, per || (jraw > 0 && jraw < n - 1), FVR,
-           ein);
-    __syncthreads();
+      emit(jfin, jraw, gc, fh + (gs + 1) * FHS + gc, gs == 0 ? cy_in + gc : fh + gs * FHS + gc,
+           per || (jraw > 0 && jraw < n - 1), FVR, ein);
     if (t < 5 * SW_W) {
       const int last = min(SW_S, nif - c * SW_S);
-      if (last > 0) fh[(t / SW_W) * SW_W + (t % SW_W)] = fh[last * FHS + (t / SW_W) * SW_W + (t % SW_W)];
+      if (last > 0) cy_out[(t / SW_W) * SW_W + (t % SW_W)] = fh[last * FHS + (t / SW_W) * SW_W + (t % SW_W)];
     }
+    if (FVR) __syncthreads();
   }
   __syncthreads();
   // The periodic line's first node (JB) with the wrapped flux carried out of the last chunk.
   if (per && gs == 0 && gcol_ok) {
     const int j = wrap(JB, n);
-    emit(j, JB, gc, fh0 + gc, fh + gc, true, false, emit_load(j, gc));
+    emit(j, JB, gc, fh0 + gc, ((nchunks & 1) ? cyb : fh) + gc, true, false, emit_load(j, gc));
   }
 }
 
