@@ -120,11 +120,14 @@ __device__ __forceinline__ R weno7(R a0, R a1, R a2, R a3, R a4, R a5, R a6, R e
   e1 *= e1;
   e2 *= e2;
   e3 *= e3;
-  // candidate values at j+1/2 relative to a3 = f_j
-  const R q0 = (R)0.5 * D0 + (R)(4.0 / 3.0) * E0 + (R)(13.0 / 12.0) * G0;
-  const R q1 = (R)0.5 * D1 + (R)(5.0 / 6.0) * E1 + (R)0.25 * G1;
-  const R q2 = (R)0.5 * D2 + (R)(1.0 / 3.0) * E2 - (R)(1.0 / 12.0) * G2;
-  const R q3 = (R)0.5 * D3 - (R)(1.0 / 6.0) * E3 + (R)(1.0 / 12.0) * G3;
+  // candidate values at j+1/2 relative to a3 = f_j: for every candidate
+  // q_r - f_j = (0.5 D + (4/3, 5/6, 1/3, -1/6)_r E + (13/12, 1/4, -1/12, 1/12)_r G)
+  // = t_r / 2 + s_r / 12 (the same differences as the indicator)
+  const R c12 = (R)(1.0 / 12.0);
+  const R q0 = (R)0.5 * t0 + c12 * s0;
+  const R q1 = (R)0.5 * t1 + c12 * s1;
+  const R q2 = (R)0.5 * t2 + c12 * s2;
+  const R q3 = (R)0.5 * t3 + c12 * s3;
   if (sizeof(R) == 4) {
     // FP32: the weights d_r / (eps + beta_r)^2 from four reciprocals; the
     // folded product of three (eps + beta)^2 factors can leave the float range.
