@@ -34,7 +34,7 @@ class Params(ctypes.Structure):
         ("Tref", ctypes.c_double), ("suth", ctypes.c_double), ("Tw", ctypes.c_double),
         ("theta1", ctypes.c_double), ("theta2", ctypes.c_double), ("eps", ctypes.c_double),
         ("viscous", ctypes.c_int32), ("scheme", ctypes.c_int32), ("lowdiss", ctypes.c_int32),
-        ("three_way", ctypes.c_int32), ("nthreads", ctypes.c_int32),
+        ("three_way", ctypes.c_int32), ("characteristic", ctypes.c_int32), ("nthreads", ctypes.c_int32),
     ]
 
 
@@ -63,6 +63,7 @@ def lib():
         L.or_ud7.restype = ctypes.c_double
         L.or_c8.argtypes = [dp]
         L.or_c8.restype = ctypes.c_double
+        L.or_char_matrices.argtypes = [pp, dp, dp, dp, dp]
         L.or_metrics.argtypes = [pp, dp, dp]
         L.or_sensor.argtypes = [pp, dp, dp, u8p]
         L.or_dudt.argtypes = [pp, dp, dp, u8p, ctypes.c_int32, dp]
@@ -106,6 +107,7 @@ def params_from_case(case, nthreads: int = 0) -> Params:
     P.scheme = 1 if case.scheme == "hybrid" else 0
     P.lowdiss = 1 if case.lowdiss == "c8" else 0
     P.three_way = int(bool(case.three_way))
+    P.characteristic = int(bool(getattr(case, "characteristic", False)))
     P.nthreads = int(nthreads)
     return P
 
@@ -121,6 +123,16 @@ def sw_split(P: Params, rho, u, v, w, p, alpha):
     a = np.ascontiguousarray(alpha, dtype=np.float64)
     lib().or_sw_split(ctypes.byref(P), rho, u, v, w, p, _dp(a), _dp(fp), _dp(fm))
     return fp, fm
+
+
+def char_matrices(P: Params, U, n):
+    """(S, S^-1) of eq 34-35 at the conserved state U for the unit normal n (5x5 each)."""
+    Uc = np.ascontiguousarray(U, dtype=np.float64)
+    nc = np.ascontiguousarray(n, dtype=np.float64)
+    S = np.zeros(25)
+    Si = np.zeros(25)
+    lib().or_char_matrices(ctypes.byref(P), _dp(Uc), _dp(nc), _dp(S), _dp(Si))
+    return S.reshape(5, 5), Si.reshape(5, 5)
 
 
 def weno7(f, eps=1e-6) -> float:

@@ -25,7 +25,13 @@
  *    scheme with linear weights (1,12,18,4)/35, p = 2 and the smoothness
  *    indicators of the Jiang-Shu integral definition;
  *  - a hybrid interface takes the low-dissipation stencil when the sensor
- *    theta of every node of its 8-node stencil is <= theta1 (eq 43).
+ *    theta of every node of its 8-node stencil is <= theta1 (eq 43);
+ *  - in characteristic variables (Sec. 2.2.2) the split fluxes f+ and f- of
+ *    the window are both carried by the S of the interface, reconstructed
+ *    field by field with the stencil the interface would use component-wise,
+ *    and their sum carried back by S^-1; the eigenvalues of eq 33 enter only
+ *    through the split.  The interface normal is the unit vector of the mean
+ *    of the two nodes' metric rows of the sweep direction.
  */
 #include "ocfd_oracle.h"
 #include <math.h>
@@ -308,10 +314,66 @@ double or_c8(const double f[8]) {
   return (-3.0 * f[0] + 29.0 * f[1] - 139.0 * f[2] + 533.0 * f[3] + 533.0 * f[4] - 139.0 * f[5] + 29.0 * f[6] - 3.0 * f[7]) / 840.0;
 }
 
-/* Numerical flux at the interface between window nodes 3 and 4 (j and j+1).
-   fpw/fmw[t][m]: split fluxes of window node j-3+t; ok[t]: node exists. */
-static void interface_flux(const or_params* P, const double fpw[8][5], const double fmw[8][5],
-                           const int ok[8], int flag, double F[5]) {
+/* ------------------------------------------------------------------ */
+/* Characteristic variables (Sec. 2.2.2, eq 31-40)                      */
+/* ------------------------------------------------------------------ */
+
+void or_char_matrices(const or_params* P, const double U[5], const double n[3], double S[25], double Sinv[25]) {
+  const double g = P->gamma;
+  const double rho = U[0], u = U[1] / rho, v = U[2] / rho, w = U[3] / rho;
+  const double V = 0.5 * (u * u + v * v + w * w);                      /* eq 25 */
+  const double p = (g - 1.0) * (U[4] - rho * V);
+  const double c = sqrt(g * p / rho);
+  const double H = V + c * c / (g - 1.0);                              /* eq 36 */
+  const double kap = (g - 1.0) / (c * c), kap1 = 0.5 * kap, chi = 1.0 / (2.0 * c); /* eq 37 */
+  double l[3], m[3];
+  if (fabs(n[2]) <= fabs(n[1])) {                                      /* eq 39 */
+    double r = sqrt(n[0] * n[0] + n[1] * n[1]);
+    l[0] = -n[1] / r; l[1] = n[0] / r; l[2] = 0.0;
+  } else {
+    double r = sqrt(n[0] * n[0] + n[2] * n[2]);
+    l[0] = -n[2] / r; l[1] = 0.0; l[2] = n[0] / r;
+  }
+  m[0] = n[1] * l[2] - n[2] * l[1];                                    /* eq 40 */
+  m[1] = n[2] * l[0] - n[0] * l[2];
+  m[2] = n[0] * l[1] - n[1] * l[0];
+  const double un = u * n[0] + v * n[1] + w * n[2];                    /* eq 38 */
+  const double ul = u * l[0] + v * l[1] + w * l[2];
+  const double um = u * m[0] + v * m[1] + w * m[2];
+  const double vel[3] = {u, v, w};
+  /* S^-1 (eq 34), column by column: the entropy wave, the two shear waves,
+     the acoustic waves u_n - c and u_n + c. */
+  Sinv[0 * 5 + 0] = 1.0; Sinv[0 * 5 + 1] = 0.0; Sinv[0 * 5 + 2] = 0.0; Sinv[0 * 5 + 3] = 1.0; Sinv[0 * 5 + 4] = 1.0;
+  for (int i = 0; i < 3; ++i) {
+    Sinv[(1 + i) * 5 + 0] = vel[i];
+    Sinv[(1 + i) * 5 + 1] = l[i];
+    Sinv[(1 + i) * 5 + 2] = m[i];
+    Sinv[(1 + i) * 5 + 3] = vel[i] - c * n[i];
+    Sinv[(1 + i) * 5 + 4] = vel[i] + c * n[i];
+  }
+  Sinv[4 * 5 + 0] = V; Sinv[4 * 5 + 1] = ul; Sinv[4 * 5 + 2] = um;
+  Sinv[4 * 5 + 3] = H - c * un; Sinv[4 * 5 + 4] = H + c * un;
+  /* S (eq 35), row by row. */
+  S[0 * 5 + 0] = 1.0 - kap * V;
+  S[1 * 5 + 0] = -ul;
+  S[2 * 5 + 0] = -um;
+  S[3 * 5 + 0] = kap1 * V + chi * un;
+  S[4 * 5 + 0] = kap1 * V - chi * un;
+  for (int i = 0; i < 3; ++i) {
+    S[0 * 5 + 1 + i] = kap * vel[i];
+    S[1 * 5 + 1 + i] = l[i];
+    S[2 * 5 + 1 + i] = m[i];
+    S[3 * 5 + 1 + i] = -chi * n[i] - kap1 * vel[i];
+    S[4 * 5 + 1 + i] = chi * n[i] - kap1 * vel[i];
+  }
+  S[0 * 5 + 4] = -kap; S[1 * 5 + 4] = 0.0; S[2 * 5 + 4] = 0.0; S[3 * 5 + 4] = kap1; S[4 * 5 + 4] = kap1;
+}
+
+/* Numerical flux at the interface between window nodes 3 and 4 (j and j+1),
+   component by component.  fpw/fmw[t][m]: split fluxes of window node j-3+t;
+   ok[t]: node exists. */
+static void interface_flux_comp(const or_params* P, const double fpw[8][5], const double fmw[8][5],
+                                const int ok[8], int flag, double F[5]) {
   int all = 1;
   for (int t = 0; t < 8; ++t) all &= ok[t];
   for (int m = 0; m < 5; ++m) {
@@ -337,6 +399,52 @@ static void interface_flux(const or_params* P, const double fpw[8][5], const dou
       F[m] = or_weno7(a, P->eps) + or_weno7(b, P->eps);
     }
   }
+}
+
+/* Numerical flux at j+1/2.  S, Sinv: NULL for the component-wise
+   reconstruction; otherwise the split fluxes of the window are carried to the
+   characteristic variables of the interface state by S, reconstructed field by
+   field with the same stencil choice, and carried back by S^-1 (eq 31). */
+static void interface_flux(const or_params* P, const double fpw[8][5], const double fmw[8][5],
+                           const int ok[8], int flag, const double* S, const double* Sinv, double F[5]) {
+  if (!S) {
+    interface_flux_comp(P, fpw, fmw, ok, flag, F);
+    return;
+  }
+  double cpw[8][5], cmw[8][5], G[5];
+  for (int t = 0; t < 8; ++t)
+    for (int k = 0; k < 5; ++k) {
+      double a = 0.0, b = 0.0;
+      for (int m = 0; m < 5; ++m) {
+        a += S[k * 5 + m] * fpw[t][m];
+        b += S[k * 5 + m] * fmw[t][m];
+      }
+      cpw[t][k] = a;
+      cmw[t][k] = b;
+    }
+  interface_flux_comp(P, cpw, cmw, ok, flag, G);
+  for (int m = 0; m < 5; ++m) {
+    double a = 0.0;
+    for (int k = 0; k < 5; ++k) a += Sinv[m * 5 + k] * G[k];
+    F[m] = a;
+  }
+}
+
+/* The characteristic matrices of interface c+1/2 along d: the interface state
+   is the mean of the conserved variables of its two nodes (eq 32), the normal
+   the unit vector of the mean of their metric rows of direction d. */
+static void interface_char(const or_params* P, const double* met, const double* U, const int c[3], int d,
+                           double S[25], double Sinv[25]) {
+  const long N = n_nodes(P);
+  const long i0 = lin(P, c);
+  long i1;
+  shifted(P, c, d, 1, &i1, NULL);
+  double Ua[5], a[3];
+  for (int m = 0; m < 5; ++m) Ua[m] = 0.5 * (U[(long)m * N + i0] + U[(long)m * N + i1]);
+  for (int q = 0; q < 3; ++q) a[q] = 0.5 * (met[(long)(3 * d + q) * N + i0] + met[(long)(3 * d + q) * N + i1]);
+  const double r = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  const double nrm[3] = {a[0] / r, a[1] / r, a[2] / r};
+  or_char_matrices(P, Ua, nrm, S, Sinv);
 }
 
 /* ------------------------------------------------------------------ */
@@ -408,7 +516,7 @@ static int has_right_interface(const or_params* P, const int c[3], int d) {
 }
 
 /* Numerical flux at c+1/2 along d, the split fluxes computed on the spot. */
-static void flux_at(const or_params* P, const double* met, const prim_t* q, const uint8_t* flags,
+static void flux_at(const or_params* P, const double* met, const double* U, const prim_t* q, const uint8_t* flags,
                     const int c[3], int d, double F[5]) {
   const long N = n_nodes(P);
   double fpw[8][5], fmw[8][5];
@@ -419,7 +527,10 @@ static void flux_at(const or_params* P, const double* met, const prim_t* q, cons
     if (ok[t]) node_split(P, met, q, N, id, d, fpw[t], fmw[t]);
     else for (int m = 0; m < 5; ++m) fpw[t][m] = fmw[t][m] = 0.0;
   }
-  interface_flux(P, fpw, fmw, ok, flags ? flags[(long)d * N + lin(P, c)] : OR_FLAG_WENO7, F);
+  double S[25], Si[25];
+  if (P->characteristic) interface_char(P, met, U, c, d, S, Si);
+  interface_flux(P, fpw, fmw, ok, flags ? flags[(long)d * N + lin(P, c)] : OR_FLAG_WENO7,
+                 P->characteristic ? S : NULL, P->characteristic ? Si : NULL, F);
 }
 
 /* Viscous flux vectors F_v, G_v, H_v (eq 9-14) at node c: Fv[d][0..3] are the
@@ -555,8 +666,10 @@ int or_dudt(const or_params* P, const double* met, const double* U, const uint8_
           fmw[t][m] = ok[t] ? fm[(long)m * N + nid] : 0.0;
         }
       }
-      double Fi[5];
-      interface_flux(P, fpw, fmw, ok, flags ? flags[(long)d * N + id] : OR_FLAG_WENO7, Fi);
+      double Fi[5], S[25], Si[25];
+      if (P->characteristic) interface_char(P, met, U, c, d, S, Si);
+      interface_flux(P, fpw, fmw, ok, flags ? flags[(long)d * N + id] : OR_FLAG_WENO7,
+                     P->characteristic ? S : NULL, P->characteristic ? Si : NULL, Fi);
       for (int m = 0; m < 5; ++m) F[(long)(5 * d + m) * N + id] = Fi[m];
     }
   }
@@ -610,11 +723,11 @@ int or_dudt_points(const or_params* P, const double* met, const double* U, const
     for (int d = 0; d < 3; ++d) {
       for (int m = 0; m < 5; ++m) Fl[d][m] = Fr[d][m] = 0.0;
       if (parts & (1 << d)) {
-        if (has_right_interface(P, c, d)) flux_at(P, met, q, flags, c, d, Fr[d]);
+        if (has_right_interface(P, c, d)) flux_at(P, met, U, q, flags, c, d, Fr[d]);
         long nl;
         if (shifted(P, c, d, -1, &nl, NULL)) {
           int cl[3]; unlin(P, nl, cl);
-          flux_at(P, met, q, flags, cl, d, Fl[d]);
+          flux_at(P, met, U, q, flags, cl, d, Fl[d]);
         }
       }
       for (int t = 0; t < 7; ++t) {

@@ -44,6 +44,7 @@ typedef struct {
   int32_t scheme;        /* OR_WENO7 or OR_HYBRID */
   int32_t lowdiss;       /* OR_UD7 or OR_C8 */
   int32_t three_way;     /* hybrid with the WENO5 tier above theta2 */
+  int32_t characteristic; /* reconstruct in characteristic variables (Sec. 2.2.2) */
   int32_t nthreads;      /* OpenMP threads (0: runtime default) */
 } or_params;
 
@@ -64,6 +65,11 @@ double or_weno7(const double f[7], double eps);            /* f_{j-3..j+3} */
 double or_weno5(const double f[5], double eps, const int valid[3]); /* f_{j-2..j+2}; valid substencils */
 double or_ud7(const double f[7]);                          /* eq 41 */
 double or_c8(const double f[8]);                           /* f_{j-3..j+4}, central */
+/* Eigenvector matrices of the flux Jacobian along the unit normal n at the
+   conserved state U (Sec. 2.2.2, eq 34-40), row-major 5x5: S (rows: left
+   eigenvectors, eigenvalues u_n, u_n, u_n, u_n - c, u_n + c) and its inverse
+   Sinv (columns: right eigenvectors). */
+void or_char_matrices(const or_params* P, const double U[5], const double n[3], double S[25], double Sinv[25]);
 
 /* ---- whole-field operations ---- */
 /* Metrics by the conservative forms of eq 3 (xyz: [3][N] -> met: [10][N] =

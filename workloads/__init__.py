@@ -54,6 +54,7 @@ class Case:
     scheme: str = "weno7"                # "weno7" | "hybrid"
     lowdiss: str = "c8"                  # "ud7" | "c8"
     three_way: bool = False
+    characteristic: bool = False         # reconstruct in characteristic variables (Sec. 2.2.2)
     inflow: Optional[np.ndarray] = None
     precision: str = "fp64"              # "fp64" | "mixed" (GPU only)
     sensor: str = "plain"                # hybrid: "plain" (pressure sensor) | "learned" (GPU only)
@@ -213,6 +214,26 @@ def sod(n: int = 200, axis: int = 0, width: int = 4) -> Case:
     steps = int(round(0.2 / dt))
     return Case(name=f"sod{n}-axis{axis}", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=conserved(g, rho, zero, zero, zero, p),
                 period=tuple(Ls), h=h, dt=dt, nsteps=3 * steps, gamma=g, Re=1.0, Ma=1.0 / math.sqrt(1.4), viscous=0)
+
+
+def lax(n: int = 200, width: int = 2) -> Case:
+    """Lax tube on the periodic box [0, 2) along x: (rho, u, p) = (0.445, 0.698,
+    3.528) for 0.5 < x < 1.5, (0.5, 0, 0.571) outside.  The discontinuity at
+    x = 1.5 is the Lax problem; on 1 <= x < 2 its waves are the only ones up to
+    t = 0.13 (the faster left state pushes the waves of x = 0.5 no further
+    than x = 1.03).  Cell-centred nodes, Euler, gamma = 1.4, time step 0.2/n,
+    0.13/dt steps of three substeps each."""
+    case = sod(n, axis=0, width=width)
+    s = case.xyz[0]
+    inside = (s > 0.5) & (s < 1.5)
+    g = case.gamma
+    rho = np.where(inside, 0.445, 0.5)
+    u = np.where(inside, 0.698, 0.0)
+    p = np.where(inside, 3.528, 0.571)
+    zero = np.zeros_like(rho)
+    dt = 0.2 / n
+    return dataclasses.replace(case, name=f"lax{n}", U0=conserved(g, rho, u, zero, zero, p), dt=dt,
+                               nsteps=3 * int(round(0.13 / dt)))
 
 
 def isotropic_turbulence(n: int = 512, seed: int = 22093, k0: float = 4.0, Mt: float = 0.6,
