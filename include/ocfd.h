@@ -119,6 +119,14 @@ typedef struct ocfd_params {
   int32_t audit_every;     /* learned sensor: compare with the plain sensor every this many substeps (0: never) */
   int32_t three_way;       /* hybrid with the plain sensor: interfaces with max theta > theta2 take
                               fifth-order WENO (eq 43, Table 2), 0 or 1 */
+  int32_t characteristic;  /* 1: WENO interfaces (WENO7, WENO5 and the boundary closures) are
+                              reconstructed in characteristic variables (Sec. 2.2.2, eq 31-40):
+                              split fluxes carried by S of the interface state (the mean of the
+                              conserved variables of its two nodes, eq 32; normal: the unit vector
+                              of the mean of their metric rows) to characteristic variables,
+                              reconstructed field by field, carried back by S^-1; 0: component
+                              by component.  Linear stencils give the same flux either way. */
+  int32_t reserved0;       /* must be 0 */
 } ocfd_params;
 
 typedef struct ocfd_solver ocfd_solver;

@@ -46,6 +46,7 @@ class ocfd_params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("sensor", ctypes.c_int32), ("sensor_every", ctypes.c_int32), ("audit_every", ctypes.c_int32),
         ("three_way", ctypes.c_int32),
+        ("characteristic", ctypes.c_int32), ("reserved0", ctypes.c_int32),
     ]
 
 
@@ -315,6 +316,7 @@ def params_from(case, **overrides) -> ocfd_params:
     p.sensor_every = int(getattr(case, "sensor_every", 1))
     p.audit_every = int(getattr(case, "audit_every", 0))
     p.three_way = int(bool(getattr(case, "three_way", False)))
+    p.characteristic = int(bool(getattr(case, "characteristic", False)))
     for k, v in overrides.items():
         setattr(p, k, v)
     return p

@@ -116,6 +116,8 @@ bool valid_params(const ocfd_params* p, std::string* why) {
   if (p->sensor_every < 0 || p->audit_every < 0) { *why = "sensor_every and audit_every must be >= 0"; return false; }
   if (p->three_way != 0 && p->three_way != 1) { *why = "three_way must be 0 or 1"; return false; }
   if (p->three_way && !(p->theta2 >= p->theta1)) { *why = "three_way needs theta2 >= theta1"; return false; }
+  if (p->characteristic != 0 && p->characteristic != 1) { *why = "characteristic must be 0 or 1"; return false; }
+  if (p->reserved0 != 0) { *why = "reserved0 must be 0"; return false; }
   int ninflow = 0;
   const int n[3] = {p->nx, p->ny, p->nz};
   for (int d = 0; d < 3; ++d) {
@@ -392,6 +394,7 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
   A.hybrid = hyb ? 1 : 0;
   A.lowdiss = s->p.lowdiss;
   A.mixed = s->p.precision == OCFD_PREC_MIXED ? 1 : 0;
+  A.characteristic = s->p.characteristic;
   // zeta first (stores the sum), eta accumulates, xi last: the last sweep
   // reads and writes the most (sum, U^n, 1/J, output), and along xi those
   // accesses are contiguous.

@@ -178,6 +178,78 @@ __device__ __forceinline__ R weno5m(R a0, R a1, R a2, R a3, R a4, R eps, bool v0
   return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
 }
 
+// Characteristic variables of one interface (Sec. 2.2.2, eq 31-40).  The
+// interface state is the mean of the conserved variables of the two nodes
+// (eq 32); the normal n is the unit vector of the mean of their metric rows of
+// the sweep direction; l and m complete the frame as eq 39-40 choose them.
+// The products with S (eq 35) and S^-1 (eq 34) are regrouped around the terms
+// their rows share:
+//   a = V f0 - u.f + f4,  b = u_n f0 - n.f      (f = (f1, f2, f3))
+//   S f = (f0 - kappa a, l.f - u_l f0, m.f - u_m f0, kappa1 a + chi b, kappa1 a - chi b)
+// and with s = g3 + g4, d = c (g4 - g3):
+//   S^-1 g = (g0 + s, u_i (g0 + s) + l_i g1 + m_i g2 + n_i d, V g0 + u_l g1 + u_m g2 + H s + u_n d).
+// The state, frame and coefficients are formed in FP64 and held in R.
+template <typename R>
+struct CharFrame {
+  R u[3], n[3], l[3], m[3];
+  R V, H, un, ul, um, c, kap, kap1, chi;
+
+  __device__ __forceinline__ void init(const Phys& ph, const double* Ua, const double* a) {
+    const double ir = rcp_r<double>(Ua[0]);
+    const double vu = Ua[1] * ir, vv = Ua[2] * ir, vw = Ua[3] * ir;
+    const double Vd = 0.5 * (vu * vu + vv * vv + vw * vw);               // eq 25
+    const double p = ph.gm1 * (Ua[4] - Ua[0] * Vd);
+    const double c2 = ph.gamma * p * ir;
+    const double cd = sqrt(c2);
+    const double is = rcp_r<double>(sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]));
+    const double n0 = a[0] * is, n1 = a[1] * is, n2 = a[2] * is;
+    double l0, l1, l2;
+    if (fabs(n2) <= fabs(n1)) {                                          // eq 39
+      const double r = rcp_r<double>(sqrt(n0 * n0 + n1 * n1));
+      l0 = -n1 * r; l1 = n0 * r; l2 = 0.0;
+    } else {
+      const double r = rcp_r<double>(sqrt(n0 * n0 + n2 * n2));
+      l0 = -n2 * r; l1 = 0.0; l2 = n0 * r;
+    }
+    const double m0 = n1 * l2 - n2 * l1, m1 = n2 * l0 - n0 * l2, m2 = n0 * l1 - n1 * l0;   // eq 40
+    const double kd = ph.gm1 * rcp_r<double>(c2);                        // eq 37
+    u[0] = (R)vu; u[1] = (R)vv; u[2] = (R)vw;
+    n[0] = (R)n0; n[1] = (R)n1; n[2] = (R)n2;
+    l[0] = (R)l0; l[1] = (R)l1; l[2] = (R)l2;
+    m[0] = (R)m0; m[1] = (R)m1; m[2] = (R)m2;
+    V = (R)Vd;
+    H = (R)(Vd + c2 * ph.inv_gm1);                                      // eq 36
+    un = (R)(vu * n0 + vv * n1 + vw * n2);                              // eq 38
+    ul = (R)(vu * l0 + vv * l1 + vw * l2);
+    um = (R)(vu * m0 + vv * m1 + vw * m2);
+    c = (R)cd;
+    kap = (R)kd;
+    kap1 = (R)(0.5 * kd);
+    chi = (R)(0.5 * rcp_r<double>(cd));
+  }
+  // w = S f
+  __device__ __forceinline__ void to_char(const R* f, R* w) const {
+    const R uf = u[0] * f[1] + u[1] * f[2] + u[2] * f[3];
+    const R a = V * f[0] - uf + f[4];
+    const R b = un * f[0] - (n[0] * f[1] + n[1] * f[2] + n[2] * f[3]);
+    w[0] = f[0] - kap * a;
+    w[1] = (l[0] * f[1] + l[1] * f[2] + l[2] * f[3]) - ul * f[0];
+    w[2] = (m[0] * f[1] + m[1] * f[2] + m[2] * f[3]) - um * f[0];
+    w[3] = kap1 * a + chi * b;
+    w[4] = kap1 * a - chi * b;
+  }
+  // F = S^-1 g
+  __device__ __forceinline__ void from_char(const R* g, R* F) const {
+    const R s = g[3] + g[4];
+    const R d = c * (g[4] - g[3]);
+    const R gs = g[0] + s;
+    F[0] = gs;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) F[1 + i] = u[i] * gs + l[i] * g[1] + m[i] * g[2] + n[i] * d;
+    F[4] = V * g[0] + ul * g[1] + um * g[2] + H * s + un * d;
+  }
+};
+
 // First derivative (times h) at node position pos of a line of n nodes from
 // values val(m) = f_{pos+m}.  Periodic lines and interior nodes use the central
 // operator of half width maxhalf; toward a non-periodic end the order drops as

@@ -130,13 +130,15 @@ struct SweepArgs {
   int hybrid;            // 0: WENO7 everywhere; 1: sensor / flags select the stencil
   int lowdiss;           // OCFD_LOWDISS_*
   int mixed;             // 1: split and reconstruction in FP32 (difference, RK in FP64)
+  int characteristic;    // 1: WENO interfaces reconstructed in characteristic variables
 };
 
 // Kernel launch entry points (ocfd_kernels.hip).  All return hipError_t of the launch.
 hipError_t launch_sweep(int dir, int mode, const SweepArgs& a, hipStream_t st);
-// One direction's sweep (instantiated in ocfd_sweep_{xi,eta,zeta}.hip).
-template <int DIR>
-hipError_t launch_sweep_d(int mode, const SweepArgs& a, hipStream_t st);
+// One direction's sweep, component-wise (CHR false) or in characteristic
+// variables (instantiated in ocfd_sweep_{xi,eta,zeta}[_char].hip).
+template <int DIR, bool CHR>
+hipError_t launch_sweep_dc(int mode, const SweepArgs& a, hipStream_t st);
 // W [5][N] = u, v, w, T, p of U.
 hipError_t launch_prim(const Geo& g, const Phys& ph, const double* U, double* W, hipStream_t st);
 hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const double* met, double* Fv,

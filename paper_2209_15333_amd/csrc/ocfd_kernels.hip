@@ -11,9 +11,14 @@
 namespace ocfd {
 
 hipError_t launch_sweep(int dir, int mode, const SweepArgs& a, hipStream_t st) {
-  if (dir == 0) return launch_sweep_d<0>(mode, a, st);
-  if (dir == 1) return launch_sweep_d<1>(mode, a, st);
-  return launch_sweep_d<2>(mode, a, st);
+  if (a.characteristic) {
+    if (dir == 0) return launch_sweep_dc<0, true>(mode, a, st);
+    if (dir == 1) return launch_sweep_dc<1, true>(mode, a, st);
+    return launch_sweep_dc<2, true>(mode, a, st);
+  }
+  if (dir == 0) return launch_sweep_dc<0, false>(mode, a, st);
+  if (dir == 1) return launch_sweep_dc<1, false>(mode, a, st);
+  return launch_sweep_dc<2, false>(mode, a, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,7 +1,7 @@
 // Directional sweep kernel of the ocfd library (one Runge-Kutta substep of
 // the curvilinear compressible Navier-Stokes solver of Dang et al.,
 // arXiv:2209.15333, Section 2).  Included by one translation unit per
-// direction, each instantiating launch_sweep_d for its direction.
+// direction and reconstruction variables, each instantiating launch_sweep_dc.
 #pragma once
 
 #include "ocfd_device.h"
@@ -31,13 +31,18 @@ namespace ocfd {
 // viscous derivative toward the ends, no wrap).  Periodic lines wrap node
 // positions at load time.  The hybrid scheme reads one flag byte per
 // interface (0: low-dissipation stencil), computed beforehand by a sensor.
+// CHR reconstructs the WENO interfaces in characteristic variables (Sec.
+// 2.2.2): the split fluxes of the window are carried to the characteristic
+// variables of the interface by S, reconstructed field by field and carried
+// back by S^-1.  A linear stencil commutes with the fixed S, so the hybrid's
+// low-dissipation interfaces skip the two products (an exact identity).
 
 constexpr int SW_W = 16;
 constexpr int SW_S = 16;
 constexpr int SW_T = SW_W * SW_S;
 constexpr int RING = 32;
 
-template <int DIR, int MODE, bool HYB, typename R, int BND>
+template <int DIR, int MODE, bool HYB, typename R, int BND, bool CHR>
 __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   constexpr int CD = (DIR == 0) ? 1 : 0;  // direction across the lines of the group
   constexpr int OD = (DIR == 2) ? 1 : 2;  // remaining direction
@@ -248,9 +253,94 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
   NodeIn ahead;
   bool have = load && gcol_ok && JB + 4 + gs <= mmax;
   if (have) ahead = fetch(JB + 4 + gs, gc);
+  // The same in characteristic variables (kind 1 or 2, or a boundary closure).
+  auto reconstruct_char = [&](int j, int col, int kind, double* dst) {
+    const int w0 = per ? (n >= 8 ? wrap1(j, n) : wrap(j, n)) : j;
+    const int w1 = per ? (n >= 8 ? wrap1(j + 1, n) : wrap(j + 1, n)) : j + 1;
+    const long long i0 = base + (long long)col * sc + (long long)w0 * sd;
+    const long long i1 = base + (long long)col * sc + (long long)w1 * sd;
+    double Ua[5], a[3];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) Ua[q] = 0.5 * (A.U[q * N + i0] + A.U[q * N + i1]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) a[q] = 0.5 * (A.met[(3 * DIR + q) * N + i0] + A.met[(3 * DIR + q) * N + i1]);
+    CharFrame<R> fr;
+    fr.init(A.ph, Ua, a);
+    // characteristic values of node j + o of the f+ (sg 0) or f- (sg 1) ring
+    auto proj = [&](int sg, int o, R* w) {
+      const R* B = ring + col + sg * 5 * SW_W + ((j + o) & (RING - 1)) * SLOT;
+      R f[5];
+#pragma unroll
+      for (int q = 0; q < 5; ++q) f[q] = B[q * SW_W];
+      fr.to_char(f, w);
+    };
+    R G[5];
+    if (!per && (j < 3 || j > n - 5)) {
+      // masked WENO5 at the ends of a bounded line; out-of-domain nodes take
+      // the centre node's values (finite, weight zero)
+      auto in = [&](int o) { const int m = j + o; return m >= 0 && m < n; };
+      R wp[5][5], wm[5][5];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        R w[5];
+        proj(0, in(t - 2) ? t - 2 : 0, w);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) wp[k][t] = w[k];
+        proj(1, in(3 - t) ? 3 - t : 1, w);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) wm[k][t] = w[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        G[k] = weno5m<R>(wp[k][0], wp[k][1], wp[k][2], wp[k][3], wp[k][4], eps, in(-2), in(-1), in(2)) +
+               weno5m<R>(wm[k][0], wm[k][1], wm[k][2], wm[k][3], wm[k][4], eps, in(3), in(2), in(-1));
+    } else if (HYB && kind == 2) {
+      R wp[5][5], wm[5][5];
+#pragma unroll
+      for (int t = 0; t < 5; ++t) {
+        R w[5];
+        proj(0, t - 2, w);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) wp[k][t] = w[k];
+        proj(1, 3 - t, w);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) wm[k][t] = w[k];
+      }
+#pragma unroll
+      for (int k = 0; k < 5; ++k)
+        G[k] = weno5m<R>(wp[k][0], wp[k][1], wp[k][2], wp[k][3], wp[k][4], eps, true, true, true) +
+               weno5m<R>(wm[k][0], wm[k][1], wm[k][2], wm[k][3], wm[k][4], eps, true, true, true);
+    } else {
+      // WENO7: f+ window j-3 .. j+3, then the mirrored f- window j+4 .. j-2
+#pragma unroll
+      for (int k = 0; k < 5; ++k) G[k] = (R)0;
+#pragma unroll
+      for (int sg = 0; sg < 2; ++sg) {
+        R wv[5][7];
+#pragma unroll
+        for (int t = 0; t < 7; ++t) {
+          R w[5];
+          proj(sg, sg == 0 ? t - 3 : 4 - t, w);
+#pragma unroll
+          for (int k = 0; k < 5; ++k) wv[k][t] = w[k];
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+          G[k] += weno7<R>(wv[k][0], wv[k][1], wv[k][2], wv[k][3], wv[k][4], wv[k][5], wv[k][6], eps);
+      }
+    }
+    R F[5];
+    fr.from_char(G, F);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) dst[q * SW_W] = (double)F[q];
+  };
   // Reconstruction of interface j of line col into dst: kind 0 the
   // low-dissipation stencil, 1 WENO7, 2 WENO5 (three-way hybrid).
   auto reconstruct = [&](int j, int col, int kind, double* dst) {
+    if (CHR && kind != 0) {
+      reconstruct_char(j, col, kind, dst);
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       const R* P = ring + col + q * SW_W;
@@ -353,45 +443,47 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
 }
 
 // Dynamic LDS: the viscous-flux ring of the FP32 and hybrid kernels.
-template <int DIR, int MODE, int BND>
+template <int DIR, int MODE, int BND, bool CHR>
 static void launch_sweep_b(const SweepArgs& a, dim3 grid, hipStream_t st) {
   const size_t lds = (a.viscous && (a.mixed || a.hybrid)) ? (size_t)RING * (4 * SW_W + 1) * sizeof(double) : 0;
   if (a.mixed) {
     if (a.hybrid)
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, float, BND>), grid, dim3(SW_T), lds, st, a);
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, float, BND, CHR>), grid, dim3(SW_T), lds, st, a);
     else
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, float, BND>), grid, dim3(SW_T), lds, st, a);
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, float, BND, CHR>), grid, dim3(SW_T), lds, st, a);
   } else {
     if (a.hybrid)
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, double, BND>), grid, dim3(SW_T), lds, st, a);
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, double, BND, CHR>), grid, dim3(SW_T), lds, st, a);
     else
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, double, BND>), grid, dim3(SW_T), lds, st, a);
+      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, double, BND, CHR>), grid, dim3(SW_T), lds, st, a);
   }
 }
 
-template <int DIR, int MODE>
+template <int DIR, int MODE, bool CHR>
 static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
   constexpr int CD = (DIR == 0) ? 1 : 0;
   constexpr int OD = (DIR == 2) ? 1 : 2;
   dim3 grid((a.g.n[CD] + SW_W - 1) / SW_W, a.g.n[OD]);
   const bool all = a.g.periodic[0] && a.g.periodic[1] && a.g.periodic[2];
   if (!a.g.periodic[DIR])
-    launch_sweep_b<DIR, MODE, 2>(a, grid, st);
+    launch_sweep_b<DIR, MODE, 2, CHR>(a, grid, st);
   else if (all)
-    launch_sweep_b<DIR, MODE, 0>(a, grid, st);
+    launch_sweep_b<DIR, MODE, 0, CHR>(a, grid, st);
   else
-    launch_sweep_b<DIR, MODE, 1>(a, grid, st);
+    launch_sweep_b<DIR, MODE, 1, CHR>(a, grid, st);
   return hipGetLastError();
 }
 
-template <int DIR>
-hipError_t launch_sweep_d(int mode, const SweepArgs& a, hipStream_t st) {
+// One translation unit per direction and reconstruction variables (component
+// or characteristic) instantiates this, so the variants compile in parallel.
+template <int DIR, bool CHR>
+hipError_t launch_sweep_dc(int mode, const SweepArgs& a, hipStream_t st) {
   if (a.hybrid && a.inviscid && !a.flags) return hipErrorInvalidValue;   // hybrid needs interface flags
   switch (mode) {
-    case MODE_SET: return launch_sweep_t<DIR, MODE_SET>(a, st);
-    case MODE_ADD: return launch_sweep_t<DIR, MODE_ADD>(a, st);
-    case MODE_RK: return launch_sweep_t<DIR, MODE_RK>(a, st);
-    default: return launch_sweep_t<DIR, MODE_DUDT>(a, st);
+    case MODE_SET: return launch_sweep_t<DIR, MODE_SET, CHR>(a, st);
+    case MODE_ADD: return launch_sweep_t<DIR, MODE_ADD, CHR>(a, st);
+    case MODE_RK: return launch_sweep_t<DIR, MODE_RK, CHR>(a, st);
+    default: return launch_sweep_t<DIR, MODE_DUDT, CHR>(a, st);
   }
 }
 

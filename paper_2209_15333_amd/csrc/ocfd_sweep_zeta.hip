@@ -1,6 +1,7 @@
-// Sweep kernels along zeta (all modes, precisions, schemes and boundary kinds).
+// Sweep kernels along zeta reconstructing component by component (all
+// modes, precisions, schemes and boundary kinds).
 #include "ocfd_sweep.h"
 
 namespace ocfd {
-template hipError_t launch_sweep_d<2>(int mode, const SweepArgs& a, hipStream_t st);
+template hipError_t launch_sweep_dc<2, false>(int mode, const SweepArgs& a, hipStream_t st);
 }  // namespace ocfd

@@ -35,8 +35,9 @@ def test_header_and_binding_agree(ocfd):
 
 
 def test_params_struct_layout(ocfd):
-    # 3 + 3 + 6 int32, 3 + 3 + 10 double, 8 int32
-    assert ctypes.sizeof(ocfd.ocfd_params) == 208
+    # 3 + 3 + 6 int32, 3 + 3 + 10 double, 10 int32
+    assert ctypes.sizeof(ocfd.ocfd_params) == 216
+    assert ocfd.ocfd_params.characteristic.offset == 208
     assert ocfd.ocfd_params.bc.offset == 24 and ocfd.ocfd_params.period.offset == 48
     assert ocfd.ocfd_params.Tw.offset == 48 + 8 * 12 and ocfd.ocfd_params.viscous.offset == 48 + 8 * 16
 
@@ -55,7 +56,8 @@ def _params(ocfd, **kw):
 def test_rejects_bad_parameters(ocfd):
     L = ocfd.lib()
     h = ctypes.c_void_p()
-    for bad in (dict(nx=0), dict(gamma=1.0), dict(viscous=4), dict(scheme=7), dict(weno_eps=0.0), dict(Ma=-1.0)):
+    for bad in (dict(nx=0), dict(gamma=1.0), dict(viscous=4), dict(scheme=7), dict(weno_eps=0.0), dict(Ma=-1.0),
+                dict(characteristic=2), dict(reserved0=1)):
         p = _params(ocfd, **bad)
         assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -1, bad
         assert L.ocfd_workspace_bytes(ctypes.byref(p)) == 0
