@@ -240,23 +240,32 @@ def learned_overhead(torch, pk, n, substeps):
 
 
 def form_ramp_mixed(torch, pk, shape, substeps):
-    """Compression ramp: WENO7 FP64 against the FP32 split/reconstruction form
-    from the same inflow state, `substeps` substeps each."""
+    """Compression ramp from the same inflow state, `substeps` substeps each:
+    WENO7 FP64 and its FP32 split/reconstruction form, both again in
+    characteristic variables, and the three-way hybrid in characteristic
+    variables.  FP32 forms carry their relative L2 against the FP64 form of
+    the same scheme."""
     import dataclasses
     import workloads
     case = workloads.compression_ramp(shape=shape)
     U = torch.from_numpy(case.U0).cuda()
+    forms = (("weno7_fp64", dict(precision="fp64"), None),
+             ("weno7_fp32", dict(precision="mixed"), "weno7_fp64"),
+             ("weno7_char_fp64", dict(characteristic=True), None),
+             ("weno7_char_fp32", dict(characteristic=True, precision="mixed"), "weno7_char_fp64"),
+             ("hybrid3_char_fp64", dict(characteristic=True, scheme="hybrid", lowdiss="ud7", three_way=True), None))
     res = {}
-    ref = None
-    for name, prec in (("weno7_fp64", "fp64"), ("weno7_fp32", "mixed")):
-        c = dataclasses.replace(case, precision=prec)
+    finals = {}
+    for name, kw, vs in forms:
+        c = dataclasses.replace(case, **kw)
         rate, Uf, sv = _timed_run(torch, pk, c, U, substeps)
         entry = {"gpt_substeps_per_s": round(rate, 4)}
-        if ref is None:
-            ref = Uf
+        if vs is None:
+            finals[name] = Uf
         else:
-            entry["rel_l2_vs_fp64"] = [float(f"{e:.3e}") for e in _rel_l2(torch, Uf, ref)]
-            entry["speedup_vs_fp64"] = round(rate / res["weno7_fp64"]["gpt_substeps_per_s"], 3)
+            entry[f"rel_l2_vs_{vs}"] = [float(f"{e:.3e}") for e in _rel_l2(torch, Uf, finals[vs])]
+        if name != "weno7_fp64":
+            entry["speedup_vs_weno7_fp64"] = round(rate / res["weno7_fp64"]["gpt_substeps_per_s"], 3)
         res[name] = entry
         _log(f"ramp: {name}: {entry}")
         sv.close()
@@ -282,6 +291,8 @@ def main():
                     help="also time the learned sensor's kernels on the 256^3 Taylor-Green run")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the isotropic-turbulence and compression-ramp form comparisons")
+    ap.add_argument("--forms", choices=["all", "hit", "ramp"], default="all",
+                    help="which form comparisons to run (unless --no-forms)")
     ap.add_argument("--hit-n", type=int, default=512)
     ap.add_argument("--hit-develop", type=int, default=2500,
                     help="plain FP64 hybrid substeps before the forms are timed (t ~ 0.9 at 512^3)")
@@ -380,10 +391,13 @@ def main():
     overhead = learned_overhead(torch, pk, args.n, args.steps) if args.learned_overhead else None
     forms = None
     if not args.no_forms:
-        forms = {"isotropic_turbulence": form_hit_learned(torch, pk, args.hit_n, args.hit_develop, 50,
-                                                          args.form_substeps),
-                 "compression_ramp": form_ramp_mixed(torch, pk, tuple(int(v) for v in args.ramp_shape.split(",")),
-                                                     args.form_substeps)}
+        forms = {}
+        if args.forms in ("all", "hit"):
+            forms["isotropic_turbulence"] = form_hit_learned(torch, pk, args.hit_n, args.hit_develop, 50,
+                                                             args.form_substeps)
+        if args.forms in ("all", "ramp"):
+            forms["compression_ramp"] = form_ramp_mixed(torch, pk, tuple(int(v) for v in args.ramp_shape.split(",")),
+                                                        args.form_substeps)
 
     cpu = None
     if not args.no_cpu_baseline:
