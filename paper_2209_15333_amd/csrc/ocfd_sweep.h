@@ -250,9 +250,11 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     const int m = JB + pm - 3;
     if (col0 + pc < ncol && (per || (m >= 0 && m < n))) split_store(m, pc, fetch(m, pc));
   }
+  // Characteristic kernels fetch each chunk's nodes when they split them
+  // instead of one chunk ahead: the registers go to the longer reconstruction.
   NodeIn ahead;
   bool have = load && gcol_ok && JB + 4 + gs <= mmax;
-  if (have) ahead = fetch(JB + 4 + gs, gc);
+  if (!CHR && have) ahead = fetch(JB + 4 + gs, gc);
   // The same in characteristic variables (kind 1 or 2, or a boundary closure).
   auto reconstruct_char = [&](int j, int col, int kind, double* dst) {
     const int w0 = per ? (n >= 8 ? wrap1(j, n) : wrap(j, n)) : j;
@@ -274,56 +276,33 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
       for (int q = 0; q < 5; ++q) f[q] = B[q * SW_W];
       fr.to_char(f, w);
     };
+    // One projected 7-node window per sign serves every stencil: WENO7 takes
+    // positions 0..6 (f+ nodes j-3 .. j+3, f- mirrored j+4 .. j-2), WENO5
+    // positions 1..5.  At the ends of a bounded line (masked WENO5) the
+    // substencils that leave it get weight zero and out-of-domain nodes take
+    // the centre node's values (finite).
+    const bool closure = !per && (j < 3 || j > n - 5);
+    const bool w5 = closure || (HYB && kind == 2);
+    auto in = [&](int o) { const int m = j + o; return !closure || (m >= 0 && m < n); };
     R G[5];
-    if (!per && (j < 3 || j > n - 5)) {
-      // masked WENO5 at the ends of a bounded line; out-of-domain nodes take
-      // the centre node's values (finite, weight zero)
-      auto in = [&](int o) { const int m = j + o; return m >= 0 && m < n; };
-      R wp[5][5], wm[5][5];
 #pragma unroll
-      for (int t = 0; t < 5; ++t) {
+    for (int k = 0; k < 5; ++k) G[k] = (R)0;
+#pragma unroll
+    for (int sg = 0; sg < 2; ++sg) {
+      R wv[5][7];
+#pragma unroll
+      for (int t = 0; t < 7; ++t) {
+        const int o = sg == 0 ? t - 3 : 4 - t;
         R w[5];
-        proj(0, in(t - 2) ? t - 2 : 0, w);
+        proj(sg, in(o) ? o : (sg == 0 ? 0 : 1), w);
 #pragma unroll
-        for (int k = 0; k < 5; ++k) wp[k][t] = w[k];
-        proj(1, in(3 - t) ? 3 - t : 1, w);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) wm[k][t] = w[k];
+        for (int k = 0; k < 5; ++k) wv[k][t] = w[k];
       }
+      if (w5) {
+        const bool v0 = sg == 0 ? in(-2) : in(3), v1 = sg == 0 ? in(-1) : in(2), v2 = sg == 0 ? in(2) : in(-1);
 #pragma unroll
-      for (int k = 0; k < 5; ++k)
-        G[k] = weno5m<R>(wp[k][0], wp[k][1], wp[k][2], wp[k][3], wp[k][4], eps, in(-2), in(-1), in(2)) +
-               weno5m<R>(wm[k][0], wm[k][1], wm[k][2], wm[k][3], wm[k][4], eps, in(3), in(2), in(-1));
-    } else if (HYB && kind == 2) {
-      R wp[5][5], wm[5][5];
-#pragma unroll
-      for (int t = 0; t < 5; ++t) {
-        R w[5];
-        proj(0, t - 2, w);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) wp[k][t] = w[k];
-        proj(1, 3 - t, w);
-#pragma unroll
-        for (int k = 0; k < 5; ++k) wm[k][t] = w[k];
-      }
-#pragma unroll
-      for (int k = 0; k < 5; ++k)
-        G[k] = weno5m<R>(wp[k][0], wp[k][1], wp[k][2], wp[k][3], wp[k][4], eps, true, true, true) +
-               weno5m<R>(wm[k][0], wm[k][1], wm[k][2], wm[k][3], wm[k][4], eps, true, true, true);
-    } else {
-      // WENO7: f+ window j-3 .. j+3, then the mirrored f- window j+4 .. j-2
-#pragma unroll
-      for (int k = 0; k < 5; ++k) G[k] = (R)0;
-#pragma unroll
-      for (int sg = 0; sg < 2; ++sg) {
-        R wv[5][7];
-#pragma unroll
-        for (int t = 0; t < 7; ++t) {
-          R w[5];
-          proj(sg, sg == 0 ? t - 3 : 4 - t, w);
-#pragma unroll
-          for (int k = 0; k < 5; ++k) wv[k][t] = w[k];
-        }
+        for (int k = 0; k < 5; ++k) G[k] += weno5m<R>(wv[k][1], wv[k][2], wv[k][3], wv[k][4], wv[k][5], eps, v0, v1, v2);
+      } else {
 #pragma unroll
         for (int k = 0; k < 5; ++k)
           G[k] += weno7<R>(wv[k][0], wv[k][1], wv[k][2], wv[k][3], wv[k][4], wv[k][5], wv[k][6], eps);
@@ -384,13 +363,15 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     const int jraw = j0 + gs;
     const bool fin = gcol_ok && (per ? (c * SW_S + gs < n && (c > 0 || gs > 0)) : jraw < n);
     const int jfin = per ? (n >= 8 ? wrap1(jraw, n) : wrap(jraw, n)) : jraw;
+    // characteristic kernels load the finishing step's inputs just before it,
+    // which keeps 32 registers free through the longer reconstruction
     EmitIn ein;
-    if (fin) ein = emit_load(jfin, gc);
-    if (have) split_store(j0 + 4 + gs, gc, ahead);
+    if (!CHR && fin) ein = emit_load(jfin, gc);
+    if (have) split_store(j0 + 4 + gs, gc, CHR ? fetch(j0 + 4 + gs, gc) : ahead);
     if (HYB && t == 0) wl_n = 0;
     __syncthreads();
     have = load && gcol_ok && c + 1 < nchunks && j0 + SW_S + 4 + gs <= mmax;
-    if (have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
+    if (!CHR && have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
     const int j = j0 + rs;
     const bool act = A.inviscid && rcol_ok && c * SW_S + rs < nif;
     if (HYB) {
@@ -425,6 +406,7 @@ __global__ __launch_bounds__(SW_T) void k_sweep(const SweepArgs A) {
     // viscous-flux ring stores overwrite slots the finishing step still reads.
     double* const cy_in = (c & 1) ? cyb : fh;
     double* const cy_out = (c & 1) ? fh : cyb;
+    if (CHR && fin) ein = emit_load(jfin, gc);
     if (fin)
       emit(jfin, jraw, gc, fh + (gs + 1) * FHS + gc, gs == 0 ? cy_in + gc : fh + gs * FHS + gc,
            per || (jraw > 0 && jraw < n - 1), FVR, ein);
