@@ -43,7 +43,8 @@ constexpr int SW_T = SW_W * SW_S;
 constexpr int RING = 32;
 
 template <int DIR, int MODE, bool HYB, typename R, int BND, bool CHR>
-__global__ __launch_bounds__(SW_T) __attribute__((amdgpu_waves_per_eu((CHR && !HYB && BND == 2 && sizeof(R) == 8) ? 2 : 1)))
+__global__ __launch_bounds__(SW_T) __attribute__((amdgpu_waves_per_eu(
+    (CHR && sizeof(R) == 8) ? (BND == 2 ? (HYB ? 1 : 2) : 3) : 1)))
 void k_sweep(const SweepArgs A) {
   constexpr int CD = (DIR == 0) ? 1 : 0;  // direction across the lines of the group
   constexpr int OD = (DIR == 2) ? 1 : 2;  // remaining direction
