@@ -538,17 +538,22 @@ static void flux_at(const or_params* P, const double* met, const double* U, cons
 static void viscous_flux_at(const or_params* P, const double* met, const prim_t* q, const int c[3], double Fv[3][4]) {
   const long N = n_nodes(P);
   const long id = lin(P, c);
-  /* Derivatives of u, v, w, T along xi, eta, zeta (sixth order, Sec. 2.3). */
+  /* Derivatives of u, v, w, T along xi, eta, zeta (sixth or eighth order,
+     Sec. 2.3). */
+  const int vh = P->viscous / 2;
   double dq[4][3];
   for (int d = 0; d < 3; ++d) {
-    double vals[4][7];
-    for (int m = -3; m <= 3; ++m) {
+    double vals[4][9];
+    for (int m = -4; m <= 4; ++m) {
       long nid;
-      if (!shifted(P, c, d, m, &nid, NULL)) { for (int s = 0; s < 4; ++s) vals[s][m + 3] = 0.0; continue; }
-      vals[0][m + 3] = q[nid].u; vals[1][m + 3] = q[nid].v; vals[2][m + 3] = q[nid].w; vals[3][m + 3] = q[nid].T;
+      if (m < -vh || m > vh || !shifted(P, c, d, m, &nid, NULL)) {
+        for (int s = 0; s < 4; ++s) vals[s][m + 4] = 0.0;
+        continue;
+      }
+      vals[0][m + 4] = q[nid].u; vals[1][m + 4] = q[nid].v; vals[2][m + 4] = q[nid].w; vals[3][m + 4] = q[nid].T;
     }
     for (int s = 0; s < 4; ++s)
-      dq[s][d] = line_derivative(vals[s], 3, c[d], dim_n(P, d), P->periodic[d], 3, P->h[d]);
+      dq[s][d] = line_derivative(vals[s], 4, c[d], dim_n(P, d), P->periodic[d], vh, P->h[d]);
   }
   /* Chain rule: d/dx_col = sum_d (metric_{d,col}/J) / (1/J) * d/d(direction d). */
   double Jinv = met[9 * N + id];
@@ -588,9 +593,9 @@ static int on_boundary(const or_params* P, const int c[3]) {
 
 /* dU/dt at node c from its interface fluxes and viscous fluxes:
    Fl[d] = flux at c-1/2, Fr[d] = flux at c+1/2 along d;
-   Fvn[d][m+3][s] = viscous flux component s of direction d at node c+m e_d. */
+   Fvn[d][m+4][s] = viscous flux component s of direction d at node c+m e_d. */
 static void assemble(const or_params* P, const double* met, const int c[3], int32_t parts,
-                     const double Fl[3][5], const double Fr[3][5], const double Fvn[3][7][4], double out[5]) {
+                     const double Fl[3][5], const double Fr[3][5], const double Fvn[3][9][4], double out[5]) {
   const long N = n_nodes(P);
   double rhs[5] = {0, 0, 0, 0, 0};
   if (on_boundary(P, c)) { for (int m = 0; m < 5; ++m) out[m] = 0.0; return; }
@@ -599,9 +604,9 @@ static void assemble(const or_params* P, const double* met, const int c[3], int3
       for (int m = 0; m < 5; ++m) rhs[m] -= (Fr[d][m] - Fl[d][m]) / P->h[d];
     if ((parts & OR_PART_VISC) && P->viscous)
       for (int s = 0; s < 4; ++s) {
-        double vals[7];
-        for (int t = 0; t < 7; ++t) vals[t] = Fvn[d][t][s];
-        rhs[s + 1] += line_derivative(vals, 3, c[d], dim_n(P, d), P->periodic[d], 3, P->h[d]);
+        double vals[9];
+        for (int t = 0; t < 9; ++t) vals[t] = Fvn[d][t][s];
+        rhs[s + 1] += line_derivative(vals, 4, c[d], dim_n(P, d), P->periodic[d], P->viscous / 2, P->h[d]);
       }
   }
   double Jinv = met[9 * N + lin(P, c)];
@@ -686,7 +691,7 @@ int or_dudt(const or_params* P, const double* met, const double* U, const uint8_
 #pragma omp parallel for schedule(static)
   for (long id = 0; id < N; ++id) {
     int c[3]; unlin(P, id, c);
-    double Fl[3][5], Fr[3][5], Fvn[3][7][4];
+    double Fl[3][5], Fr[3][5], Fvn[3][9][4];
     for (int d = 0; d < 3; ++d) {
       long nl;
       int okl = shifted(P, c, d, -1, &nl, NULL);
@@ -694,9 +699,9 @@ int or_dudt(const or_params* P, const double* met, const double* U, const uint8_
         Fr[d][m] = F[(long)(5 * d + m) * N + id];
         Fl[d][m] = okl ? F[(long)(5 * d + m) * N + nl] : 0.0;
       }
-      for (int t = 0; t < 7; ++t) {
+      for (int t = 0; t < 9; ++t) {
         long nid;
-        int ok = shifted(P, c, d, t - 3, &nid, NULL);
+        int ok = t - 4 >= -P->viscous / 2 && t - 4 <= P->viscous / 2 && shifted(P, c, d, t - 4, &nid, NULL);
         for (int s = 0; s < 4; ++s) Fvn[d][t][s] = ok ? Fv[(long)(4 * d + s) * N + nid] : 0.0;
       }
     }
@@ -719,7 +724,7 @@ int or_dudt_points(const or_params* P, const double* met, const double* U, const
 #pragma omp parallel for schedule(dynamic)
   for (int64_t s = 0; s < npts; ++s) {
     int c[3]; unlin(P, (long)nodes[s], c);
-    double Fl[3][5], Fr[3][5], Fvn[3][7][4];
+    double Fl[3][5], Fr[3][5], Fvn[3][9][4];
     for (int d = 0; d < 3; ++d) {
       for (int m = 0; m < 5; ++m) Fl[d][m] = Fr[d][m] = 0.0;
       if (parts & (1 << d)) {
@@ -730,11 +735,12 @@ int or_dudt_points(const or_params* P, const double* met, const double* U, const
           flux_at(P, met, U, q, flags, cl, d, Fl[d]);
         }
       }
-      for (int t = 0; t < 7; ++t) {
+      for (int t = 0; t < 9; ++t) {
         long nid;
         for (int k = 0; k < 4; ++k) Fvn[d][t][k] = 0.0;
         if (!((parts & OR_PART_VISC) && P->viscous)) continue;
-        if (!shifted(P, c, d, t - 3, &nid, NULL)) continue;
+        if (t - 4 < -P->viscous / 2 || t - 4 > P->viscous / 2) continue;
+        if (!shifted(P, c, d, t - 4, &nid, NULL)) continue;
         int cn[3]; unlin(P, nid, cn);
         double v[3][4];
         viscous_flux_at(P, met, q, cn, v);

@@ -40,7 +40,7 @@ typedef struct {
   double Tw;             /* isothermal wall temperature / reference temperature */
   double theta1, theta2; /* sensor thresholds (eq 43) */
   double eps;            /* WENO epsilon */
-  int32_t viscous;       /* 0: Euler; 6: sixth-order central viscous terms (Sec. 2.3) */
+  int32_t viscous;       /* 0: Euler; 6 or 8: sixth- or eighth-order central viscous terms (Sec. 2.3) */
   int32_t scheme;        /* OR_WENO7 or OR_HYBRID */
   int32_t lowdiss;       /* OR_UD7 or OR_C8 */
   int32_t three_way;     /* hybrid with the WENO5 tier above theta2 */
