@@ -273,7 +273,7 @@ def form_ramp_mixed(torch, pk, shape, substeps):
         torch.cuda.empty_cache()
     nx, ny, nz = shape
     return {"workload": f"Mach 2.9 24-degree compression ramp {nx}x{ny}x{nz}, inflow/outflow/isothermal wall "
-                        f"Tw 2.84/periodic span, C6 viscous, Re_delta 5e4; {substeps} substeps from the inflow state",
+                        f"Tw 2.84/periodic span, C8 viscous, Re_delta 5e4; {substeps} substeps from the inflow state",
             "forms": res}
 
 

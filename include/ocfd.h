@@ -110,7 +110,10 @@ typedef struct ocfd_params {
   double Tw;               /* wall temperature / reference temperature (WALL faces, > 0) */
   double theta1, theta2;   /* sensor thresholds of eq 43 */
   double weno_eps;         /* epsilon of the WENO nonlinear weights */
-  int32_t viscous;         /* 0: Euler; 6: sixth-order central viscous terms */
+  int32_t viscous;         /* 0: Euler; 6 or 8: sixth- or eighth-order central viscous terms (Sec. 2.3:
+                              node gradients and the derivative of the viscous fluxes; on bounded
+                              lines second-order one-sided at the end node, then second-, fourth-
+                              and sixth-order central toward the interior) */
   int32_t scheme;          /* OCFD_SCHEME_* */
   int32_t lowdiss;         /* OCFD_LOWDISS_* */
   int32_t precision;       /* OCFD_PREC_* */

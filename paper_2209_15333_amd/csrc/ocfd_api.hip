@@ -103,7 +103,7 @@ bool valid_params(const ocfd_params* p, std::string* why) {
     if (!(p->h[d] > 0.0) || !std::isfinite(p->h[d])) { *why = "h must be positive and finite"; return false; }
   if (!(p->gamma > 1.0)) { *why = "gamma must exceed 1"; return false; }
   if (!(p->Ma > 0.0)) { *why = "Ma must be positive"; return false; }
-  if (p->viscous != 0 && p->viscous != 6) { *why = "viscous must be 0 or 6"; return false; }
+  if (p->viscous != 0 && p->viscous != 6 && p->viscous != 8) { *why = "viscous must be 0, 6 or 8"; return false; }
   if (p->viscous && !(p->Re > 0.0 && p->Pr > 0.0 && p->Tref > 0.0 && p->suth >= 0.0)) {
     *why = "Re, Pr, Tref must be positive and suth non-negative";
     return false;
@@ -193,6 +193,7 @@ void setup_geo_phys(ocfd_solver* s) {
   ph.theta1 = p.theta1;
   ph.theta2 = p.theta2;
   ph.three_way = p.three_way;
+  ph.vh = p.viscous == 8 ? 4 : 3;
   for (int d = 0; d < 3; ++d) {
     ph.h[d] = p.h[d];
     ph.ih[d] = 1.0 / p.h[d];

@@ -102,6 +102,7 @@ struct Phys {
   double eps;               // WENO epsilon
   double theta1, theta2;    // sensor thresholds (eq 43)
   int three_way;            // plain sensor marks max theta > theta2 with flag 2 (WENO5)
+  int vh;                   // half width of the interior viscous central stencil (3: sixth, 4: eighth order)
   double h[3], ih[3];       // computational spacing and its inverse
   double period[3];
 };

@@ -78,9 +78,11 @@ hipError_t launch_pressure(const Geo& g, const Phys& ph, const double* U, double
 constexpr int VT_X = 64;
 constexpr int VT_Y = 4;
 
+template <int VH>
 __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ W,
                                                    const double* __restrict__ met, double* __restrict__ Fv,
                                                    int ntx, int nty, int nseg, int zseg) {
+  constexpr int ZW = 2 * VH + 1;   // planes of the zeta window
   const int per = gridDim.x / 8;
   const int L = (blockIdx.x % 8) * per + blockIdx.x / 8;
   if (L >= ntx * nty * nseg) return;
@@ -98,43 +100,53 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
   // plane index of k (wrapped when zeta is periodic, clamped otherwise: the
   // clamped planes are loaded but never used by the boundary closure)
   auto zi = [&](int k) { return pz ? wrap(k, nz) : min(max(k, 0), nz - 1); };
-  double zw[4][7];
+  double zw[4][ZW];
 #pragma unroll
-  for (int o = -3; o <= 2; ++o) {
+  for (int o = -VH; o < VH; ++o) {
     const long long id = colid + (long long)zi(k0 + o) * sz;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) zw[q][o + 3] = W[q * N + id];
+    for (int q = 0; q < 4; ++q) zw[q][o + VH] = W[q * N + id];
   }
-  // neighbour offsets along xi and eta (periodic lines; a non-periodic line
-  // uses the closure of line_deriv with direct offsets)
-  const long long xp1 = wrap(i + 1, nx) - i, xm1 = wrap(i - 1, nx) - i;
-  const long long xp2 = wrap(i + 2, nx) - i, xm2 = wrap(i - 2, nx) - i;
-  const long long xp3 = wrap(i + 3, nx) - i, xm3 = wrap(i - 3, nx) - i;
-  const long long yp1 = (long long)(wrap(j + 1, ny) - j) * nx, ym1 = (long long)(wrap(j - 1, ny) - j) * nx;
-  const long long yp2 = (long long)(wrap(j + 2, ny) - j) * nx, ym2 = (long long)(wrap(j - 2, ny) - j) * nx;
-  const long long yp3 = (long long)(wrap(j + 3, ny) - j) * nx, ym3 = (long long)(wrap(j - 3, ny) - j) * nx;
-  for (int k = k0; k < k1; ++k) {
-    const long long idn = colid + (long long)zi(k + 3) * sz;
+  // neighbour offsets along xi and eta of periodic lines (xo[m-1]: +m,
+  // xo[VH+m-1]: -m); a non-periodic line uses the closure of line_deriv with
+  // direct offsets
+  long long xo[2 * VH], yo[2 * VH];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) zw[q][6] = W[q * N + idn];
+  for (int m = 1; m <= VH; ++m) {
+    xo[m - 1] = wrap(i + m, nx) - i;
+    xo[VH + m - 1] = wrap(i - m, nx) - i;
+    yo[m - 1] = (long long)(wrap(j + m, ny) - j) * nx;
+    yo[VH + m - 1] = (long long)(wrap(j - m, ny) - j) * nx;
+  }
+  // interior central derivative of half width VH (sixth or eighth order)
+  auto central = [&](auto val) {
+    if constexpr (VH == 3)
+      return 0.75 * (val(1) - val(-1)) - 0.15 * (val(2) - val(-2)) + (1.0 / 60.0) * (val(3) - val(-3));
+    else
+      return 0.8 * (val(1) - val(-1)) - 0.2 * (val(2) - val(-2)) + (4.0 / 105.0) * (val(3) - val(-3)) -
+             (1.0 / 280.0) * (val(4) - val(-4));
+  };
+  for (int k = k0; k < k1; ++k) {
+    const long long idn = colid + (long long)zi(k + VH) * sz;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) zw[q][ZW - 1] = W[q * N + idn];
     const long long id = colid + (long long)k * sz;
     double dq[4][3];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const double* f = W + q * N + id;
       if (px)
-        dq[q][0] = (0.75 * (f[xp1] - f[xm1]) - 0.15 * (f[xp2] - f[xm2]) + (1.0 / 60.0) * (f[xp3] - f[xm3])) * ph.ih[0];
+        dq[q][0] = central([&](int m) { return f[m > 0 ? xo[m - 1] : xo[VH - m - 1]]; }) * ph.ih[0];
       else
-        dq[q][0] = line_deriv([&](int m) { return f[m]; }, i, nx, false, 3) * ph.ih[0];
+        dq[q][0] = line_deriv([&](int m) { return f[m]; }, i, nx, false, VH) * ph.ih[0];
       if (py)
-        dq[q][1] = (0.75 * (f[yp1] - f[ym1]) - 0.15 * (f[yp2] - f[ym2]) + (1.0 / 60.0) * (f[yp3] - f[ym3])) * ph.ih[1];
+        dq[q][1] = central([&](int m) { return f[m > 0 ? yo[m - 1] : yo[VH - m - 1]]; }) * ph.ih[1];
       else
-        dq[q][1] = line_deriv([&](int m) { return f[(long long)m * nx]; }, j, ny, false, 3) * ph.ih[1];
+        dq[q][1] = line_deriv([&](int m) { return f[(long long)m * nx]; }, j, ny, false, VH) * ph.ih[1];
       if (pz)
-        dq[q][2] = (0.75 * (zw[q][4] - zw[q][2]) - 0.15 * (zw[q][5] - zw[q][1]) + (1.0 / 60.0) * (zw[q][6] - zw[q][0])) *
-                   ph.ih[2];
+        dq[q][2] = central([&](int m) { return zw[q][VH + m]; }) * ph.ih[2];
       else
-        dq[q][2] = line_deriv([&](int m) { return zw[q][3 + m]; }, k, nz, false, 3) * ph.ih[2];
+        dq[q][2] = line_deriv([&](int m) { return zw[q][VH + m]; }, k, nz, false, VH) * ph.ih[2];
     }
     // metrics are read once and the fluxes written once: non-temporal, so
     // they do not push the planes of u, v, w, T (re-read as neighbours) out of L2
@@ -148,7 +160,7 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
 #pragma unroll
       for (int c = 0; c < 3; ++c)
         gr[q][c] = (m[c] * ij) * dq[q][0] + (m[3 + c] * ij) * dq[q][1] + (m[6 + c] * ij) * dq[q][2];
-    const double T = zw[3][3];
+    const double T = zw[3][VH];
     const double mu = T * sqrt(T) * (1.0 + ph.suth) / (T + ph.suth);
     const double kc = mu * ph.kcoef;
     const double mr = mu * ph.inv_Re;
@@ -158,7 +170,7 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) tau[a][b] = mr * (gr[a][b] + gr[b][a] - (a == b ? (2.0 / 3.0) * div : 0.0));
-    const double u = zw[0][3], v = zw[1][3], w = zw[2][3];
+    const double u = zw[0][VH], v = zw[1][VH], w = zw[2][VH];
     double th[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) th[a] = u * tau[0][a] + v * tau[1][a] + w * tau[2][a] + kc * gr[3][a];
@@ -173,7 +185,7 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
-      for (int o = 0; o < 6; ++o) zw[q][o] = zw[q][o + 1];
+      for (int o = 0; o < ZW - 1; ++o) zw[q][o] = zw[q][o + 1];
   }
 }
 
@@ -188,7 +200,10 @@ hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const
   nseg = (g.n[2] + zseg - 1) / zseg;
   const long long tiles = (long long)ntx * nty * nseg;
   const unsigned nb = (unsigned)(8 * ((tiles + 7) / 8));
-  hipLaunchKernelGGL(k_visc_flux, dim3(nb), dim3(256), 0, st, g, ph, W, met, Fv, ntx, nty, nseg, zseg);
+  if (ph.vh == 4)
+    hipLaunchKernelGGL(k_visc_flux<4>, dim3(nb), dim3(256), 0, st, g, ph, W, met, Fv, ntx, nty, nseg, zseg);
+  else
+    hipLaunchKernelGGL(k_visc_flux<3>, dim3(nb), dim3(256), 0, st, g, ph, W, met, Fv, ntx, nty, nseg, zseg);
   return hipGetLastError();
 }
 

@@ -186,9 +186,10 @@ void k_sweep(const SweepArgs A) {
         const int w = per ? (n >= 8 ? wrap1(p, n) : wrap(p, n)) : p;
         return A.Fv[(long long)(4 * DIR + q) * N + id + (long long)(w - j) * sd];
       };
-      // sixth order inside, then fourth and second order toward the ends of a
-      // bounded line (Sec. 2.3)
-      const int dist = per ? 3 : min(j, n - 1 - j);
+      // sixth or eighth order inside, then sixth, fourth and second order
+      // toward the ends of a bounded line (Sec. 2.3)
+      const int vh = A.ph.vh;
+      const int dist = per ? vh : min(min(j, n - 1 - j), vh);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         double d;
@@ -196,8 +197,11 @@ void k_sweep(const SweepArgs A) {
           d = 0.5 * (F(q, 1) - F(q, -1));
         else if (dist == 2)
           d = (2.0 / 3.0) * (F(q, 1) - F(q, -1)) - (1.0 / 12.0) * (F(q, 2) - F(q, -2));
-        else
+        else if (dist == 3)
           d = 0.75 * (F(q, 1) - F(q, -1)) - 0.15 * (F(q, 2) - F(q, -2)) + (1.0 / 60.0) * (F(q, 3) - F(q, -3));
+        else
+          d = 0.8 * (F(q, 1) - F(q, -1)) - 0.2 * (F(q, 2) - F(q, -2)) + (4.0 / 105.0) * (F(q, 3) - F(q, -3)) -
+              (1.0 / 280.0) * (F(q, 4) - F(q, -4));
         r[q + 1] += d * ih;
       }
     }

@@ -301,7 +301,7 @@ def _smooth_noise(rng, shape, sigma_cells: float = 2.0):
 
 def compression_ramp(shape: Tuple[int, int, int] = (1024, 160, 128), seed: int = 22094, Ma: float = 2.9,
                      angle_deg: float = 24.0, Re: float = 5e4, Tw: float = 2.84, dt: Optional[float] = None,
-                     nsteps: int = 100, noise: float = 0.05) -> Case:
+                     nsteps: int = 100, noise: float = 0.05, viscous: int = 8) -> Case:
     """Supersonic flow over a compression ramp on a body-fitted grid (lengths in
     units of the inflow boundary-layer thickness delta).
 
@@ -314,7 +314,8 @@ def compression_ramp(shape: Tuple[int, int, int] = (1024, 160, 128), seed: int =
     and recovery factor Pr^(1/2), uniform pressure 1/(gamma Ma^2), plus
     noise * u_bar * (Gaussian-smoothed white noise, 2 cells, unit rms) on u,
     v, w (PCG64(seed)).  Boundaries: inflow (the initial profile) at x = -20,
-    extrapolation at the outlet and the top, isothermal wall at y_w."""
+    extrapolation at the outlet and the top, isothermal wall at y_w.  Viscous
+    terms of eighth order, as the paper's ramp runs (Sec. 5.1, 6.1)."""
     nx, ny, nz = shape
     g, Pr = 1.4, 0.72
     r, H, Lz = 0.25, 10.0, 4.0
@@ -353,7 +354,7 @@ def compression_ramp(shape: Tuple[int, int, int] = (1024, 160, 128), seed: int =
     h = (32.0 / (nx - 1), H / (ny - 1), Lz / nz)
     return Case(name=f"ramp{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=U0, period=(0.0, 0.0, Lz), h=h,
                 dt=dt, nsteps=nsteps, periodic=(0, 0, 1), bc=(1, 2, 3, 2, 0, 0), gamma=g, Re=Re, Ma=Ma, Pr=Pr,
-                Tref=108.1, Tw=Tw, inflow=inflow)
+                Tref=108.1, Tw=Tw, inflow=inflow, viscous=viscous)
 
 
 def bounded_box(shape: Tuple[int, int, int] = (36, 20, 18), seed: int = 22095, Ma: float = 0.5, Re: float = 500.0,
