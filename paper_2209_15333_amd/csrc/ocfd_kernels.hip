@@ -69,12 +69,14 @@ hipError_t launch_pressure(const Geo& g, const Phys& ph, const double* U, double
 // Output Fv[4*d + q][N], q = momentum x, y, z, energy.
 //
 // A workgroup owns a 64 x 4 tile of (xi, eta) columns and marches along zeta
-// through one segment of planes, keeping each column's seven-plane window of
-// u, v, w, T in registers, so every plane is read from memory once per
-// segment.  Neighbours along xi and eta are read directly (they sit in the
-// same or adjacent rows of the plane).  Tiles are numbered so that the eight
-// XCDs each receive a contiguous range (round-robin dispatch), which keeps a
-// whole segment of neighbouring tiles on one L2.
+// through one segment of planes, keeping each column's (2 VH + 1)-plane window
+// of u, v, w, T in registers, so every plane is read from memory once per
+// segment.  Neighbours along xi and eta come from an LDS patch of the current
+// plane: the tile (from the register windows) and a ring VH nodes wide
+// around it (read from memory one plane ahead into registers).  Tiles are
+// numbered so that the eight XCDs each receive a contiguous range
+// (round-robin dispatch), which keeps a whole segment of neighbouring tiles
+// on one L2.
 constexpr int VT_X = 64;
 constexpr int VT_Y = 4;
 
@@ -82,24 +84,79 @@ template <int VH>
 __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ W,
                                                    const double* __restrict__ met, double* __restrict__ Fv,
                                                    int ntx, int nty, int nseg, int zseg) {
-  constexpr int ZW = 2 * VH + 1;   // planes of the zeta window
+  constexpr int ZW = 2 * VH + 1;          // planes of the zeta window
+  constexpr int PX = VT_X + 2 * VH;       // patch width (xi) and height (eta)
+  constexpr int PY = VT_Y + 2 * VH;
+  constexpr int NR = PX * PY - VT_X * VT_Y;   // ring nodes around the tile
+  constexpr int NH = (4 * NR + 255) / 256;    // ring values per thread and plane
+  __shared__ double patch[4][PY][PX];
   const int per = gridDim.x / 8;
   const int L = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  if (L >= ntx * nty * nseg) return;
+  if (L >= ntx * nty * nseg) return;          // uniform over the workgroup
   const int tx = L % ntx, ty = (L / ntx) % nty, zs = L / (ntx * nty);
-  const int i = tx * VT_X + (threadIdx.x & (VT_X - 1));
-  const int j = ty * VT_Y + threadIdx.x / VT_X;
+  const int lx = threadIdx.x & (VT_X - 1), ly = threadIdx.x / VT_X;
+  const int i = tx * VT_X + lx;
+  const int j = ty * VT_Y + ly;
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
-  if (i >= nx || j >= ny) return;
+  const bool own = i < nx && j < ny;
   const int k0 = zs * zseg;
   const int k1 = min(nz, k0 + zseg);
   const long long N = g.N;
   const long long sz = g.s[2];
-  const long long colid = i + (long long)nx * j;
   const bool px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
+  // node positions of the patch, wrapped on periodic lines and clamped on
+  // bounded ones (clamped entries are never read by the closures)
+  auto xi_of = [&](int gi) { return px ? wrap(gi, nx) : min(max(gi, 0), nx - 1); };
+  auto eta_of = [&](int gj) { return py ? wrap(gj, ny) : min(max(gj, 0), ny - 1); };
   // plane index of k (wrapped when zeta is periodic, clamped otherwise: the
   // clamped planes are loaded but never used by the boundary closure)
   auto zi = [&](int k) { return pz ? wrap(k, nz) : min(max(k, 0), nz - 1); };
+  // this thread's column (a tile position outside the grid takes the wrapped
+  // or clamped column, so its patch entry holds what a neighbour expects)
+  const long long colid = xi_of(i) + (long long)nx * eta_of(j);
+  // the ring around the tile: patch index and node position (xi + nx eta)
+  // of each of its NR nodes, computed once per workgroup
+  __shared__ int ring_at[NR];
+  __shared__ int ring_pos[NR];
+  for (int r = threadIdx.x; r < NR; r += 256) {
+    int yy, xx;
+    if (r < 2 * VH * PX) {          // full rows above and below the tile
+      yy = r / PX;
+      xx = r % PX;
+      if (yy >= VH) yy += VT_Y;
+    } else {                         // the VH columns left and right of it
+      const int r2 = r - 2 * VH * PX;
+      yy = VH + r2 / (2 * VH);
+      const int c = r2 % (2 * VH);
+      xx = c < VH ? c : VT_X + c;
+    }
+    ring_at[r] = yy * PX + xx;
+    ring_pos[r] = xi_of(tx * VT_X + xx - VH) + nx * eta_of(ty * VT_Y + yy - VH);
+  }
+  __syncthreads();
+  double* const pf = &patch[0][0][0];
+  // ring value s of this thread and plane: value v = thread + 256 s of the
+  // 4 NR (field-major)
+  auto ring_load = [&](double* ring, int k) {
+#pragma unroll
+    for (int s = 0; s < NH; ++s) {
+      const int v = threadIdx.x + 256 * s;
+      if (v < 4 * NR) {
+        const int q = v / NR, r = v - q * NR;
+        ring[s] = W[q * N + ring_pos[r] + (long long)k * sz];
+      }
+    }
+  };
+  auto ring_store = [&](const double* ring) {
+#pragma unroll
+    for (int s = 0; s < NH; ++s) {
+      const int v = threadIdx.x + 256 * s;
+      if (v < 4 * NR) {
+        const int q = v / NR, r = v - q * NR;
+        pf[q * (PX * PY) + ring_at[r]] = ring[s];
+      }
+    }
+  };
   double zw[4][ZW];
 #pragma unroll
   for (int o = -VH; o < VH; ++o) {
@@ -107,17 +164,8 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
 #pragma unroll
     for (int q = 0; q < 4; ++q) zw[q][o + VH] = W[q * N + id];
   }
-  // neighbour offsets along xi and eta of periodic lines (xo[m-1]: +m,
-  // xo[VH+m-1]: -m); a non-periodic line uses the closure of line_deriv with
-  // direct offsets
-  long long xo[2 * VH], yo[2 * VH];
-#pragma unroll
-  for (int m = 1; m <= VH; ++m) {
-    xo[m - 1] = wrap(i + m, nx) - i;
-    xo[VH + m - 1] = wrap(i - m, nx) - i;
-    yo[m - 1] = (long long)(wrap(j + m, ny) - j) * nx;
-    yo[VH + m - 1] = (long long)(wrap(j - m, ny) - j) * nx;
-  }
+  double ring[NH];
+  ring_load(ring, k0);
   // interior central derivative of half width VH (sixth or eighth order)
   auto central = [&](auto val) {
     if constexpr (VH == 3)
@@ -130,58 +178,67 @@ __global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph
     const long long idn = colid + (long long)zi(k + VH) * sz;
 #pragma unroll
     for (int q = 0; q < 4; ++q) zw[q][ZW - 1] = W[q * N + idn];
+    // the patch of plane k: the tile from the windows, the ring prefetched
+#pragma unroll
+    for (int q = 0; q < 4; ++q) patch[q][VH + ly][VH + lx] = zw[q][VH];
+    ring_store(ring);
+    __syncthreads();
+    if (k + 1 < k1) ring_load(ring, k + 1);
     const long long id = colid + (long long)k * sz;
-    double dq[4][3];
+    if (own) {
+      double dq[4][3];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const double* f = W + q * N + id;
-      if (px)
-        dq[q][0] = central([&](int m) { return f[m > 0 ? xo[m - 1] : xo[VH - m - 1]]; }) * ph.ih[0];
-      else
-        dq[q][0] = line_deriv([&](int m) { return f[m]; }, i, nx, false, VH) * ph.ih[0];
-      if (py)
-        dq[q][1] = central([&](int m) { return f[m > 0 ? yo[m - 1] : yo[VH - m - 1]]; }) * ph.ih[1];
-      else
-        dq[q][1] = line_deriv([&](int m) { return f[(long long)m * nx]; }, j, ny, false, VH) * ph.ih[1];
-      if (pz)
-        dq[q][2] = central([&](int m) { return zw[q][VH + m]; }) * ph.ih[2];
-      else
-        dq[q][2] = line_deriv([&](int m) { return zw[q][VH + m]; }, k, nz, false, VH) * ph.ih[2];
+      for (int q = 0; q < 4; ++q) {
+        const double* rowx = &patch[q][VH + ly][VH + lx];
+        if (px)
+          dq[q][0] = central([&](int m) { return rowx[m]; }) * ph.ih[0];
+        else
+          dq[q][0] = line_deriv([&](int m) { return rowx[m]; }, i, nx, false, VH) * ph.ih[0];
+        if (py)
+          dq[q][1] = central([&](int m) { return rowx[m * PX]; }) * ph.ih[1];
+        else
+          dq[q][1] = line_deriv([&](int m) { return rowx[m * PX]; }, j, ny, false, VH) * ph.ih[1];
+        if (pz)
+          dq[q][2] = central([&](int m) { return zw[q][VH + m]; }) * ph.ih[2];
+        else
+          dq[q][2] = line_deriv([&](int m) { return zw[q][VH + m]; }, k, nz, false, VH) * ph.ih[2];
+      }
+      // metrics are read once and the fluxes written once: non-temporal, so
+      // they do not push the planes of u, v, w, T (re-read as neighbours) out of L2
+      const double ij = 1.0 / __builtin_nontemporal_load(met + 9 * N + id);
+      double m[9];
+#pragma unroll
+      for (int r = 0; r < 9; ++r) m[r] = __builtin_nontemporal_load(met + r * N + id);
+      double gr[4][3];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          gr[q][c] = (m[c] * ij) * dq[q][0] + (m[3 + c] * ij) * dq[q][1] + (m[6 + c] * ij) * dq[q][2];
+      const double T = zw[3][VH];
+      const double mu = T * sqrt(T) * (1.0 + ph.suth) / (T + ph.suth);
+      const double kc = mu * ph.kcoef;
+      const double mr = mu * ph.inv_Re;
+      const double div = gr[0][0] + gr[1][1] + gr[2][2];
+      double tau[3][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) tau[a][b] = mr * (gr[a][b] + gr[b][a] - (a == b ? (2.0 / 3.0) * div : 0.0));
+      const double u = zw[0][VH], v = zw[1][VH], w = zw[2][VH];
+      double th[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) th[a] = u * tau[0][a] + v * tau[1][a] + w * tau[2][a] + kc * gr[3][a];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const double m0 = m[3 * d], m1 = m[3 * d + 1], m2 = m[3 * d + 2];
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          __builtin_nontemporal_store(m0 * tau[0][b] + m1 * tau[1][b] + m2 * tau[2][b], Fv + (4 * d + b) * N + id);
+        __builtin_nontemporal_store(m0 * th[0] + m1 * th[1] + m2 * th[2], Fv + (4 * d + 3) * N + id);
+      }
     }
-    // metrics are read once and the fluxes written once: non-temporal, so
-    // they do not push the planes of u, v, w, T (re-read as neighbours) out of L2
-    const double ij = 1.0 / __builtin_nontemporal_load(met + 9 * N + id);
-    double m[9];
-#pragma unroll
-    for (int r = 0; r < 9; ++r) m[r] = __builtin_nontemporal_load(met + r * N + id);
-    double gr[4][3];
-#pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-        gr[q][c] = (m[c] * ij) * dq[q][0] + (m[3 + c] * ij) * dq[q][1] + (m[6 + c] * ij) * dq[q][2];
-    const double T = zw[3][VH];
-    const double mu = T * sqrt(T) * (1.0 + ph.suth) / (T + ph.suth);
-    const double kc = mu * ph.kcoef;
-    const double mr = mu * ph.inv_Re;
-    const double div = gr[0][0] + gr[1][1] + gr[2][2];
-    double tau[3][3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b) tau[a][b] = mr * (gr[a][b] + gr[b][a] - (a == b ? (2.0 / 3.0) * div : 0.0));
-    const double u = zw[0][VH], v = zw[1][VH], w = zw[2][VH];
-    double th[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) th[a] = u * tau[0][a] + v * tau[1][a] + w * tau[2][a] + kc * gr[3][a];
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const double m0 = m[3 * d], m1 = m[3 * d + 1], m2 = m[3 * d + 2];
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        __builtin_nontemporal_store(m0 * tau[0][b] + m1 * tau[1][b] + m2 * tau[2][b], Fv + (4 * d + b) * N + id);
-      __builtin_nontemporal_store(m0 * th[0] + m1 * th[1] + m2 * th[2], Fv + (4 * d + 3) * N + id);
-    }
+    __syncthreads();
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
