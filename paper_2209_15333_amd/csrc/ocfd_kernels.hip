@@ -81,7 +81,7 @@ constexpr int VT_X = 64;
 constexpr int VT_Y = 4;
 
 template <int VH>
-__global__ __launch_bounds__(256, VH == 4 ? 2 : 3) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ W,
+__global__ __launch_bounds__(256, 2) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ W,
                                                    const double* __restrict__ met, double* __restrict__ Fv,
                                                    int ntx, int nty, int nseg, int zseg) {
   constexpr int ZW = 2 * VH + 1;          // planes of the zeta window
