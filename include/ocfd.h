@@ -85,7 +85,12 @@ extern "C" {
 #define OCFD_RED_PMIN 6     /* min pressure */
 #define OCFD_RED_RHOMIN 7   /* min density */
 #define OCFD_RED_NONFINITE 8 /* number of non-finite conserved values */
-#define OCFD_RED_COUNT 9
+#define OCFD_RED_WENO0 9    /* 9..11: fraction of the interfaces of xi, eta, zeta whose stencil in the
+                               last right-hand side was WENO (WENO7, WENO5 or a bounded-end closure);
+                               1 for the WENO7 scheme; NaN for a hybrid solver that has not evaluated
+                               one since its creation or its last ocfd_set_flags (the paper reports
+                               over 90% low-dissipation, Sec. 2.2.3) */
+#define OCFD_RED_COUNT 12
 
 /* Kernel classes timed by the profiling counters. */
 #define OCFD_K_SWEEP_XI 0
@@ -203,7 +208,9 @@ int ocfd_reduce(ocfd_solver* s, double dt, double* out_host);
 
 /* Per-interface scheme flags flags_dev [3][N] (byte: 0 low-dissipation,
    1 WENO7, 2 WENO5) used by the hybrid scheme instead of the sensor, or NULL
-   to go back to the sensor.  The caller keeps the buffer alive while set. */
+   to go back to the sensor.  The caller keeps the buffer alive while set.
+   Resets the WENO fractions of ocfd_reduce to NaN until the next
+   right-hand side. */
 int ocfd_set_flags(ocfd_solver* s, const uint8_t* flags_dev);
 
 /* Kernel timing: when enabled, every launch is bracketed by HIP events on the

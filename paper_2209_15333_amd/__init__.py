@@ -26,7 +26,8 @@ OCFD_PREC_FP64, OCFD_PREC_MIXED = 0, 1
 OCFD_SENSOR_PLAIN, OCFD_SENSOR_LEARNED = 0, 1
 OCFD_BC_NONE, OCFD_BC_INFLOW, OCFD_BC_EXTRAP, OCFD_BC_WALL = 0, 1, 2, 3
 OCFD_PART_XI, OCFD_PART_ETA, OCFD_PART_ZETA, OCFD_PART_VISC, OCFD_PART_ALL = 1, 2, 4, 8, 15
-OCFD_RED_COUNT = 9
+OCFD_RED_WENO0 = 9
+OCFD_RED_COUNT = 12
 OCFD_K_COUNT = 6
 ERRORS = {-1: "BADARG", -2: "BADSIZE", -3: "HIP", -4: "UNSUPPORTED", -5: "STATE"}
 

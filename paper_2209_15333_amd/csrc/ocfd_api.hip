@@ -35,6 +35,8 @@ struct ocfd_solver {
   uint16_t* feat = nullptr;       // [N][4] node features, bf16
   uint8_t* lflags = nullptr;      // [3][N] learned flags
   uint8_t* pflags = nullptr;      // [3][N] plain flags (audit, collection)
+  const uint8_t* last_flags = nullptr;  // flags the last right-hand side read (hybrid)
+  bool rhs_done = false;          // a right-hand side has been evaluated since creation or set_flags
   float* mlp = nullptr;           // [NPARAM] FP32 master weights
   float* adam_m = nullptr;
   float* adam_v = nullptr;
@@ -378,6 +380,8 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
     if (e != hipSuccess) return hip_fail(s, e, "sensor flags kernel");
     flags = s->pflags;
   }
+  s->last_flags = hyb ? flags : nullptr;
+  s->rhs_done = true;
   SweepArgs A;
   memset(&A, 0, sizeof(A));
   A.g = s->g;
@@ -625,17 +629,34 @@ int ocfd_reduce(ocfd_solver* s, double dt, double* out) {
   if (!ready(s, &rc)) return rc;
   if (!out) return fail(s, OCFD_ERR_BADARG, "null output");
   if (!s->have_grid || !s->have_state) return fail(s, OCFD_ERR_STATE, "grid and state must be set first");
-  hipError_t e = launch_reduce(s->g, s->ph, s->Ub[s->stage], s->met, dt, s->partial, reduce_blocks(s->g), s->red,
-                               s->st);
+  const bool hyb = s->p.scheme == OCFD_SCHEME_HYBRID;
+  const uint8_t* fl = hyb && s->rhs_done ? s->last_flags : nullptr;
+  hipError_t e = launch_reduce(s->g, s->ph, s->Ub[s->stage], s->met, dt, fl, s->partial, reduce_blocks(s->g),
+                               s->red, s->st);
   if (e == hipSuccess)
     e = hipMemcpyAsync(out, s->red, OCFD_RED_COUNT * sizeof(double), hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-  return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "reduction");
+  if (e != hipSuccess) return hip_fail(s, e, "reduction");
+  // WENO fractions: counts over the interfaces that exist along each direction
+  const int n[3] = {s->p.nx, s->p.ny, s->p.nz};
+  for (int d = 0; d < 3; ++d) {
+    const double total = (double)s->g.N - (s->p.periodic[d] ? 0.0 : (double)(s->g.N / n[d]));
+    double& f = out[OCFD_RED_WENO0 + d];
+    if (!hyb)
+      f = 1.0;
+    else if (!fl)
+      f = NAN;
+    else
+      f = total > 0.0 ? f / total : 0.0;
+  }
+  return OCFD_OK;
 }
 
 int ocfd_set_flags(ocfd_solver* s, const uint8_t* flags) {
   if (!s) return OCFD_ERR_BADARG;
   s->flags = flags;
+  s->last_flags = nullptr;   // the previous evaluation's flags may belong to a buffer being released
+  s->rhs_done = false;
   return OCFD_OK;
 }
 

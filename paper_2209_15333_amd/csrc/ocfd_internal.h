@@ -155,7 +155,7 @@ hipError_t launch_metric_inner(const Geo& g, const Phys& ph, const double* xyz, 
 hipError_t launch_metric_outer(const Geo& g, const Phys& ph, const double* xyz, const double* inner, double* met,
                                hipStream_t st);
 hipError_t launch_reduce(const Geo& g, const Phys& ph, const double* U, const double* met, double dt,
-                         double* partial, int nblocks, double* out, hipStream_t st);
+                         const uint8_t* flags, double* partial, int nblocks, double* out, hipStream_t st);
 int reduce_blocks(const Geo& g);
 
 // Sensors (ocfd_sensor.hip).

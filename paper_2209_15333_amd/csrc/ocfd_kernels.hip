@@ -460,13 +460,14 @@ int reduce_blocks(const Geo& g) {
   return (int)b;
 }
 
-// Combine two partial records (sums add; CFL max; p, rho min; count add).
+// Combine two partial records (sums add; CFL max; p, rho min; counts add).
 __device__ __forceinline__ void red_combine(double* a, const double* b) {
   for (int q = 0; q < 5; ++q) a[q] += b[q];
   a[5] = fmax(a[5], b[5]);
   a[6] = fmin(a[6], b[6]);
   a[7] = fmin(a[7], b[7]);
   a[8] += b[8];
+  for (int d = 0; d < 3; ++d) a[9 + d] += b[9 + d];
 }
 
 __device__ void block_reduce(double (*sh)[RED_T], double* acc, double* out) {
@@ -488,12 +489,16 @@ __device__ void block_reduce(double (*sh)[RED_T], double* acc, double* out) {
   if (t < NRED) out[t] = sh[t][0];
 }
 
+// Entries 9..11 count the interfaces (node + 1/2 along d, where it exists)
+// whose stencil was WENO: a nonzero flag or a bounded-end closure (flags null:
+// no counts, the host fills in the fractions).
 __global__ __launch_bounds__(RED_T) void k_reduce_partial(const Geo g, const Phys ph, const double* __restrict__ U,
                                                           const double* __restrict__ met, double dt,
+                                                          const uint8_t* __restrict__ flags,
                                                           double* __restrict__ partial) {
   __shared__ double sh[NRED][RED_T];
   const long long N = g.N;
-  double acc[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY, 0.0};
+  double acc[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY, 0.0, 0.0, 0.0, 0.0};
   for (long long id = (long long)blockIdx.x * RED_T + threadIdx.x; id < N; id += (long long)gridDim.x * RED_T) {
     const double jinv = met[9 * N + id];
     double Uq[5];
@@ -516,6 +521,17 @@ __global__ __launch_bounds__(RED_T) void k_reduce_partial(const Geo g, const Phy
     acc[5] = fmax(acc[5], local * dt);
     acc[6] = fmin(acc[6], p);
     acc[7] = fmin(acc[7], rho);
+    if (flags) {
+      int pq[3];
+      node_position(g, id, pq);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        const int n = g.n[d];
+        if (!g.periodic[d] && pq[d] == n - 1) continue;   // no interface at the last node
+        const bool closure = !g.periodic[d] && (pq[d] < 3 || pq[d] > n - 5);
+        acc[9 + d] += (closure || flags[d * N + id] != 0) ? 1.0 : 0.0;
+      }
+    }
   }
   block_reduce(sh, acc, partial + (long long)blockIdx.x * NRED);
 }
@@ -523,14 +539,14 @@ __global__ __launch_bounds__(RED_T) void k_reduce_partial(const Geo g, const Phy
 __global__ __launch_bounds__(RED_T) void k_reduce_final(const double* __restrict__ partial, int nb,
                                                         double* __restrict__ out) {
   __shared__ double sh[NRED][RED_T];
-  double acc[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY, 0.0};
+  double acc[NRED] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, INFINITY, INFINITY, 0.0, 0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nb; b += RED_T) red_combine(acc, partial + (long long)b * NRED);
   block_reduce(sh, acc, out);
 }
 
 hipError_t launch_reduce(const Geo& g, const Phys& ph, const double* U, const double* met, double dt,
-                         double* partial, int nblocks, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_reduce_partial, dim3(nblocks), dim3(RED_T), 0, st, g, ph, U, met, dt, partial);
+                         const uint8_t* flags, double* partial, int nblocks, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_partial, dim3(nblocks), dim3(RED_T), 0, st, g, ph, U, met, dt, flags, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(RED_T), 0, st, partial, nblocks, out);

@@ -126,6 +126,23 @@ def test_bounded_hybrid_parity(pk, torch_cuda, orc, lowdiss):
     print(f"ramp hybrid {lowdiss}: low-dissipation fraction {low:.3f}", flush=True)
     assert 0.05 < low < 0.95
     assert np.array_equal(fl.cpu().numpy(), flags)
+    # WENO fractions of the evaluation: nonzero flags or bounded-end closures,
+    # over the interfaces that exist (none at the last node of a bounded line)
+    s.dudt(_dev(torch_cuda, case.U0))
+    got = np.array(s.reduce(case.dt))[9:12]
+    ref = []
+    for d, ax in enumerate((3, 2, 1)):
+        n = case.U0.shape[ax]
+        pos = np.arange(n).reshape([-1 if a == ax - 1 else 1 for a in range(3)])
+        weno = flags[d] != 0
+        if not case.periodic[d]:
+            exists = np.broadcast_to(pos < n - 1, weno.shape)
+            weno = weno | np.broadcast_to((pos < 3) | (pos > n - 5), weno.shape)
+        else:
+            exists = np.ones_like(weno)
+        ref.append((weno & exists).sum() / exists.sum())
+    print(f"ramp hybrid {lowdiss}: WENO fractions {got} (oracle flags {ref})", flush=True)
+    assert np.allclose(got, ref, rtol=1e-15, atol=0)
     s.advance(3, case.dt)
     got = s.state().cpu().numpy()
     ref, _, _ = orc.advance(P, met, case.U0, 3, case.dt, inflow=case.inflow)

@@ -224,6 +224,28 @@ def test_reduce_parity(pk, torch_cuda, orc):
     mom = np.abs(ref[0]) + np.abs(ref[4])
     assert np.all(np.abs(got[1:4] - ref[1:4]) <= 1e-13 * mom)
     assert got[8] == 0.0
+    assert np.array_equal(got[9:12], [1.0, 1.0, 1.0])   # WENO7 everywhere
+
+
+def test_reduce_weno_fraction(pk, torch_cuda, orc):
+    """Hybrid: per direction, the fraction of interfaces whose flag in the
+    last right-hand side was WENO, against the oracle's flags counted here;
+    NaN before the first evaluation."""
+    case = workloads.taylor_green(shape=(32, 20, 24), distorted=True)
+    case.scheme, case.three_way = "hybrid", True
+    case.U0 = _local_noise(case, 0.08, 11)
+    P, met = _orc(orc, case)
+    theta, flags = orc.sensor(P, case.U0)
+    near = (np.abs(theta - case.theta1) < 1e-12) | (np.abs(theta - case.theta2) < 1e-12)
+    assert not near.any()
+    s = _solver(pk, torch_cuda, case)
+    assert np.all(np.isnan(np.array(s.reduce(case.dt))[9:12]))
+    s.dudt(_dev(torch_cuda, case.U0))
+    got = np.array(s.reduce(case.dt))[9:12]
+    ref = (flags != 0).reshape(3, -1).mean(axis=1)
+    print("WENO fractions", got, ref, flush=True)
+    assert 0.0 < ref.min() and ref.max() < 1.0
+    assert np.array_equal(got, ref)
 
 
 # --------------------------------------------------- full-size configuration
