@@ -32,7 +32,6 @@ FLOPS_SW = 92            # Steger-Warming split of a node, both signs
 FLOPS_WENO7 = 143        # one seventh-order WENO reconstruction
 FLOPS_IFACE = 10 * FLOPS_WENO7 + 5
 FLOPS_DIFF = 10          # flux difference of the five components
-FLOPS_VDIV = 40          # sixth-order derivative of the four viscous fluxes, added
 FLOPS_MODE = {"set": 0, "add": 5, "rk": 30}
 FLOPS_VISC_FLUX = 300    # gradients, chain rule, Sutherland, stresses, heat flux, fluxes
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
@@ -48,8 +47,8 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {"sweep_xi": {"fetch_kib": 2036892, "write_kib": 665600}}
 
 
-def sweep_flops(mode: str, viscous: bool) -> int:
-    return FLOPS_PRIM + FLOPS_SW + FLOPS_IFACE + FLOPS_DIFF + (FLOPS_VDIV if viscous else 0) + FLOPS_MODE[mode]
+def sweep_flops(mode: str) -> int:
+    return FLOPS_PRIM + FLOPS_SW + FLOPS_IFACE + FLOPS_DIFF + FLOPS_MODE[mode]
 
 
 def make_cases(n: int):
@@ -363,12 +362,13 @@ def main():
             print(f"[bench] {k:14s} {ms / cnt * 1e3:9.1f} us/launch  {cnt:6d} launches  {ms:9.2f} ms",
                   file=sys.stderr, flush=True)
     dom = max((k for k in tot if k.startswith("sweep")), key=lambda k: tot[k][0])
-    # The zeta sweep applies the Runge-Kutta update; xi stores, eta accumulates.
-    mode = {"sweep_xi": "set", "sweep_eta": "add", "sweep_zeta": "rk"}[dom]
+    # The xi sweep (last) applies the Runge-Kutta update and eta accumulates;
+    # zeta (first) stores the sum, or adds to the viscous divergence.
     flops_launch = {}
     for c, p in zip(cases, prof):
         ms, cnt = p[dom]
-        flops_launch[c.name] = (sweep_flops(mode, c.viscous > 0) * c.N, ms / cnt)
+        mode = {"sweep_xi": "rk", "sweep_eta": "add", "sweep_zeta": "add" if c.viscous else "set"}[dom]
+        flops_launch[c.name] = (sweep_flops(mode) * c.N, ms / cnt)
     total_flops = sum(f * 1 for f, _ in flops_launch.values())
     total_ms = sum(t for _, t in flops_launch.values())
     achieved = total_flops / (total_ms * 1e-3) / 1e12

@@ -355,6 +355,12 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
   hipError_t e;
   const bool visc = s->p.viscous && (parts & OCFD_PART_VISC);
   const bool hyb = s->p.scheme == OCFD_SCHEME_HYBRID;
+  // Where the viscous derivative goes: the FP32 and hybrid sweeps stage the
+  // viscous fluxes of their direction in an LDS ring and add the derivative
+  // in their finishing step; the FP64 WENO7 sweep keeps its occupancy instead,
+  // and a separate kernel writes the whole divergence first (the sweeps then
+  // accumulate onto it).
+  const bool vdiv = visc && !hyb && s->p.precision != OCFD_PREC_MIXED;
   if (visc) {
     {
       Timed tm(s, OCFD_K_PRIM);
@@ -364,6 +370,8 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
     {
       Timed tm(s, OCFD_K_VISC);
       e = launch_visc_flux(s->g, s->ph, s->W, s->met, s->Fv, s->st);
+      // the divergence of the viscous fluxes opens the sum the sweeps add to
+      if (e == hipSuccess && vdiv) e = launch_visc_div(s->g, s->ph, s->Fv, s->rhs, s->st);
     }
     if (e != hipSuccess) return hip_fail(s, e, "viscous flux kernel");
   }
@@ -388,7 +396,7 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
   A.ph = s->ph;
   A.U = Ucur;
   A.met = s->met;
-  A.Fv = visc ? s->Fv : nullptr;
+  A.Fv = visc && !vdiv ? s->Fv : nullptr;
   A.flags = flags;
   A.rhs = s->rhs;
   A.Un = Un;
@@ -400,14 +408,14 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
   A.lowdiss = s->p.lowdiss;
   A.mixed = s->p.precision == OCFD_PREC_MIXED ? 1 : 0;
   A.characteristic = s->p.characteristic;
-  // zeta first (stores the sum), eta accumulates, xi last: the last sweep
-  // reads and writes the most (sum, U^n, 1/J, output), and along xi those
-  // accesses are contiguous.
+  // zeta first (stores the sum, or adds to the viscous divergence), eta
+  // accumulates, xi last: the last sweep reads and writes the most (sum, U^n,
+  // 1/J, output), and along xi those accesses are contiguous.
   for (int step = 0; step < 3; ++step) {
     const int d = 2 - step;
     A.inviscid = (parts >> d) & 1;
-    A.viscous = visc ? 1 : 0;
-    const int m = step == 0 ? MODE_SET : (step == 1 ? MODE_ADD : mode);
+    A.viscous = visc && !vdiv ? 1 : 0;
+    const int m = step == 0 ? (vdiv ? MODE_ADD : MODE_SET) : (step == 1 ? MODE_ADD : mode);
     Timed tm(s, OCFD_K_SWEEP_XI + d);
     e = launch_sweep(d, m, A, s->st);
     if (e != hipSuccess) return hip_fail(s, e, "sweep kernel");

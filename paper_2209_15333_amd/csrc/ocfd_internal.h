@@ -142,6 +142,8 @@ template <int DIR, bool CHR>
 hipError_t launch_sweep_dc(int mode, const SweepArgs& a, hipStream_t st);
 // W [5][N] = u, v, w, T, p of U.
 hipError_t launch_prim(const Geo& g, const Phys& ph, const double* U, double* W, hipStream_t st);
+// rhs [5][N] = divergence of the viscous fluxes Fv [12][N] (mass row 0).
+hipError_t launch_visc_div(const Geo& g, const Phys& ph, const double* Fv, double* rhs, hipStream_t st);
 hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const double* met, double* Fv,
                             hipStream_t st);
 // One face (d, side) of a bounded direction set by boundary kind `kind`.

@@ -264,6 +264,159 @@ hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const
   return hipGetLastError();
 }
 
+// Divergence of the viscous fluxes (Sec. 2.3): rhs[0] = 0 and, for the
+// momentum and energy rows, rhs[1+q] = sum_d (d/d xi_d of Fv[4d+q]) / h_d,
+// each derivative of half width VH with the closures of line_deriv on
+// bounded lines (end nodes take the one-sided value; their dU/dt is zero
+// anyway).  Each flux is differentiated along its own direction only: the
+// zeta fluxes through a register window of the zeta march, the xi fluxes from
+// an LDS row patch (the tile plus VH columns each side), the eta fluxes from
+// an LDS column patch (the tile plus VH rows above and below, read from memory
+// one plane ahead into registers).  Same tiles and XCD numbering as
+// k_visc_flux.
+template <int VH>
+__global__ __launch_bounds__(256, 2) void k_visc_div(const Geo g, const Phys ph, const double* __restrict__ Fv,
+                                                  double* __restrict__ rhs, int ntx, int nty, int nseg, int zseg) {
+  constexpr int ZW = 2 * VH + 1;
+  constexpr int SX = VT_Y * (VT_X + 2 * VH);   // one field of the xi patch
+  constexpr int SY = (VT_Y + 2 * VH) * VT_X;   // one field of the eta patch
+  constexpr int NRX = VT_Y * 2 * VH;           // halo nodes of the xi patch
+  constexpr int NRY = 2 * VH * VT_X;           // halo nodes of the eta patch
+  constexpr int NR = NRX + NRY;
+  constexpr int NH = (4 * NR + 255) / 256;     // halo values per thread and plane
+  __shared__ double pbuf[4 * SX + 4 * SY];
+  __shared__ int ring_at[NR];                  // offset of field 0 in pbuf
+  __shared__ int ring_pos[NR];                 // node position xi + nx eta
+  const int per = gridDim.x / 8;
+  const int L = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (L >= ntx * nty * nseg) return;           // uniform over the workgroup
+  const int tx = L % ntx, ty = (L / ntx) % nty, zs = L / (ntx * nty);
+  const int lx = threadIdx.x & (VT_X - 1), ly = threadIdx.x / VT_X;
+  const int i = tx * VT_X + lx;
+  const int j = ty * VT_Y + ly;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const bool own = i < nx && j < ny;
+  const int k0 = zs * zseg;
+  const int k1 = min(nz, k0 + zseg);
+  const long long N = g.N;
+  const long long sz = g.s[2];
+  const bool px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
+  auto xi_of = [&](int gi) { return px ? wrap(gi, nx) : min(max(gi, 0), nx - 1); };
+  auto eta_of = [&](int gj) { return py ? wrap(gj, ny) : min(max(gj, 0), ny - 1); };
+  auto zi = [&](int k) { return pz ? wrap(k, nz) : min(max(k, 0), nz - 1); };
+  const long long colid = xi_of(i) + (long long)nx * eta_of(j);
+  for (int r = threadIdx.x; r < NR; r += 256) {
+    int at, gi, gj;
+    if (r < NRX) {                      // xi patch: VH columns left and right of the tile
+      const int row = r / (2 * VH), c = r % (2 * VH);
+      const int xx = c < VH ? c : VT_X + c;
+      at = row * (VT_X + 2 * VH) + xx;
+      gi = tx * VT_X + xx - VH;
+      gj = ty * VT_Y + row;
+    } else {                            // eta patch: VH rows above and below
+      const int r2 = r - NRX;
+      const int row = r2 / VT_X, xx = r2 % VT_X;
+      const int yy = row < VH ? row : row + VT_Y;
+      at = 4 * SX + yy * VT_X + xx;
+      gi = tx * VT_X + xx;
+      gj = ty * VT_Y + yy - VH;
+    }
+    ring_at[r] = at;
+    ring_pos[r] = xi_of(gi) + nx * eta_of(gj);
+  }
+  __syncthreads();
+  // halo value s of this thread: v = thread + 256 s of the 4 NR (field-major);
+  // xi-patch nodes read Fv[q], eta-patch nodes Fv[4 + q]
+  auto ring_load = [&](double* ring, int k) {
+#pragma unroll
+    for (int s = 0; s < NH; ++s) {
+      const int v = threadIdx.x + 256 * s;
+      if (v < 4 * NR) {
+        const int q = v / NR, r = v - q * NR;
+        ring[s] = Fv[(r < NRX ? q : 4 + q) * N + ring_pos[r] + (long long)k * sz];
+      }
+    }
+  };
+  auto ring_store = [&](const double* ring) {
+#pragma unroll
+    for (int s = 0; s < NH; ++s) {
+      const int v = threadIdx.x + 256 * s;
+      if (v < 4 * NR) {
+        const int q = v / NR, r = v - q * NR;
+        pbuf[ring_at[r] + q * (r < NRX ? SX : SY)] = ring[s];
+      }
+    }
+  };
+  double zw[4][ZW];
+#pragma unroll
+  for (int o = -VH; o < VH; ++o) {
+    const long long id = colid + (long long)zi(k0 + o) * sz;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) zw[q][o + VH] = Fv[(8 + q) * N + id];
+  }
+  double ring[NH];
+  ring_load(ring, k0);
+  auto central = [&](auto val) {
+    if constexpr (VH == 3)
+      return 0.75 * (val(1) - val(-1)) - 0.15 * (val(2) - val(-2)) + (1.0 / 60.0) * (val(3) - val(-3));
+    else
+      return 0.8 * (val(1) - val(-1)) - 0.2 * (val(2) - val(-2)) + (4.0 / 105.0) * (val(3) - val(-3)) -
+             (1.0 / 280.0) * (val(4) - val(-4));
+  };
+  for (int k = k0; k < k1; ++k) {
+    const long long id = colid + (long long)k * sz;
+    const long long idn = colid + (long long)zi(k + VH) * sz;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      zw[q][ZW - 1] = Fv[(8 + q) * N + idn];
+      pbuf[q * SX + ly * (VT_X + 2 * VH) + VH + lx] = Fv[q * N + id];
+      pbuf[4 * SX + q * SY + (VH + ly) * VT_X + lx] = Fv[(4 + q) * N + id];
+    }
+    ring_store(ring);
+    __syncthreads();
+    if (k + 1 < k1) ring_load(ring, k + 1);
+    if (own) {
+      double r[5];
+      r[0] = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const double* fx = pbuf + q * SX + ly * (VT_X + 2 * VH) + VH + lx;
+        const double* fy = pbuf + 4 * SX + q * SY + (VH + ly) * VT_X + lx;
+        const double dx = px ? central([&](int m) { return fx[m]; })
+                             : line_deriv([&](int m) { return fx[m]; }, i, nx, false, VH);
+        const double dy = py ? central([&](int m) { return fy[m * VT_X]; })
+                             : line_deriv([&](int m) { return fy[m * VT_X]; }, j, ny, false, VH);
+        const double dz = pz ? central([&](int m) { return zw[q][VH + m]; })
+                             : line_deriv([&](int m) { return zw[q][VH + m]; }, k, nz, false, VH);
+        r[1 + q] = dx * ph.ih[0] + dy * ph.ih[1] + dz * ph.ih[2];
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q) __builtin_nontemporal_store(r[q], rhs + q * N + id);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int o = 0; o < ZW - 1; ++o) zw[q][o] = zw[q][o + 1];
+  }
+}
+
+hipError_t launch_visc_div(const Geo& g, const Phys& ph, const double* Fv, double* rhs, hipStream_t st) {
+  const int ntx = (g.n[0] + VT_X - 1) / VT_X;
+  const int nty = (g.n[1] + VT_Y - 1) / VT_Y;
+  int nseg = (2048 + ntx * nty - 1) / (ntx * nty);
+  nseg = nseg < 1 ? 1 : (nseg > g.n[2] ? g.n[2] : nseg);
+  const int zseg = (g.n[2] + nseg - 1) / nseg;
+  nseg = (g.n[2] + zseg - 1) / zseg;
+  const long long tiles = (long long)ntx * nty * nseg;
+  const unsigned nb = (unsigned)(8 * ((tiles + 7) / 8));
+  if (ph.vh == 4)
+    hipLaunchKernelGGL(k_visc_div<4>, dim3(nb), dim3(256), 0, st, g, ph, Fv, rhs, ntx, nty, nseg, zseg);
+  else
+    hipLaunchKernelGGL(k_visc_div<3>, dim3(nb), dim3(256), 0, st, g, ph, Fv, rhs, ntx, nty, nseg, zseg);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Boundary conditions of a face of a bounded direction.  The paper names the
 // kinds (inflow, extrapolated outflow and far field, isothermal no-slip wall)
