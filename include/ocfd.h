@@ -92,7 +92,8 @@ extern "C" {
                                over 90% low-dissipation, Sec. 2.2.3) */
 #define OCFD_RED_COUNT 12
 
-/* Kernel classes timed by the profiling counters. */
+/* Kernel classes timed by the profiling counters (OCFD_K_VISC: the viscous
+   fluxes and their divergence; OCFD_K_PRIM: the plain sensor's pressure). */
 #define OCFD_K_SWEEP_XI 0
 #define OCFD_K_SWEEP_ETA 1
 #define OCFD_K_SWEEP_ZETA 2

@@ -25,7 +25,7 @@ struct ocfd_solver {
   double* met = nullptr;
   double* Ub[3] = {nullptr, nullptr, nullptr};  // [0] = U^n; [1], [2] = stage values
   double* rhs = nullptr;
-  double* W = nullptr;
+  double* P = nullptr;            // [N] pressure (plain sensor)
   double* Fv = nullptr;
   double* theta = nullptr;
   double* partial = nullptr;
@@ -85,7 +85,7 @@ int hip_fail(ocfd_solver* s, hipError_t e, const char* what) {
 }
 
 // Field-region sizes of the workspace, in doubles per node.
-constexpr int WS_MET = 10, WS_STATE = 5, WS_RHS = 5, WS_PRIM = 5, WS_FV = 12, WS_THETA = 1;
+constexpr int WS_MET = 10, WS_STATE = 5, WS_RHS = 5, WS_PRES = 1, WS_FV = 12, WS_THETA = 1;
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -216,7 +216,7 @@ size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver
   double* u1 = take(WS_STATE * fb);
   double* u2 = take(WS_STATE * fb);
   double* rhs = take(WS_RHS * fb);
-  double* W = take(WS_PRIM * fb);
+  double* pres = take(WS_PRES * fb);
   double* Fv = take(WS_FV * fb);
   double* th = take(WS_THETA * fb);
   double* partial = take((size_t)nred * OCFD_RED_COUNT * sizeof(double));
@@ -238,7 +238,7 @@ size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver
     s->Ub[1] = u1;
     s->Ub[2] = u2;
     s->rhs = rhs;
-    s->W = W;
+    s->P = pres;
     s->Fv = Fv;
     s->theta = th;
     s->partial = partial;
@@ -293,12 +293,17 @@ bool ready(ocfd_solver* s, int* rc) {
   return true;
 }
 
-// Node sensor theta of U into s->theta.  prims_fresh: W already holds the
-// primitives of U (p is its fifth field); otherwise p is computed into it.
-int plain_theta(ocfd_solver* s, const double* U, bool prims_fresh) {
-  double* P = s->W + 4 * s->g.N;
-  hipError_t e = prims_fresh ? hipSuccess : launch_pressure(s->g, s->ph, U, P, s->st);
-  if (e == hipSuccess) e = launch_sensor(s->g, P, s->theta, s->st);
+// Node sensor theta of U into s->theta (the pressure of U into s->P first).
+int plain_theta(ocfd_solver* s, const double* U) {
+  hipError_t e;
+  {
+    Timed tm(s, OCFD_K_PRIM);
+    e = launch_pressure(s->g, s->ph, U, s->P, s->st);
+  }
+  if (e == hipSuccess) {
+    Timed tm(s, OCFD_K_OTHER);
+    e = launch_sensor(s->g, s->P, s->theta, s->st);
+  }
   return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "sensor kernels");
 }
 
@@ -320,7 +325,7 @@ int learned_flags(ocfd_solver* s, const double* Ucur, bool count_substep) {
     if (e != hipSuccess) return hip_fail(s, e, "learned sensor kernels");
   }
   if (count_substep && s->p.audit_every > 0 && k % s->p.audit_every == 0) {
-    int rc = plain_theta(s, Ucur, false);
+    int rc = plain_theta(s, Ucur);
     if (rc) return rc;
     e = launch_plain_flags(s->g, s->ph, s->theta, s->pflags, s->st);
     if (e == hipSuccess) e = launch_flag_stats(s->g, s->pflags, s->lflags, s->cnt, COUNT_BLOCKS, s->st);
@@ -363,13 +368,8 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
   const bool vdiv = visc && !hyb && s->p.precision != OCFD_PREC_MIXED;
   if (visc) {
     {
-      Timed tm(s, OCFD_K_PRIM);
-      e = launch_prim(s->g, s->ph, Ucur, s->W, s->st);
-    }
-    if (e != hipSuccess) return hip_fail(s, e, "prim kernel");
-    {
       Timed tm(s, OCFD_K_VISC);
-      e = launch_visc_flux(s->g, s->ph, s->W, s->met, s->Fv, s->st);
+      e = launch_visc_flux(s->g, s->ph, Ucur, s->met, s->Fv, s->st);
       // the divergence of the viscous fluxes opens the sum the sweeps add to
       if (e == hipSuccess && vdiv) e = launch_visc_div(s->g, s->ph, s->Fv, s->rhs, s->st);
     }
@@ -381,10 +381,12 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
     if (rc) return rc;
     flags = s->lflags;
   } else if (hyb && !flags) {
-    Timed tm(s, OCFD_K_OTHER);
-    int rc = plain_theta(s, Ucur, visc);
+    int rc = plain_theta(s, Ucur);
     if (rc) return rc;
-    e = launch_plain_flags(s->g, s->ph, s->theta, s->pflags, s->st);
+    {
+      Timed tm(s, OCFD_K_OTHER);
+      e = launch_plain_flags(s->g, s->ph, s->theta, s->pflags, s->st);
+    }
     if (e != hipSuccess) return hip_fail(s, e, "sensor flags kernel");
     flags = s->pflags;
   }
@@ -743,7 +745,7 @@ int ocfd_sensor_flags(ocfd_solver* s, const double* U, int32_t which, uint8_t* f
   if (!s->have_grid) return fail(s, OCFD_ERR_STATE, "no grid set");
   hipError_t e;
   if (which == OCFD_SENSOR_PLAIN) {
-    rc = plain_theta(s, U, false);
+    rc = plain_theta(s, U);
     if (rc) return rc;
     e = launch_plain_flags(s->g, s->ph, s->theta, flags, s->st);
   } else if (which == OCFD_SENSOR_LEARNED) {
@@ -788,7 +790,7 @@ int ocfd_sensor_collect(ocfd_solver* s, uint64_t seed, double keep_weno, double 
   const uint32_t tp = (uint32_t)std::min(4294967295.0, keep_weno * 4294967296.0);
   const uint32_t tl = (uint32_t)std::min(4294967295.0, keep_low * 4294967296.0);
   const double* U = s->Ub[s->stage];
-  rc = plain_theta(s, U, false);
+  rc = plain_theta(s, U);
   if (rc) return rc;
   hipError_t e = launch_plain_flags(s->g, s->ph, s->theta, s->pflags, s->st);
   if (e == hipSuccess) e = launch_features(s->g, s->ph, U, s->met, s->feat, s->st);

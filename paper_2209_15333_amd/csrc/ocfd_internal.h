@@ -140,11 +140,10 @@ hipError_t launch_sweep(int dir, int mode, const SweepArgs& a, hipStream_t st);
 // variables (instantiated in ocfd_sweep_{xi,eta,zeta}[_char].hip).
 template <int DIR, bool CHR>
 hipError_t launch_sweep_dc(int mode, const SweepArgs& a, hipStream_t st);
-// W [5][N] = u, v, w, T, p of U.
-hipError_t launch_prim(const Geo& g, const Phys& ph, const double* U, double* W, hipStream_t st);
 // rhs [5][N] = divergence of the viscous fluxes Fv [12][N] (mass row 0).
 hipError_t launch_visc_div(const Geo& g, const Phys& ph, const double* Fv, double* rhs, hipStream_t st);
-hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const double* met, double* Fv,
+// Fv [12][N] (viscous fluxes of xi, eta, zeta; momentum x, y, z, energy) of U.
+hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* U, const double* met, double* Fv,
                             hipStream_t st);
 // One face (d, side) of a bounded direction set by boundary kind `kind`.
 hipError_t launch_bc(const Geo& g, const Phys& ph, double* U, int d, int side, int kind, double Tw,

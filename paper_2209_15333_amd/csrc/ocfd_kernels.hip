@@ -22,26 +22,10 @@ hipError_t launch_sweep(int dir, int mode, const SweepArgs& a, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// Primitive variables and viscous fluxes (eq 9-16, Sec. 2.3)
+// Pressure and viscous fluxes (eq 9-16, Sec. 2.3)
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_prim(const Geo g, const Phys ph, const double* __restrict__ U,
-                                              double* __restrict__ W) {
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= g.N) return;
-  const long long N = g.N;
-  const double rho = U[id];
-  const double ir = 1.0 / rho;
-  const double u = U[N + id] * ir, v = U[2 * N + id] * ir, w = U[3 * N + id] * ir;
-  const double p = ph.gm1 * (U[4 * N + id] - 0.5 * rho * (u * u + v * v + w * w));
-  W[id] = u;
-  W[N + id] = v;
-  W[2 * N + id] = w;
-  W[3 * N + id] = ph.gamma * ph.Ma2 * p * ir;  // T = gamma Ma^2 p / rho (eq 16-17)
-  W[4 * N + id] = p;
-}
-
-// Pressure alone (runs without viscous terms), into P[N].
+// Pressure of every node, into P[N] (the plain sensor's input).
 __global__ __launch_bounds__(256) void k_pressure(const Geo g, const Phys ph, const double* __restrict__ U,
                                                   double* __restrict__ P) {
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -51,18 +35,14 @@ __global__ __launch_bounds__(256) void k_pressure(const Geo g, const Phys ph, co
   P[id] = ph.gm1 * (U[4 * N + id] - 0.5 * (m1 * m1 + m2 * m2 + m3 * m3) / U[id]);
 }
 
-hipError_t launch_prim(const Geo& g, const Phys& ph, const double* U, double* W, hipStream_t st) {
-  hipLaunchKernelGGL(k_prim, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, U, W);
-  return hipGetLastError();
-}
-
 hipError_t launch_pressure(const Geo& g, const Phys& ph, const double* U, double* P, hipStream_t st) {
   hipLaunchKernelGGL(k_pressure, dim3((unsigned)((g.N + 255) / 256)), dim3(256), 0, st, g, ph, U, P);
   return hipGetLastError();
 }
 
-// Viscous flux vectors of the three directions at every node: derivatives of
-// u, v, w, T along xi, eta, zeta; Cartesian gradients by the chain rule with
+// Viscous flux vectors of the three directions at every node, from the
+// conserved variables: u, v, w, T of each node read (eq 5, 8, 16-17);
+// derivatives of u, v, w, T along xi, eta, zeta; Cartesian gradients by the chain rule with
 // the node metrics; Sutherland viscosity (eq 15), heat conductivity (eq 14),
 // stresses (eq 13) and stress work plus heat flux (eq 12); the flux of
 // direction d is (row d of the metrics / J) applied to tau and Theta (eq 9-11).
@@ -81,14 +61,14 @@ constexpr int VT_X = 64;
 constexpr int VT_Y = 4;
 
 template <int VH>
-__global__ __launch_bounds__(256, 2) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ W,
+__global__ __launch_bounds__(256, 2) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ U,
                                                    const double* __restrict__ met, double* __restrict__ Fv,
                                                    int ntx, int nty, int nseg, int zseg) {
   constexpr int ZW = 2 * VH + 1;          // planes of the zeta window
   constexpr int PX = VT_X + 2 * VH;       // patch width (xi) and height (eta)
   constexpr int PY = VT_Y + 2 * VH;
   constexpr int NR = PX * PY - VT_X * VT_Y;   // ring nodes around the tile
-  constexpr int NH = (4 * NR + 255) / 256;    // ring values per thread and plane
+  constexpr int NH = (NR + 255) / 256;        // ring nodes per thread and plane
   __shared__ double patch[4][PY][PX];
   const int per = gridDim.x / 8;
   const int L = (blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -135,36 +115,56 @@ __global__ __launch_bounds__(256, 2) void k_visc_flux(const Geo g, const Phys ph
   }
   __syncthreads();
   double* const pf = &patch[0][0][0];
-  // ring value s of this thread and plane: value v = thread + 256 s of the
-  // 4 NR (field-major)
-  auto ring_load = [&](double* ring, int k) {
+  // u, v, w, T of a node from its conserved variables (eq 5, 8, 16-17)
+  auto prim = [&](const double* c, double* o) {
+    const double rho = c[0];
+    const double ir = 1.0 / rho;
+    const double u = c[1] * ir, v = c[2] * ir, w = c[3] * ir;
+    const double p = ph.gm1 * (c[4] - 0.5 * rho * (u * u + v * v + w * w));
+    o[0] = u;
+    o[1] = v;
+    o[2] = w;
+    o[3] = ph.gamma * ph.Ma2 * p * ir;
+  };
+  // ring node s of this thread: r = thread + 256 s; its conserved variables
+  // are read one plane ahead and turned into u, v, w, T when stored
+  auto ring_load = [&](double (*ring)[5], int k) {
 #pragma unroll
     for (int s = 0; s < NH; ++s) {
-      const int v = threadIdx.x + 256 * s;
-      if (v < 4 * NR) {
-        const int q = v / NR, r = v - q * NR;
-        ring[s] = W[q * N + ring_pos[r] + (long long)k * sz];
+      const int r = threadIdx.x + 256 * s;
+      if (r < NR) {
+        const long long id = ring_pos[r] + (long long)k * sz;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) ring[s][c] = U[c * N + id];
       }
     }
   };
-  auto ring_store = [&](const double* ring) {
+  auto ring_store = [&](const double (*ring)[5]) {
 #pragma unroll
     for (int s = 0; s < NH; ++s) {
-      const int v = threadIdx.x + 256 * s;
-      if (v < 4 * NR) {
-        const int q = v / NR, r = v - q * NR;
-        pf[q * (PX * PY) + ring_at[r]] = ring[s];
+      const int r = threadIdx.x + 256 * s;
+      if (r < NR) {
+        double o[4];
+        prim(ring[s], o);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) pf[q * (PX * PY) + ring_at[r]] = o[q];
       }
     }
   };
+  // the zeta window of this column (u, v, w, T of planes k - VH .. k + VH)
   double zw[4][ZW];
+  auto zload = [&](int k, int slot) {
+    const long long id = colid + (long long)zi(k) * sz;
+    double c[5], o[4];
 #pragma unroll
-  for (int o = -VH; o < VH; ++o) {
-    const long long id = colid + (long long)zi(k0 + o) * sz;
+    for (int q = 0; q < 5; ++q) c[q] = U[q * N + id];
+    prim(c, o);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) zw[q][o + VH] = W[q * N + id];
-  }
-  double ring[NH];
+    for (int q = 0; q < 4; ++q) zw[q][slot] = o[q];
+  };
+#pragma unroll
+  for (int o = -VH; o < VH; ++o) zload(k0 + o, o + VH);
+  double ring[NH][5];
   ring_load(ring, k0);
   // interior central derivative of half width VH (sixth or eighth order)
   auto central = [&](auto val) {
@@ -175,9 +175,7 @@ __global__ __launch_bounds__(256, 2) void k_visc_flux(const Geo g, const Phys ph
              (1.0 / 280.0) * (val(4) - val(-4));
   };
   for (int k = k0; k < k1; ++k) {
-    const long long idn = colid + (long long)zi(k + VH) * sz;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) zw[q][ZW - 1] = W[q * N + idn];
+    zload(k + VH, ZW - 1);
     // the patch of plane k: the tile from the windows, the ring prefetched
 #pragma unroll
     for (int q = 0; q < 4; ++q) patch[q][VH + ly][VH + lx] = zw[q][VH];
@@ -246,7 +244,7 @@ __global__ __launch_bounds__(256, 2) void k_visc_flux(const Geo g, const Phys ph
   }
 }
 
-hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const double* met, double* Fv,
+hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* U, const double* met, double* Fv,
                             hipStream_t st) {
   const int ntx = (g.n[0] + VT_X - 1) / VT_X;
   const int nty = (g.n[1] + VT_Y - 1) / VT_Y;
@@ -258,9 +256,9 @@ hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* W, const
   const long long tiles = (long long)ntx * nty * nseg;
   const unsigned nb = (unsigned)(8 * ((tiles + 7) / 8));
   if (ph.vh == 4)
-    hipLaunchKernelGGL(k_visc_flux<4>, dim3(nb), dim3(256), 0, st, g, ph, W, met, Fv, ntx, nty, nseg, zseg);
+    hipLaunchKernelGGL(k_visc_flux<4>, dim3(nb), dim3(256), 0, st, g, ph, U, met, Fv, ntx, nty, nseg, zseg);
   else
-    hipLaunchKernelGGL(k_visc_flux<3>, dim3(nb), dim3(256), 0, st, g, ph, W, met, Fv, ntx, nty, nseg, zseg);
+    hipLaunchKernelGGL(k_visc_flux<3>, dim3(nb), dim3(256), 0, st, g, ph, U, met, Fv, ntx, nty, nseg, zseg);
   return hipGetLastError();
 }
 
