@@ -19,8 +19,9 @@ namespace ocfd {
 //   2. each thread reconstructs one interface j+1/2 (WENO7, or the hybrid's
 //      low-dissipation stencil) from the ring;
 //   3. each thread forms one node's flux difference (F(j+1/2) - F(j-1/2))/h,
-//      adds the sixth-order derivative of the viscous flux of this direction
-//      and applies the mode (store, accumulate, Runge-Kutta update, dU/dt).
+//      (FP32 and hybrid sweeps) adds the central derivative of the viscous
+//      flux of this direction, and applies the mode (store, accumulate,
+//      Runge-Kutta update, dU/dt).
 // The flux of the chunk's last interface is carried to the next chunk, so
 // every interface is reconstructed exactly once, and the first node of a
 // periodic line is finished after the last chunk with the wrapped flux.
@@ -55,9 +56,10 @@ void k_sweep(const SweepArgs A) {
   constexpr int FHS = 5 * SW_W + 1;
   constexpr int FVS = 4 * SW_W + 1;
   // Viscous-flux neighbours staged in an LDS ring (16.6 KB per workgroup):
-  // pays where the sweep is bound by memory latency (FP32 reconstruction,
-  // hybrid); the FP64 WENO7 sweep keeps three workgroups per CU instead and
-  // reads them from memory.
+  // the FP32 and hybrid sweeps add the derivative of the viscous fluxes of
+  // their direction in the finishing step; the FP64 WENO7 sweep keeps three
+  // workgroups per CU instead and has no viscous code (a separate kernel
+  // writes the viscous divergence it accumulates onto).
   constexpr bool FVR = HYB || sizeof(R) == 4;
   __shared__ R ring[RING * SLOT];
   __shared__ double fh[(SW_S + 1) * FHS];  // fh[0]: carried flux; fh[s+1]: interface j0+s
@@ -178,7 +180,7 @@ void k_sweep(const SweepArgs A) {
     double r[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) r[q] = (A.inviscid && inv) ? -(Fr[q * SW_W] - Fl[q * SW_W]) * ih : 0.0;
-    if (A.viscous && inv) {
+    if (FVR && A.viscous && inv) {
       // F(q, k): component q of the viscous flux at node jr + k
       auto F = [&](int q, int k) {
         if (ringfv) return fvr[((jr + k) & (RING - 1)) * FVS + q * SW_W + col];
@@ -467,6 +469,9 @@ static hipError_t launch_sweep_t(const SweepArgs& a, hipStream_t st) {
 template <int DIR, bool CHR>
 hipError_t launch_sweep_dc(int mode, const SweepArgs& a, hipStream_t st) {
   if (a.hybrid && a.inviscid && !a.flags) return hipErrorInvalidValue;   // hybrid needs interface flags
+  // only the FP32 and hybrid sweeps (LDS ring) add the viscous derivative;
+  // the FP64 WENO7 ones take it from the viscous divergence kernel
+  if (a.viscous && !a.hybrid && !a.mixed) return hipErrorInvalidValue;
   switch (mode) {
     case MODE_SET: return launch_sweep_t<DIR, MODE_SET, CHR>(a, st);
     case MODE_ADD: return launch_sweep_t<DIR, MODE_ADD, CHR>(a, st);
