@@ -352,6 +352,18 @@ __global__ __launch_bounds__(256, 2) void k_visc_div(const Geo g, const Phys ph,
 #pragma unroll
     for (int q = 0; q < 4; ++q) zw[q][o + VH] = Fv[(8 + q) * N + id];
   }
+  // this column's values of the next plane, read one plane ahead: the xi and
+  // eta fluxes of plane k and the zeta fluxes of plane k + VH
+  double nx_own[8], nx_z[4];
+  auto own_load = [&](int k) {
+    const long long id = colid + (long long)k * sz;
+    const long long idz = colid + (long long)zi(k + VH) * sz;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) nx_own[q] = Fv[q * N + id];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) nx_z[q] = Fv[(8 + q) * N + idz];
+  };
+  own_load(k0);
   double ring[NH];
   ring_load(ring, k0);
   auto central = [&](auto val) {
@@ -363,16 +375,18 @@ __global__ __launch_bounds__(256, 2) void k_visc_div(const Geo g, const Phys ph,
   };
   for (int k = k0; k < k1; ++k) {
     const long long id = colid + (long long)k * sz;
-    const long long idn = colid + (long long)zi(k + VH) * sz;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      zw[q][ZW - 1] = Fv[(8 + q) * N + idn];
-      pbuf[q * SX + ly * (VT_X + 2 * VH) + VH + lx] = Fv[q * N + id];
-      pbuf[4 * SX + q * SY + (VH + ly) * VT_X + lx] = Fv[(4 + q) * N + id];
+      zw[q][ZW - 1] = nx_z[q];
+      pbuf[q * SX + ly * (VT_X + 2 * VH) + VH + lx] = nx_own[q];
+      pbuf[4 * SX + q * SY + (VH + ly) * VT_X + lx] = nx_own[4 + q];
     }
     ring_store(ring);
     __syncthreads();
-    if (k + 1 < k1) ring_load(ring, k + 1);
+    if (k + 1 < k1) {
+      ring_load(ring, k + 1);
+      own_load(k + 1);
+    }
     if (own) {
       double r[5];
       r[0] = 0.0;
