@@ -276,6 +276,106 @@ def form_ramp_mixed(torch, pk, shape, substeps):
             "forms": res}
 
 
+def form_ramp_full(torch, pk, shape, train, substeps, report):
+    """The ramp at scale with the full chosen form.  The plain FP64 hybrid
+    (UD7 / WENO7, plain sensor) runs `train` substeps from the inflow state
+    with the plain sensor's flags sampled every 50 substeps; the perceptron is
+    trained and calibrated on the GPU.  Then, from the same inflow state, the
+    plain FP64 hybrid and the FP32 + learned-sensor hybrid (network every
+    substep, audited every `report` substeps, union fallback) run `substeps`
+    substeps each in turns of `report`; after every turn the per-field
+    relative L2 between the two states and the audit rates of the turn are
+    recorded.  Each form's time is the sum of its turns."""
+    import dataclasses
+    import workloads
+    t_all = time.perf_counter()
+    case = dataclasses.replace(workloads.compression_ramp(shape=shape), scheme="hybrid", lowdiss="ud7")
+    nx, ny, nz = shape
+    _log(f"ramp{nx}x{ny}x{nz}: inputs ready ({time.perf_counter() - t_all:.0f} s)")
+    xyz = torch.from_numpy(case.xyz).cuda()
+    inflow = torch.from_numpy(case.inflow).cuda()
+    U0 = torch.from_numpy(case.U0).cuda()
+
+    def solver(c):
+        sv = pk.Solver(pk.params_from(c))
+        sv.set_grid(xyz)
+        sv.set_inflow(inflow)
+        sv.set_state(U0)
+        return sv
+    s = solver(case)
+    cap = 8_000_000
+    buf = torch.empty(pk.ocfd_sensor_sample_bytes(cap), dtype=torch.uint8, device="cuda")
+    pk.ocfd_sensor_bind_samples(s.h, buf)
+    t0 = time.perf_counter()
+    total = 0
+    every = 50
+    for k in range(train // every):
+        s.advance(every, case.dt)
+        total = pk.ocfd_sensor_collect(s.h, 9000 + k, 0.05, 0.0005)
+    torch.cuda.synchronize()
+    t_dev = time.perf_counter() - t0
+    pk.ocfd_sensor_set_params(s.h, workloads.sensor_initial_weights(13))
+    t0 = time.perf_counter()
+    stats = pk.ocfd_sensor_train(s.h, 4, 2048, 3e-3, 9, 0.1)
+    cal = pk.ocfd_sensor_calibrate(s.h, 0.1, 0.5)
+    t_train = time.perf_counter() - t0
+    params = pk.ocfd_sensor_get_params(s.h)
+    tau = cal[0]
+    _log(f"ramp{nx}x{ny}x{nz}: {train} plain substeps in {t_dev:.1f} s, {total} samples; trained in {t_train:.1f} s, "
+         f"tau {tau:.3g}, held-out recall {cal[1]}, false-positive rate {cal[2]:.4f}")
+    del buf
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    plain = solver(case)
+    learned = solver(dataclasses.replace(case, precision="mixed", sensor="learned", sensor_every=1,
+                                         audit_every=report))
+    pk.ocfd_sensor_set_params(learned.h, params)
+    pk.ocfd_sensor_set_threshold(learned.h, tau)
+    t_plain = t_learned = 0.0
+    turns = []
+    prev = [0.0] * 6
+    for k in range(substeps // report):
+        for sv, which in ((plain, "p"), (learned, "l")):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sv.advance(report, case.dt)
+            torch.cuda.synchronize()
+            if which == "p":
+                t_plain += time.perf_counter() - t0
+            else:
+                t_learned += time.perf_counter() - t0
+        a = pk.ocfd_sensor_audit(learned.h)
+        d = [a[i] - prev[i] for i in range(6)]
+        prev = a
+        red = plain.reduce(case.dt)
+        turns.append({"substeps": (k + 1) * report,
+                      "rel_l2_learned_fp32_vs_plain_fp64": [float(f"{e:.3e}") for e in
+                                                            _rel_l2(torch, learned.state(), plain.state())],
+                      "plain_weno_frac": round(d[2] / max(d[1], 1), 5),
+                      "learned_weno_frac": round(d[3] / max(d[1], 1), 5),
+                      "mismatch_rate": round(d[5] / max(d[1], 1), 6),
+                      "missed_frac_of_plain_weno": round(d[4] / max(d[2], 1), 6),
+                      "plain_weno_frac_by_direction": [round(v, 5) for v in red[9:12]]})
+        _log(f"ramp{nx}x{ny}x{nz}: {turns[-1]}")
+    rate_p = case.N * substeps / t_plain / 1e9
+    rate_l = case.N * substeps / t_learned / 1e9
+    plain.close()
+    learned.close()
+    del plain, learned, xyz, inflow, U0
+    torch.cuda.empty_cache()
+    return {"workload": f"Mach 2.9 24-degree compression ramp {nx}x{ny}x{nz} ({case.N} points), C8 viscous, "
+                        f"hybrid UD7 / WENO7 from the inflow state; {substeps} substeps per form",
+            "training": {"plain_substeps": train, "samples": total, "epochs": 4, "batch": 2048,
+                         "loss_first_last": [round(stats[0], 5), round(stats[1], 5)], "tau": tau,
+                         "heldout_recall": cal[1], "heldout_false_positive_rate": round(cal[2], 5),
+                         "train_s": round(t_train, 2)},
+            "forms": {"hybrid_plain_fp64": {"gpt_substeps_per_s": round(rate_p, 4)},
+                      "hybrid_learned_fp32": {"gpt_substeps_per_s": round(rate_l, 4),
+                                              "speedup_vs_hybrid_plain_fp64": round(rate_l / rate_p, 3)}},
+            "every_100_substeps": turns}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -290,8 +390,10 @@ def main():
                     help="also time the learned sensor's kernels on the 256^3 Taylor-Green run")
     ap.add_argument("--no-forms", action="store_true",
                     help="skip the isotropic-turbulence and compression-ramp form comparisons")
-    ap.add_argument("--forms", choices=["all", "hit", "ramp"], default="all",
+    ap.add_argument("--forms", choices=["all", "hit", "ramp", "ramp_full"], default="all",
                     help="which form comparisons to run (unless --no-forms)")
+    ap.add_argument("--ramp-full-shape", type=str, default="2048,256,256")
+    ap.add_argument("--ramp-full-substeps", type=int, default=1000)
     ap.add_argument("--hit-n", type=int, default=512)
     ap.add_argument("--hit-develop", type=int, default=2500,
                     help="plain FP64 hybrid substeps before the forms are timed (t ~ 0.9 at 512^3)")
@@ -398,6 +500,9 @@ def main():
         if args.forms in ("all", "ramp"):
             forms["compression_ramp"] = form_ramp_mixed(torch, pk, tuple(int(v) for v in args.ramp_shape.split(",")),
                                                         args.form_substeps)
+        if args.forms in ("all", "ramp_full"):
+            forms["compression_ramp_at_scale"] = form_ramp_full(
+                torch, pk, tuple(int(v) for v in args.ramp_full_shape.split(",")), 500, args.ramp_full_substeps, 100)
 
     cpu = None
     if not args.no_cpu_baseline:

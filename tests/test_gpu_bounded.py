@@ -205,3 +205,68 @@ def test_ramp_full_size_sampled(pk, torch_cuda, orc):
     ref = orc.dudt_points(P, met, case.U0, nodes).T
     ref_pert = orc.dudt_points(P, met, ulp_perturbed(case.U0), nodes).T
     assert_within_roundoff(got[:, nodes], ref, ref_pert, what=f"{case.name} sampled dU/dt ({len(nodes)} nodes)")
+
+
+def test_ramp_at_scale_hybrid_sampled(pk, torch_cuda, orc):
+    """The ramp at its largest size (2048 x 256 x 256, 134 M points) with the
+    plain FP64 hybrid (UD7 / WENO7, the GPU's own sensor) in the launch
+    configuration the benchmark times: dU/dt at sampled nodes, some within
+    six nodes of the faces, against the oracle node by node (its own sensor
+    over the whole field).  Flags could differ only where theta lies within
+    1e-12 of theta1 in a sampled node's windows; there are none here."""
+    import dataclasses
+    case = dataclasses.replace(workloads.compression_ramp(shape=(2048, 256, 256)), scheme="hybrid", lowdiss="ud7")
+    # the initial pressure is uniform: seeded pressure noise in a ball around
+    # the ramp corner (mid-span) gives the sensor WENO regions
+    rng = np.random.default_rng(19)
+    x = case.xyz[0][case.nz // 2]
+    y = case.xyz[1][case.nz // 2]
+    zi = np.arange(case.nz)[:, None, None] - case.nz // 2
+    ball = np.exp(-(x * x + (y - 1.0) ** 2)[None] / (2.0 * 1.5 ** 2) - zi * zi / (2.0 * 40.0 ** 2))
+    U0 = case.U0.copy()
+    U0[4] *= 1.0 + 0.05 * ball * rng.standard_normal(ball.shape)
+    case.U0 = U0
+    case.inflow = np.ascontiguousarray(U0[:, :, :, 0])
+    print("case", case.name, "hybrid", flush=True)
+    s = _solver(pk, torch_cuda, case)
+    got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy().reshape(5, -1)
+    weno = np.array(s.reduce(case.dt))[9:12]
+    s.close()
+    del s
+    torch_cuda.cuda.empty_cache()
+    print("GPU WENO fractions", weno, flush=True)
+    rng = np.random.default_rng(8)
+    nx, ny, nz = case.nx, case.ny, case.nz
+    edge = np.r_[0:6, nx - 6:nx]
+    wall = np.r_[0:6, ny - 6:ny]
+    near = []
+    for _ in range(30):
+        i = rng.choice(edge) if rng.random() < 0.5 else rng.integers(nx)
+        j = rng.choice(wall) if rng.random() < 0.5 or i not in edge else rng.integers(ny)
+        near.append(i + nx * (j + ny * rng.integers(nz)))
+    # and nodes inside the ball, where WENO7 and low-dissipation interfaces mix
+    inball = np.flatnonzero(ball.reshape(-1) > 0.3)
+    nodes = np.unique(np.r_[rng.choice(case.N, 60, replace=False), near,
+                            rng.choice(inball, 60, replace=False)]).astype(np.int64)
+    P = orc.params_from_case(case, nthreads=0)
+    met = orc.metrics(P, case.xyz)
+    theta, flags = orc.sensor(P, case.U0)
+    assert np.abs(theta - case.theta1).min() > 1e-12
+    ref_frac = []
+    for d, ax in enumerate((3, 2, 1)):
+        n = case.U0.shape[ax]
+        pos = np.arange(n).reshape([-1 if a == ax - 1 else 1 for a in range(3)])
+        w = flags[d] != 0
+        if not case.periodic[d]:
+            exists = np.broadcast_to(pos < n - 1, w.shape)
+            w = w | np.broadcast_to((pos < 3) | (pos > n - 5), w.shape)
+        else:
+            exists = np.ones_like(w)
+        ref_frac.append((w & exists).sum() / exists.sum())
+    print("oracle WENO fractions", ref_frac, flush=True)
+    assert np.allclose(weno, ref_frac, rtol=1e-15, atol=0)
+    assert min(ref_frac) > 0.005   # interior WENO7 interfaces in every direction
+    del theta
+    ref = orc.dudt_points(P, met, case.U0, nodes, flags=flags).T
+    ref_pert = orc.dudt_points(P, met, ulp_perturbed(case.U0), nodes, flags=flags).T
+    assert_within_roundoff(got[:, nodes], ref, ref_pert, what=f"{case.name} hybrid sampled dU/dt ({len(nodes)} nodes)")

@@ -290,12 +290,17 @@ def isotropic_turbulence(n: int = 512, seed: int = 22093, k0: float = 4.0, Mt: f
 
 
 def _smooth_noise(rng, shape, sigma_cells: float = 2.0):
-    """Gaussian-smoothed white noise (periodic smoothing by FFT), unit rms."""
+    """Gaussian-smoothed white noise (periodic smoothing by FFT), unit rms.
+    Real-to-complex transforms on all host cores (the filter is real and
+    even, so the result is the real part of the full complex product)."""
+    import os
+    import scipy.fft
     w = rng.standard_normal(shape)
-    k = [np.fft.fftfreq(n) for n in shape]
-    kk = np.meshgrid(*k, indexing="ij")
-    filt = np.exp(-2.0 * (math.pi * sigma_cells) ** 2 * sum(q * q for q in kk))
-    out = np.real(np.fft.ifftn(np.fft.fftn(w) * filt))
+    k = [np.fft.fftfreq(n) for n in shape[:-1]] + [np.fft.rfftfreq(shape[-1])]
+    filt = np.exp(-2.0 * (math.pi * sigma_cells) ** 2 * (k[0][:, None, None] ** 2 + k[1][None, :, None] ** 2 +
+                                                         k[2][None, None, :] ** 2))
+    nw = os.cpu_count() or 1
+    out = scipy.fft.irfftn(scipy.fft.rfftn(w, workers=nw) * filt, s=shape, workers=nw)
     return out / np.sqrt(np.mean(out * out))
 
 
