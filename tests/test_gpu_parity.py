@@ -279,6 +279,44 @@ def test_full_size_sampled(pk, torch_cuda, orc, which):
     _sampled_parity(pk, torch_cuda, orc, case)
 
 
+def test_hit512_full_size_hybrid_sampled(pk, torch_cuda, orc):
+    """Decaying isotropic turbulence at the benchmark's 512^3 with the plain
+    FP64 hybrid (C8 / WENO7, the GPU's own sensor) in its launch
+    configuration: WENO fractions per direction equal to the oracle's, dU/dt
+    at sampled nodes against the oracle node by node.  The initial field has
+    no shocklets yet: seeded pressure noise in a ball gives the sensor WENO
+    regions."""
+    case = workloads.isotropic_turbulence(512)
+    assert case.scheme == "hybrid"
+    rng = np.random.default_rng(23)
+    n = case.nx
+    c = np.arange(n) - n // 2
+    ball = np.exp(-(c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2) / (2.0 * 40.0 ** 2))
+    U0 = case.U0.copy()
+    U0[4] *= 1.0 + 0.05 * ball * rng.standard_normal(ball.shape)
+    case.U0 = U0
+    s = _solver(pk, torch_cuda, case)
+    got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy().reshape(5, -1)
+    weno = np.array(s.reduce(case.dt))[9:12]
+    s.close()
+    del s
+    torch_cuda.cuda.empty_cache()
+    P, met = _orc(orc, case)
+    theta, flags = orc.sensor(P, case.U0)
+    assert np.abs(theta - case.theta1).min() > 1e-12
+    del theta
+    ref_frac = (flags != 0).reshape(3, -1).mean(axis=1)
+    print("WENO fractions", weno, ref_frac, flush=True)
+    assert np.array_equal(weno, ref_frac)
+    assert ref_frac.min() > 0.005
+    inball = np.flatnonzero(ball.reshape(-1) > 0.3)
+    nodes = np.unique(np.r_[rng.choice(case.N, 60, replace=False), rng.choice(inball, 80, replace=False),
+                            [0, case.N - 1]]).astype(np.int64)
+    L = orc.dudt_points(P, met, case.U0, nodes, flags=flags)
+    L_pert = orc.dudt_points(P, met, _ulp_perturbed(case.U0), nodes, flags=flags)
+    _assert_within_roundoff(got[:, nodes], L.T, L_pert.T, what=f"{case.name} hybrid sampled dU/dt ({len(nodes)} nodes)")
+
+
 def test_full_size_conservation(pk, torch_cuda):
     """Conserved totals after 30 substeps of the 256^3 distorted Taylor-Green
     run stay at their initial values to FP64 roundoff."""
