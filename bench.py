@@ -33,7 +33,6 @@ FLOPS_WENO7 = 143        # one seventh-order WENO reconstruction
 FLOPS_IFACE = 10 * FLOPS_WENO7 + 5
 FLOPS_DIFF = 10          # flux difference of the five components
 FLOPS_MODE = {"set": 0, "add": 5, "rk": 30}
-FLOPS_VISC_FLUX = 300    # gradients, chain rule, Sutherland, stresses, heat flux, fluxes
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 HBM_PEAK_GBS = 8000.0
