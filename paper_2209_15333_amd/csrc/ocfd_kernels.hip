@@ -48,7 +48,7 @@ hipError_t launch_pressure(const Geo& g, const Phys& ph, const double* U, double
 // direction d is (row d of the metrics / J) applied to tau and Theta (eq 9-11).
 // Output Fv[4*d + q][N], q = momentum x, y, z, energy.
 //
-// A workgroup owns a 64 x 4 tile of (xi, eta) columns and marches along zeta
+// A workgroup owns a VT_X x VT_Y tile of (xi, eta) columns and marches along zeta
 // through one segment of planes, keeping each column's (2 VH + 1)-plane window
 // of u, v, w, T in registers, so every plane is read from memory once per
 // segment.  Neighbours along xi and eta come from an LDS patch of the current
@@ -57,10 +57,12 @@ hipError_t launch_pressure(const Geo& g, const Phys& ph, const double* U, double
 // numbered so that the eight XCDs each receive a contiguous range
 // (round-robin dispatch), which keeps a whole segment of neighbouring tiles
 // on one L2.
-constexpr int VT_X = 64;
-constexpr int VT_Y = 4;
+// Tile shapes (xi x eta columns of a workgroup of 256): 32 x 8 for the
+// viscous fluxes (their U ring is five values a node, so the smaller ring
+// pays) and for the eighth-order divergence; 64 x 4 for the sixth-order
+// divergence (measured on MI355X at 256^3 and on the ramp).
 
-template <int VH>
+template <int VH, int VT_X, int VT_Y>
 __global__ __launch_bounds__(256, 2) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ U,
                                                    const double* __restrict__ met, double* __restrict__ Fv,
                                                    int ntx, int nty, int nseg, int zseg) {
@@ -244,21 +246,35 @@ __global__ __launch_bounds__(256, 2) void k_visc_flux(const Geo g, const Phys ph
   }
 }
 
+// Workgroups of a z-marching tile launch: ntx x nty tiles per plane, nseg
+// segments of zseg planes, enough for ~2048 workgroups; a multiple of 8 so
+// the XCD-contiguous numbering is exact.
+struct TileGrid {
+  int ntx, nty, nseg, zseg;
+  unsigned nb;
+};
+static TileGrid tile_grid(const Geo& g, int tx, int ty) {
+  TileGrid t;
+  t.ntx = (g.n[0] + tx - 1) / tx;
+  t.nty = (g.n[1] + ty - 1) / ty;
+  int nseg = (2048 + t.ntx * t.nty - 1) / (t.ntx * t.nty);
+  nseg = nseg < 1 ? 1 : (nseg > g.n[2] ? g.n[2] : nseg);
+  t.zseg = (g.n[2] + nseg - 1) / nseg;
+  t.nseg = (g.n[2] + t.zseg - 1) / t.zseg;
+  const long long tiles = (long long)t.ntx * t.nty * t.nseg;
+  t.nb = (unsigned)(8 * ((tiles + 7) / 8));
+  return t;
+}
+
 hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* U, const double* met, double* Fv,
                             hipStream_t st) {
-  const int ntx = (g.n[0] + VT_X - 1) / VT_X;
-  const int nty = (g.n[1] + VT_Y - 1) / VT_Y;
-  // Enough segments along zeta for ~2048 workgroups.
-  int nseg = (2048 + ntx * nty - 1) / (ntx * nty);
-  nseg = nseg < 1 ? 1 : (nseg > g.n[2] ? g.n[2] : nseg);
-  const int zseg = (g.n[2] + nseg - 1) / nseg;
-  nseg = (g.n[2] + zseg - 1) / zseg;
-  const long long tiles = (long long)ntx * nty * nseg;
-  const unsigned nb = (unsigned)(8 * ((tiles + 7) / 8));
+  const TileGrid t = tile_grid(g, 32, 8);
   if (ph.vh == 4)
-    hipLaunchKernelGGL(k_visc_flux<4>, dim3(nb), dim3(256), 0, st, g, ph, U, met, Fv, ntx, nty, nseg, zseg);
+    hipLaunchKernelGGL((k_visc_flux<4, 32, 8>), dim3(t.nb), dim3(256), 0, st, g, ph, U, met, Fv, t.ntx, t.nty, t.nseg,
+                       t.zseg);
   else
-    hipLaunchKernelGGL(k_visc_flux<3>, dim3(nb), dim3(256), 0, st, g, ph, U, met, Fv, ntx, nty, nseg, zseg);
+    hipLaunchKernelGGL((k_visc_flux<3, 32, 8>), dim3(t.nb), dim3(256), 0, st, g, ph, U, met, Fv, t.ntx, t.nty, t.nseg,
+                       t.zseg);
   return hipGetLastError();
 }
 
@@ -270,9 +286,9 @@ hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* U, const
 // zeta fluxes through a register window of the zeta march, the xi fluxes from
 // an LDS row patch (the tile plus VH columns each side), the eta fluxes from
 // an LDS column patch (the tile plus VH rows above and below, read from memory
-// one plane ahead into registers).  Same tiles and XCD numbering as
+// one plane ahead into registers).  Same tile scheme and XCD numbering as
 // k_visc_flux.
-template <int VH>
+template <int VH, int VT_X, int VT_Y>
 __global__ __launch_bounds__(256, 2) void k_visc_div(const Geo g, const Phys ph, const double* __restrict__ Fv,
                                                   double* __restrict__ rhs, int ntx, int nty, int nseg, int zseg) {
   constexpr int ZW = 2 * VH + 1;
@@ -414,18 +430,15 @@ __global__ __launch_bounds__(256, 2) void k_visc_div(const Geo g, const Phys ph,
 }
 
 hipError_t launch_visc_div(const Geo& g, const Phys& ph, const double* Fv, double* rhs, hipStream_t st) {
-  const int ntx = (g.n[0] + VT_X - 1) / VT_X;
-  const int nty = (g.n[1] + VT_Y - 1) / VT_Y;
-  int nseg = (2048 + ntx * nty - 1) / (ntx * nty);
-  nseg = nseg < 1 ? 1 : (nseg > g.n[2] ? g.n[2] : nseg);
-  const int zseg = (g.n[2] + nseg - 1) / nseg;
-  nseg = (g.n[2] + zseg - 1) / zseg;
-  const long long tiles = (long long)ntx * nty * nseg;
-  const unsigned nb = (unsigned)(8 * ((tiles + 7) / 8));
-  if (ph.vh == 4)
-    hipLaunchKernelGGL(k_visc_div<4>, dim3(nb), dim3(256), 0, st, g, ph, Fv, rhs, ntx, nty, nseg, zseg);
-  else
-    hipLaunchKernelGGL(k_visc_div<3>, dim3(nb), dim3(256), 0, st, g, ph, Fv, rhs, ntx, nty, nseg, zseg);
+  if (ph.vh == 4) {
+    const TileGrid t = tile_grid(g, 32, 8);
+    hipLaunchKernelGGL((k_visc_div<4, 32, 8>), dim3(t.nb), dim3(256), 0, st, g, ph, Fv, rhs, t.ntx, t.nty, t.nseg,
+                       t.zseg);
+  } else {
+    const TileGrid t = tile_grid(g, 64, 4);
+    hipLaunchKernelGGL((k_visc_div<3, 64, 4>), dim3(t.nb), dim3(256), 0, st, g, ph, Fv, rhs, t.ntx, t.nty, t.nseg,
+                       t.zseg);
+  }
   return hipGetLastError();
 }
 
