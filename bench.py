@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # reads FETCH_SIZE = 256 MiB and WRITE_SIZE = 512 MiB, so bytes fetched are
 # 2 x FETCH_SIZE.  Valid for the kernel as committed with that file; other
 # configurations report null.
-PMC_TRAFFIC = {"sweep_xi": {"fetch_kib": 1473260, "write_kib": 665600}}
+PMC_TRAFFIC = {"sweep_xi": {"fetch_kib": 1473148, "write_kib": 665600}}
 
 
 def sweep_flops(mode: str) -> int:
