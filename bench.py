@@ -67,9 +67,20 @@ def cpu_baseline(cases, threads: int):
         total_t += time.perf_counter() - t0
         total_pts += c.N
         del met
+    # the same oracle on one core, on a smaller sample of the same kind
+    import workloads
+    small = workloads.taylor_green(96, distorted=True)
+    P = oracle.params_from_case(small, nthreads=1)
+    met = oracle.metrics(P, small.xyz)
+    t0 = time.perf_counter()
+    oracle.advance(P, met, small.U0, 1, small.dt)
+    t1 = time.perf_counter() - t0
     return {"value": total_pts / total_t / 1e9, "unit": "Gpt-substeps/s", "cores": threads, "kind": "oracle",
             "sample": f"one substep of each of the {len(cases)} runs at full size ({total_pts} point-substeps), "
-                      f"{total_t:.1f} s"}
+                      f"{total_t:.1f} s",
+            "single_core": {"value": small.N / t1 / 1e9, "cores": 1,
+                            "sample": f"one substep of the distorted Taylor-Green vortex at 96^3 ({small.N} "
+                                      f"point-substeps), {t1:.1f} s"}}
 
 
 def _log(msg):
