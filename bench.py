@@ -26,7 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # FP64 flops per grid point of one launch, counted from the formulas of the
-# method (add, multiply, divide and square root count one each).
+# method (add, multiply, divide and square root count one each; an FMA two).
 FLOPS_PRIM = 15          # rho, u, v, w, p and c of a node
 FLOPS_SW = 92            # Steger-Warming split of a node, both signs
 FLOPS_WENO7 = 143        # one seventh-order WENO reconstruction
