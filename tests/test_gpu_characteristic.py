@@ -151,3 +151,61 @@ def test_char_mixed_precision_drift(pk, torch_cuda, orc):
     l2, _ = rel_errors(got, ref)
     print(f"char lax mixed 60 substeps: rel L2 {l2}", flush=True)
     assert np.all(l2 <= 1e-5)
+
+
+def test_char_learned_sensor_hybrid(pk, torch_cuda, orc):
+    """The learned sensor's flags driving the characteristic reconstruction:
+    developed isotropic turbulence, hybrid C8 with WENO7 where the network's
+    probability reaches the threshold.  The threshold sits in the widest gap of
+    the oracle's probabilities; the GPU's flags (bf16 operands, FP32 sums) may
+    still differ at an interface whose probability is at the threshold, and the
+    nodes next to such an interface are left out of the dU/dt comparison."""
+    from oracle import mlp
+    case = workloads.isotropic_turbulence(24, seed=22093)
+    case.scheme, case.lowdiss = "hybrid", "c8"
+    P0 = orc.params_from_case(case)
+    met = orc.metrics(P0, case.xyz)
+    case.U0, _, _ = orc.advance(P0, met, case.U0, 30, case.dt)
+    case = _char(case)
+    case.sensor = "learned"
+    theta = mlp.init_params(5)
+    theta[mlp.NPARAM - 33:mlp.NPARAM - 1] *= 300.0
+    theta32 = theta.astype(np.float32).astype(np.float64)
+    F = mlp.node_features(case.gamma, case.h, met, case.U0).astype(np.float32).astype(np.float64)
+    nodes = np.arange(case.N)
+    p = np.stack([mlp.forward(theta32, mlp.interface_inputs(F, d, nodes), round_bf16=True)[0] for d in range(3)])
+    mid = np.sort(p[(p > 0.1) & (p < 0.9)])
+    g = int(np.argmax(np.diff(mid)))
+    tau = 0.5 * (mid[g] + mid[g + 1])
+    flags = (p >= tau).astype(np.uint8).reshape((3,) + case.U0.shape[1:])
+    frac = flags.reshape(3, -1).mean(axis=1)
+    print(f"tau {tau:.6f} in a gap of {mid[g + 1] - mid[g]:.2e}; WENO fractions {frac}", flush=True)
+    assert np.all(frac > 0.01) and np.all(frac < 0.99)
+
+    s = _solver(pk, torch_cuda, case)
+    pk.ocfd_sensor_set_params(s.h, theta)
+    pk.ocfd_sensor_set_threshold(s.h, tau)
+    fl = torch_cuda.zeros((3,) + case.U0.shape[1:], dtype=torch_cuda.uint8, device="cuda")
+    pk.ocfd_sensor_flags(s.h, _dev(torch_cuda, case.U0), pk.OCFD_SENSOR_LEARNED, fl)
+    bad = fl.cpu().numpy() != flags
+    print("flag disagreements", bad.sum(), flush=True)
+    assert bad.sum() <= 1e-4 * case.N + 2
+    assert np.all(np.abs(p.reshape(bad.shape)[bad] - tau) < 1e-3)
+    # nodes whose stencil reads a disagreeing interface (either side, each direction)
+    near = np.zeros(case.U0.shape[1:], bool)
+    for d in range(3):
+        ax = 2 - d
+        for sh in (-1, 0, 1):
+            near |= np.roll(bad[d], sh, axis=ax)
+    keep = ~near.reshape(-1)
+
+    P = orc.params_from_case(case)
+    ref = orc.dudt(P, met, case.U0, flags=flags)
+    ref_pert = orc.dudt(P, met, ulp_perturbed(case.U0), flags=flags)
+    got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy()
+    sel = lambda a: a.reshape(5, -1)[:, keep]
+    assert_within_roundoff(sel(got), sel(ref), sel(ref_pert), what="char learned hybrid")
+    # and the projection mattered where WENO7 was chosen
+    comp = orc.dudt(orc.params_from_case(dataclasses.replace(case, characteristic=False)), met, case.U0,
+                    flags=flags)
+    assert rel_errors(comp, ref)[0].max() > 1e-8
