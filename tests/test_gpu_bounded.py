@@ -180,31 +180,81 @@ def test_bounded_call_order_errors(pk, torch_cuda):
         t.set_inflow(_dev(torch_cuda, np.zeros((5, 8, 16))))
 
 
-def test_ramp_full_size_sampled(pk, torch_cuda, orc):
-    """The compression ramp at the benchmark's size (1024 x 160 x 128) in its
-    launch configuration: dU/dt at sampled nodes, a third of them within six
-    nodes of the inflow, outflow, wall and top faces, against the oracle
-    evaluated node by node."""
-    case = workloads.compression_ramp()
-    print("case", case.name, flush=True)
-    s = _solver(pk, torch_cuda, case)
-    got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy().reshape(5, -1)
-    del s
-    rng = np.random.default_rng(7)
+def _ramp_noise_ball(case, rng, z_sigma):
+    """Seeded pressure noise in a ball around the ramp corner (mid-span): the
+    initial pressure is uniform, so without it the sensor marks no interior
+    interface.  Returns the ball's weight per node; case.U0 and the inflow
+    face are replaced."""
+    x = case.xyz[0][case.nz // 2]
+    y = case.xyz[1][case.nz // 2]
+    zi = np.arange(case.nz)[:, None, None] - case.nz // 2
+    ball = np.exp(-(x * x + (y - 1.0) ** 2)[None] / (2.0 * 1.5 ** 2) - zi * zi / (2.0 * z_sigma ** 2))
+    U0 = case.U0.copy()
+    U0[4] *= 1.0 + 0.05 * ball * rng.standard_normal(ball.shape)
+    case.U0 = U0
+    case.inflow = np.ascontiguousarray(U0[:, :, :, 0])
+    return ball
+
+
+def _ramp_sample(case, rng, n_any, n_near):
+    """Sampled node indices: n_any anywhere and n_near of them within six
+    nodes of the inflow, outflow, wall or top faces."""
     nx, ny, nz = case.nx, case.ny, case.nz
     edge = np.r_[0:6, nx - 6:nx]
     wall = np.r_[0:6, ny - 6:ny]
     near = []
-    for _ in range(40):
+    for _ in range(n_near):
         i = rng.choice(edge) if rng.random() < 0.5 else rng.integers(nx)
         j = rng.choice(wall) if rng.random() < 0.5 or i not in edge else rng.integers(ny)
         near.append(i + nx * (j + ny * rng.integers(nz)))
-    nodes = np.unique(np.r_[rng.choice(case.N, 80, replace=False), near]).astype(np.int64)
+    return np.r_[rng.choice(case.N, n_any, replace=False), near].astype(np.int64)
+
+
+RAMP_FORMS = {"weno7": {}, "weno7_char": dict(characteristic=True),
+              "hybrid3_char": dict(characteristic=True, scheme="hybrid", lowdiss="ud7", three_way=True)}
+
+
+@pytest.mark.parametrize("form", list(RAMP_FORMS))
+def test_ramp_full_size_sampled(pk, torch_cuda, orc, form):
+    """The compression ramp at the benchmark's size (1024 x 160 x 128) in its
+    launch configuration, for each FP64 form the benchmark times there: WENO7,
+    WENO7 in characteristic variables, and the three-way hybrid in
+    characteristic variables (the GPU's own sensor; seeded pressure noise
+    around the corner so that all three stencils occur).  dU/dt at sampled
+    nodes, a third of them within six nodes of the inflow, outflow, wall and
+    top faces, against the oracle evaluated node by node; the hybrid's oracle
+    uses its own sensor over the whole field."""
+    import dataclasses
+    case = dataclasses.replace(workloads.compression_ramp(), **RAMP_FORMS[form])
+    hyb = case.scheme == "hybrid"
+    rng = np.random.default_rng(7)
+    if hyb:
+        ball = _ramp_noise_ball(case, np.random.default_rng(23), 20.0)
+    print("case", case.name, form, flush=True)
+    s = _solver(pk, torch_cuda, case)
+    got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy().reshape(5, -1)
+    s.close()
+    del s
+    torch_cuda.cuda.empty_cache()
+    nodes = _ramp_sample(case, rng, 80, 40)
+    flags = None
     P = orc.params_from_case(case, nthreads=0)
     met = orc.metrics(P, case.xyz)
-    ref = orc.dudt_points(P, met, case.U0, nodes).T
-    ref_pert = orc.dudt_points(P, met, ulp_perturbed(case.U0), nodes).T
-    assert_within_roundoff(got[:, nodes], ref, ref_pert, what=f"{case.name} sampled dU/dt ({len(nodes)} nodes)")
+    if hyb:
+        nodes = np.r_[nodes, rng.choice(np.flatnonzero(ball.reshape(-1) > 0.3), 60, replace=False)]
+        theta, flags = orc.sensor(P, case.U0)
+        # flags could differ only where theta lies at a threshold
+        assert np.abs(theta - case.theta1).min() > 1e-12 and np.abs(theta - case.theta2).min() > 1e-12
+        del theta
+        inner = flags[:, 8:-8, 8:-8, 8:-8]
+        frac = [(inner == v).mean() for v in (0, 1, 2)]
+        print("interior flag fractions (low, WENO7, WENO5)", frac, flush=True)
+        assert min(frac) > 1e-3
+    nodes = np.unique(nodes)
+    ref = orc.dudt_points(P, met, case.U0, nodes, flags=flags).T
+    ref_pert = orc.dudt_points(P, met, ulp_perturbed(case.U0), nodes, flags=flags).T
+    assert_within_roundoff(got[:, nodes], ref, ref_pert,
+                           what=f"{case.name} {form} sampled dU/dt ({len(nodes)} nodes)")
 
 
 def test_ramp_at_scale_hybrid_sampled(pk, torch_cuda, orc):
@@ -216,17 +266,7 @@ def test_ramp_at_scale_hybrid_sampled(pk, torch_cuda, orc):
     1e-12 of theta1 in a sampled node's windows; there are none here."""
     import dataclasses
     case = dataclasses.replace(workloads.compression_ramp(shape=(2048, 256, 256)), scheme="hybrid", lowdiss="ud7")
-    # the initial pressure is uniform: seeded pressure noise in a ball around
-    # the ramp corner (mid-span) gives the sensor WENO regions
-    rng = np.random.default_rng(19)
-    x = case.xyz[0][case.nz // 2]
-    y = case.xyz[1][case.nz // 2]
-    zi = np.arange(case.nz)[:, None, None] - case.nz // 2
-    ball = np.exp(-(x * x + (y - 1.0) ** 2)[None] / (2.0 * 1.5 ** 2) - zi * zi / (2.0 * 40.0 ** 2))
-    U0 = case.U0.copy()
-    U0[4] *= 1.0 + 0.05 * ball * rng.standard_normal(ball.shape)
-    case.U0 = U0
-    case.inflow = np.ascontiguousarray(U0[:, :, :, 0])
+    ball = _ramp_noise_ball(case, np.random.default_rng(19), 40.0)
     print("case", case.name, "hybrid", flush=True)
     s = _solver(pk, torch_cuda, case)
     got = s.dudt(_dev(torch_cuda, case.U0)).cpu().numpy().reshape(5, -1)
@@ -236,18 +276,9 @@ def test_ramp_at_scale_hybrid_sampled(pk, torch_cuda, orc):
     torch_cuda.cuda.empty_cache()
     print("GPU WENO fractions", weno, flush=True)
     rng = np.random.default_rng(8)
-    nx, ny, nz = case.nx, case.ny, case.nz
-    edge = np.r_[0:6, nx - 6:nx]
-    wall = np.r_[0:6, ny - 6:ny]
-    near = []
-    for _ in range(30):
-        i = rng.choice(edge) if rng.random() < 0.5 else rng.integers(nx)
-        j = rng.choice(wall) if rng.random() < 0.5 or i not in edge else rng.integers(ny)
-        near.append(i + nx * (j + ny * rng.integers(nz)))
+    nodes = _ramp_sample(case, rng, 60, 30)
     # and nodes inside the ball, where WENO7 and low-dissipation interfaces mix
-    inball = np.flatnonzero(ball.reshape(-1) > 0.3)
-    nodes = np.unique(np.r_[rng.choice(case.N, 60, replace=False), near,
-                            rng.choice(inball, 60, replace=False)]).astype(np.int64)
+    nodes = np.unique(np.r_[nodes, rng.choice(np.flatnonzero(ball.reshape(-1) > 0.3), 60, replace=False)])
     P = orc.params_from_case(case, nthreads=0)
     met = orc.metrics(P, case.xyz)
     theta, flags = orc.sensor(P, case.U0)
