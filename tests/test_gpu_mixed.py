@@ -70,3 +70,34 @@ def test_mixed_full_size_drift(pk, which):
     assert np.all(l2 <= TOL_DRIFT)
     assert abs(r1[0] - r0[0]) <= 1e-13 * abs(r0[0])
     assert abs(r1[4] - r0[4]) <= 1e-13 * abs(r0[4])
+
+
+@pytest.mark.parametrize("characteristic", [False, True])
+def test_mixed_ramp_full_size_drift(pk, characteristic):
+    """The compression ramp at the benchmark's size (1024 x 160 x 128, C8
+    viscous terms, inflow, outflow and isothermal wall): 100 substeps of the
+    FP32 form, component-wise and in characteristic variables, against the
+    FP64 path of the same scheme."""
+    import dataclasses
+    import torch
+    case = dataclasses.replace(workloads.compression_ramp(), characteristic=characteristic)
+
+    def run(c):
+        s = pk.Solver(pk.params_from(c))
+        s.set_grid(torch.from_numpy(c.xyz).cuda())
+        s.set_state(torch.from_numpy(c.U0).cuda())
+        s.set_inflow(torch.from_numpy(np.ascontiguousarray(c.inflow)).cuda())
+        s.advance(100, c.dt)
+        out = s.state().cpu().numpy()
+        s.close()
+        del s
+        torch.cuda.empty_cache()
+        return out
+
+    ref = run(case)
+    got = run(dataclasses.replace(case, precision="mixed"))
+    assert np.all(np.isfinite(got))
+    l2, linf = rel_errors(got, ref)
+    print(f"ramp mixed (characteristic {characteristic}) vs FP64 after 100 substeps: rel L2 {l2}, rel Linf {linf}",
+          flush=True)
+    assert np.all(l2 <= TOL_DRIFT)
