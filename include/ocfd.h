@@ -8,8 +8,9 @@
  * stage of the third-order Runge-Kutta scheme, eq 45) evaluates
  *   dU/dt = J * [ -d(F - Fv)/dxi - d(G - Gv)/deta - d(H - Hv)/dzeta ]   (eq 1)
  * with Steger-Warming splitting of the inviscid fluxes (eq 19-30), seventh-order
- * WENO or hybrid reconstruction along each grid direction (Sec. 2.2.3), and
- * sixth-order central viscous and heat-flux terms (eq 9-16, Sec. 2.3).
+ * WENO or hybrid reconstruction along each grid direction (Sec. 2.2.3,
+ * component-wise or in characteristic variables, Sec. 2.2.2), and sixth- or
+ * eighth-order central viscous and heat-flux terms (eq 9-16, Sec. 2.3).
  *
  * Conventions shared by every entry point
  *  - Arrays are structure-of-arrays, field-major, x fastest: field f of node
@@ -39,6 +40,9 @@ extern "C" {
 #define OCFD_ERR_HIP (-3)         /* a HIP runtime call failed */
 #define OCFD_ERR_UNSUPPORTED (-4) /* option combination not built */
 #define OCFD_ERR_STATE (-5)       /* call out of order (e.g. advance before set_state) */
+#define OCFD_ERR_NONFINITE (-6)   /* ocfd_advance's state check found a non-finite conserved value or a
+                                     density or pressure <= 0 (ocfd_substeps_done names the substep) */
+#define OCFD_ERR_CFL (-7)         /* ocfd_advance's state check found the CFL number above cfl_max */
 
 /* Inviscid schemes (Sec. 2.2.3, Table 2). */
 #define OCFD_SCHEME_WENO7 0   /* seventh-order WENO at every interface */
@@ -135,7 +139,16 @@ typedef struct ocfd_params {
                               of the mean of their metric rows) to characteristic variables,
                               reconstructed field by field, carried back by S^-1; 0: component
                               by component.  Linear stencils give the same flux either way. */
+  int32_t check_every;     /* ocfd_advance checks the state after every this many substeps (counted
+                              from ocfd_set_state; 0: never): non-finite conserved values, density or
+                              pressure <= 0 (OCFD_ERR_NONFINITE), CFL number above cfl_max
+                              (OCFD_ERR_CFL); each check synchronises the stream */
+  int32_t flag_window;     /* plain sensor, how node values of theta decide interface j+1/2 (eq 43 applies
+                              theta "at positions"): 0: the maximum over the nodes j-3 .. j+4 of its
+                              stencil; 1: the maximum of theta_j and theta_j+1 */
   int32_t reserved0;       /* must be 0 */
+  double cfl_max;          /* > 0: CFL limit of the state check (the CFL number as OCFD_RED_CFL);
+                              0: no CFL check */
 } ocfd_params;
 
 typedef struct ocfd_solver ocfd_solver;
@@ -146,14 +159,16 @@ int ocfd_params_default(ocfd_params* p);
 
 /* Bytes of device workspace a solver with these parameters needs (0 if the
    parameters are invalid).  The workspace holds the metrics [10][N], three
-   state buffers [5][N], the right-hand side [5][N], the primitive variables
-   [5][N] (u, v, w, T, p) and the viscous fluxes [12][N], all FP64, the sensor and
-   learned-sensor buffers, the inflow face [5][face] and small reduction
-   buffers. */
+   state buffers [5][N], the right-hand-side sum [5][N], the node pressure [N]
+   and sensor [N] and the viscous fluxes [12][N], all FP64, the learned-sensor
+   buffers (node features, two flag fields, network and optimiser state), the
+   inflow face [5][face] and small reduction buffers. */
 size_t ocfd_workspace_bytes(const ocfd_params* p);
 
 /* Create a solver.  stream: a hipStream_t (NULL: the default stream).  The
-   solver copies *p.  Errors: BADARG (null pointer / invalid parameter). */
+   solver copies *p.  Errors: BADARG (null pointer / invalid parameter),
+   UNSUPPORTED (the learned sensor with three_way: the network decides two
+   ways only). */
 int ocfd_create(const ocfd_params* p, void* stream, ocfd_solver** out);
 
 /* Hand the solver caller-owned device memory of at least
@@ -181,21 +196,30 @@ int ocfd_set_metrics(ocfd_solver* s, const double* met_dev);
 int ocfd_get_metrics(ocfd_solver* s, double* met_dev);
 
 /* Set the conserved state U_dev [5][N] = rho, rho u, rho v, rho w, E (eq 5)
-   and restart the Runge-Kutta cycle at stage 0. */
+   and restart the Runge-Kutta cycle at stage 0; the substep count (which
+   times the learned sensor's evaluations, its audits and the state checks)
+   restarts at 0. */
 int ocfd_set_state(ocfd_solver* s, const double* U_dev);
 /* Copy out the current state (the value the next substep starts from). */
 int ocfd_get_state(ocfd_solver* s, double* U_dev);
 /* Mid-step restart: the state at the start of the current step and the stage
    (0, 1, 2).  set_step_state takes the current state, the step-start state
-   and the stage. */
+   and the stage, and sets the substep count to the stage. */
 int ocfd_get_step_state(ocfd_solver* s, double* Un_dev, int32_t* stage_host);
 int ocfd_set_step_state(ocfd_solver* s, const double* U_dev, const double* Un_dev, int32_t stage);
 
 /* Advance n substeps of eq 45 with time step dt: substep k of a step sets
    U(k) = a_k U^n + b_k (U(k-1) + dt L(U(k-1))), (a,b) = (0,1), (3/4,1/4),
-   (1/3,2/3), then sets the faces of bounded directions (OCFD_BC_*).
-   Errors: BADARG (n < 0, dt not finite), STATE. */
+   (1/3,2/3), then sets the faces of bounded directions (OCFD_BC_*).  With
+   check_every > 0 the state is checked after every substep whose count is a
+   multiple of it; a failed check stops the advance there (the state is the
+   one that failed).  Errors: BADARG (n < 0, dt not finite), STATE,
+   NONFINITE, CFL. */
 int ocfd_advance(ocfd_solver* s, int32_t n_substeps, double dt);
+/* Substeps completed since ocfd_set_state (or the stage given to
+   ocfd_set_step_state); after OCFD_ERR_NONFINITE or OCFD_ERR_CFL, the substep
+   whose result failed the check.  -1 for a null solver. */
+int64_t ocfd_substeps_done(const ocfd_solver* s);
 
 /* dudt_dev [5][N] = L(U_dev) = dU/dt for the parts selected by the
    OCFD_PART_* mask, without touching the solver's state (zero on the faces of

@@ -34,7 +34,8 @@ class Params(ctypes.Structure):
         ("Tref", ctypes.c_double), ("suth", ctypes.c_double), ("Tw", ctypes.c_double),
         ("theta1", ctypes.c_double), ("theta2", ctypes.c_double), ("eps", ctypes.c_double),
         ("viscous", ctypes.c_int32), ("scheme", ctypes.c_int32), ("lowdiss", ctypes.c_int32),
-        ("three_way", ctypes.c_int32), ("characteristic", ctypes.c_int32), ("nthreads", ctypes.c_int32),
+        ("three_way", ctypes.c_int32), ("characteristic", ctypes.c_int32), ("flag_window", ctypes.c_int32),
+        ("nthreads", ctypes.c_int32),
     ]
 
 
@@ -108,6 +109,7 @@ def params_from_case(case, nthreads: int = 0) -> Params:
     P.lowdiss = 1 if case.lowdiss == "c8" else 0
     P.three_way = int(bool(case.three_way))
     P.characteristic = int(bool(getattr(case, "characteristic", False)))
+    P.flag_window = int(getattr(case, "flag_window", 0))
     P.nthreads = int(nthreads)
     return P
 

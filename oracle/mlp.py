@@ -17,7 +17,8 @@ WENO stencil.  This module holds, in plain numpy:
 * the same forward/backward with values rounded to bfloat16 at the points
   where the GPU kernels feed its matrix cores (inputs, weights of the two
   hidden layers, hidden activations, back-propagated pre-activation
-  gradients), so the two can be compared on identical operands.
+  gradients), so the two can be compared on identical operands;
+* the Adam update of the training loop.
 
 Parameters are one flat float array: W1 [32 in x 32 out] (row = input),
 b1 [32], W2 [32 x 32], b2 [32], w3 [32], b3 [1].
@@ -100,6 +101,20 @@ def loss_and_grad(theta, X, y, w, round_bf16: bool = False):
     g["W1"] = x.T @ r(da1)
     g["b1"] = da1.sum(axis=0)
     return L, pack(g)
+
+
+def adam_step(theta, m, v, g, t: int, lr: float, b1: float = 0.9, b2: float = 0.999, eps: float = 1e-8):
+    """One Adam update (Kingma and Ba, "Adam: a method for stochastic
+    optimization", ICLR 2015, Algorithm 1) of the flat parameters theta with
+    gradient g at step t >= 1: biased moments m, v, their bias corrections
+    m / (1 - b1^t), v / (1 - b2^t), and the step lr * mhat / (sqrt(vhat) + eps).
+    Returns new (theta, m, v)."""
+    g = np.asarray(g, dtype=np.float64)
+    m = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    return np.asarray(theta, dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + eps), m, v
 
 
 # ------------------------------------------------------------------ features

@@ -468,10 +468,14 @@ static double node_theta(const or_params* P, const double* U, const int c[3]) {
   return th;
 }
 
-/* Flag of the interface j+1/2 along d from the sensor of its 8 stencil nodes. */
+/* Flag of the interface j+1/2 along d (eq 43) from the largest sensor value
+   of its window: the 8 stencil nodes j-3 .. j+4, or with flag_window = 1 the
+   two nodes j and j+1 (the paper applies theta "at positions" without naming
+   them; both readings give every interface one flag, as conservation needs). */
 static int interface_flag(const or_params* P, const double* theta, const int c[3], int d) {
   double mx = 0.0;
-  for (int m = -3; m <= 4; ++m) {
+  const int lo = P->flag_window == 1 ? 0 : -3, hi = P->flag_window == 1 ? 1 : 4;
+  for (int m = lo; m <= hi; ++m) {
     long id;
     if (!shifted(P, c, d, m, &id, NULL)) continue;
     if (theta[id] > mx) mx = theta[id];

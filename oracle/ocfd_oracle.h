@@ -45,6 +45,7 @@ typedef struct {
   int32_t lowdiss;       /* OR_UD7 or OR_C8 */
   int32_t three_way;     /* hybrid with the WENO5 tier above theta2 */
   int32_t characteristic; /* reconstruct in characteristic variables (Sec. 2.2.2) */
+  int32_t flag_window;   /* sensor window of interface j+1/2: 0 nodes j-3..j+4; 1 nodes j, j+1 */
   int32_t nthreads;      /* OpenMP threads (0: runtime default) */
 } or_params;
 

@@ -29,7 +29,8 @@ OCFD_PART_XI, OCFD_PART_ETA, OCFD_PART_ZETA, OCFD_PART_VISC, OCFD_PART_ALL = 1, 
 OCFD_RED_WENO0 = 9
 OCFD_RED_COUNT = 12
 OCFD_K_COUNT = 6
-ERRORS = {-1: "BADARG", -2: "BADSIZE", -3: "HIP", -4: "UNSUPPORTED", -5: "STATE"}
+ERRORS = {-1: "BADARG", -2: "BADSIZE", -3: "HIP", -4: "UNSUPPORTED", -5: "STATE", -6: "NONFINITE", -7: "CFL"}
+OCFD_ERR_NONFINITE, OCFD_ERR_CFL = -6, -7
 
 
 class ocfd_params(ctypes.Structure):
@@ -47,12 +48,18 @@ class ocfd_params(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("sensor", ctypes.c_int32), ("sensor_every", ctypes.c_int32), ("audit_every", ctypes.c_int32),
         ("three_way", ctypes.c_int32),
-        ("characteristic", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("characteristic", ctypes.c_int32), ("check_every", ctypes.c_int32),
+        ("flag_window", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("cfl_max", ctypes.c_double),
     ]
 
 
 class OcfdError(RuntimeError):
-    pass
+    """A failed entry point; .code is its OCFD_ERR_* value."""
+
+    def __init__(self, msg: str, code: int = 0):
+        super().__init__(msg)
+        self.code = code
 
 
 _lib = None
@@ -80,6 +87,8 @@ def lib() -> ctypes.CDLL:
         L.ocfd_get_step_state.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_int32)]
         L.ocfd_set_step_state.argtypes = [vp, vp, vp, ctypes.c_int32]
         L.ocfd_advance.argtypes = [vp, ctypes.c_int32, ctypes.c_double]
+        L.ocfd_substeps_done.argtypes = [vp]
+        L.ocfd_substeps_done.restype = ctypes.c_int64
         L.ocfd_dudt.argtypes = [vp, vp, vp, ctypes.c_int32]
         L.ocfd_reduce.argtypes = [vp, ctypes.c_double, dp]
         L.ocfd_profile.argtypes = [vp, ctypes.c_int32]
@@ -122,7 +131,7 @@ def _ptr(t: Optional[torch.Tensor]):
 def _check(handle, rc: int, what: str):
     if rc != OCFD_OK:
         msg = lib().ocfd_last_error(handle).decode() if handle else ""
-        raise OcfdError(f"{what}: {ERRORS.get(rc, rc)} {msg}")
+        raise OcfdError(f"{what}: {ERRORS.get(rc, rc)} {msg}", rc)
 
 
 # ----------------------------------------------------------------- C entry points
@@ -184,6 +193,10 @@ def ocfd_set_step_state(h, U: torch.Tensor, Un: torch.Tensor, stage: int):
 
 def ocfd_advance(h, n: int, dt: float):
     _check(h, lib().ocfd_advance(h, n, dt), "ocfd_advance")
+
+
+def ocfd_substeps_done(h) -> int:
+    return int(lib().ocfd_substeps_done(h))
 
 
 def ocfd_dudt(h, U: torch.Tensor, out: torch.Tensor, parts: int = OCFD_PART_ALL):
@@ -318,6 +331,7 @@ def params_from(case, **overrides) -> ocfd_params:
     p.audit_every = int(getattr(case, "audit_every", 0))
     p.three_way = int(bool(getattr(case, "three_way", False)))
     p.characteristic = int(bool(getattr(case, "characteristic", False)))
+    p.flag_window = int(getattr(case, "flag_window", 0))
     for k, v in overrides.items():
         setattr(p, k, v)
     return p

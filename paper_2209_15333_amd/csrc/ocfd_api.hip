@@ -92,8 +92,11 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 constexpr int GRAD_BLOCKS = 64;     // workgroups of one training step
 constexpr int COUNT_BLOCKS = 1024;  // workgroups of the collection / flag-count passes
 
-bool valid_params(const ocfd_params* p, std::string* why) {
+// Parameter check; *code receives the error code of a rejected set
+// (BADARG, or UNSUPPORTED for a combination that is not built).
+bool valid_params(const ocfd_params* p, std::string* why, int* code = nullptr) {
   char buf[256];
+  if (code) *code = OCFD_ERR_BADARG;
   if (!p) { *why = "null params"; return false; }
   if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->nx > 65535 || p->ny > 65535 || p->nz > 65535) {
     snprintf(buf, sizeof(buf), "grid %d x %d x %d outside [1, 65535]", p->nx, p->ny, p->nz);
@@ -119,7 +122,17 @@ bool valid_params(const ocfd_params* p, std::string* why) {
   if (p->three_way != 0 && p->three_way != 1) { *why = "three_way must be 0 or 1"; return false; }
   if (p->three_way && !(p->theta2 >= p->theta1)) { *why = "three_way needs theta2 >= theta1"; return false; }
   if (p->characteristic != 0 && p->characteristic != 1) { *why = "characteristic must be 0 or 1"; return false; }
+  if (p->check_every < 0) { *why = "check_every must be >= 0"; return false; }
+  if (p->flag_window != 0 && p->flag_window != 1) { *why = "flag_window must be 0 or 1"; return false; }
+  if (!(p->cfl_max >= 0.0 && std::isfinite(p->cfl_max))) { *why = "cfl_max must be finite and >= 0"; return false; }
   if (p->reserved0 != 0) { *why = "reserved0 must be 0"; return false; }
+  if (p->scheme == OCFD_SCHEME_HYBRID && p->sensor == OCFD_SENSOR_LEARNED && p->three_way) {
+    // the network decides low-dissipation / WENO7 only; its audit fallback
+    // could not tell the plain sensor's WENO5 tier apart
+    *why = "the learned sensor decides two ways: three_way needs the plain sensor";
+    if (code) *code = OCFD_ERR_UNSUPPORTED;
+    return false;
+  }
   int ninflow = 0;
   const int n[3] = {p->nx, p->ny, p->nz};
   for (int d = 0; d < 3; ++d) {
@@ -195,6 +208,7 @@ void setup_geo_phys(ocfd_solver* s) {
   ph.theta1 = p.theta1;
   ph.theta2 = p.theta2;
   ph.three_way = p.three_way;
+  ph.flag_window = p.flag_window;
   ph.vh = p.viscous == 8 ? 4 : 3;
   for (int d = 0; d < 3; ++d) {
     ph.h[d] = p.h[d];
@@ -438,6 +452,26 @@ int apply_bc(ocfd_solver* s, double* U) {
   return OCFD_OK;
 }
 
+// The state check of ocfd_advance: the reduction of the current state, then
+// non-finite values or a non-positive density or pressure (NONFINITE) and the
+// CFL number against cfl_max (CFL).  Synchronises.
+int check_state(ocfd_solver* s, double dt) {
+  hipError_t e = launch_reduce(s->g, s->ph, s->Ub[s->stage], s->met, dt, nullptr, s->partial, reduce_blocks(s->g),
+                               s->red, s->st);
+  double r[OCFD_RED_COUNT];
+  if (e == hipSuccess) e = hipMemcpyAsync(r, s->red, sizeof(r), hipMemcpyDeviceToHost, s->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+  if (e != hipSuccess) return hip_fail(s, e, "state check");
+  if (r[OCFD_RED_NONFINITE] > 0.0 || !(r[OCFD_RED_RHOMIN] > 0.0) || !(r[OCFD_RED_PMIN] > 0.0))
+    return fail(s, OCFD_ERR_NONFINITE,
+                "state after substep %lld: %.0f non-finite conserved values, min density %g, min pressure %g",
+                s->substep, r[OCFD_RED_NONFINITE], r[OCFD_RED_RHOMIN], r[OCFD_RED_PMIN]);
+  if (s->p.cfl_max > 0.0 && !(r[OCFD_RED_CFL] <= s->p.cfl_max))
+    return fail(s, OCFD_ERR_CFL, "state after substep %lld: CFL number %g above the limit %g", s->substep,
+                r[OCFD_RED_CFL], s->p.cfl_max);
+  return OCFD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -483,9 +517,10 @@ int ocfd_create(const ocfd_params* p, void* stream, ocfd_solver** out) {
   if (!out) return OCFD_ERR_BADARG;
   *out = nullptr;
   std::string why;
-  if (!valid_params(p, &why)) {
+  int code = OCFD_ERR_BADARG;
+  if (!valid_params(p, &why, &code)) {
     fprintf(stderr, "ocfd_create: %s\n", why.c_str());
-    return OCFD_ERR_BADARG;
+    return code;
   }
   ocfd_solver* s = new (std::nothrow) ocfd_solver();
   if (!s) return OCFD_ERR_BADARG;
@@ -563,6 +598,7 @@ int ocfd_set_state(ocfd_solver* s, const double* U) {
   hipError_t e = hipMemcpyAsync(s->Ub[0], U, 5 * s->g.N * sizeof(double), hipMemcpyDeviceToDevice, s->st);
   if (e != hipSuccess) return hip_fail(s, e, "state copy");
   s->stage = 0;
+  s->substep = 0;
   s->have_state = true;
   return OCFD_OK;
 }
@@ -596,6 +632,7 @@ int ocfd_set_step_state(ocfd_solver* s, const double* U, const double* Un, int32
   if (e == hipSuccess && stage > 0) e = hipMemcpyAsync(s->Ub[stage], U, b, hipMemcpyDeviceToDevice, s->st);
   if (e != hipSuccess) return hip_fail(s, e, "state copy");
   s->stage = stage;
+  s->substep = stage;
   s->have_state = true;
   return OCFD_OK;
 }
@@ -620,9 +657,15 @@ int ocfd_advance(ocfd_solver* s, int32_t n, double dt) {
     }
     s->stage = (k + 1) % 3;
     s->substep += 1;
+    if (s->p.check_every > 0 && s->substep % s->p.check_every == 0) {
+      rc = check_state(s, dt);
+      if (rc) return rc;
+    }
   }
   return OCFD_OK;
 }
+
+int64_t ocfd_substeps_done(const ocfd_solver* s) { return s ? (int64_t)s->substep : -1; }
 
 int ocfd_dudt(ocfd_solver* s, const double* U, double* out, int32_t parts) {
   int rc;

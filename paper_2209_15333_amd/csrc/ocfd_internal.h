@@ -102,6 +102,7 @@ struct Phys {
   double eps;               // WENO epsilon
   double theta1, theta2;    // sensor thresholds (eq 43)
   int three_way;            // plain sensor marks max theta > theta2 with flag 2 (WENO5)
+  int flag_window;          // plain sensor window of interface j+1/2: 0 nodes j-3 .. j+4; 1 nodes j, j+1
   int vh;                   // half width of the interior viscous central stencil (3: sixth, 4: eighth order)
   double h[3], ih[3];       // computational spacing and its inverse
   double period[3];
@@ -160,8 +161,9 @@ hipError_t launch_reduce(const Geo& g, const Phys& ph, const double* U, const do
 int reduce_blocks(const Geo& g);
 
 // Sensors (ocfd_sensor.hip).
-// Interface flags from theta: 0 low-dissipation (max theta over the 8-node
-// window <= theta1), 1 WENO7, 2 WENO5 (three_way and max theta > theta2).
+// Interface flags from theta: 0 low-dissipation (max theta over the window
+// <= theta1; the window is nodes j-3 .. j+4, or j and j+1 when flag_window is
+// 1), 1 WENO7, 2 WENO5 (three_way and max theta > theta2).
 hipError_t launch_plain_flags(const Geo& g, const Phys& ph, const double* theta, uint8_t* flags, hipStream_t st);
 hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, uint16_t* feat,
                            hipStream_t st);

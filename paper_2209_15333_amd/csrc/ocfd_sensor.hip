@@ -43,16 +43,21 @@ __device__ __forceinline__ v4f mfma16(const v4bf& a, const v4bf& b, const v4f& c
 
 // ---------------------------------------------------------------------------
 // Plain sensor flags: interface j+1/2 along d is low-dissipation iff the node
-// sensor theta is <= theta1 at every node j-3 .. j+4; otherwise WENO7, or
-// WENO5 in the three-way hybrid when the window maximum exceeds theta2.
+// sensor theta is <= theta1 at every node of its window; otherwise WENO7, or
+// WENO5 in the three-way hybrid when the window maximum exceeds theta2.  The
+// window (the paper applies theta "at positions" without saying which) is
+// the interface's stencil, nodes j-3 .. j+4 (W0 = -3, W1 = 4), or its two
+// nodes j, j+1 (W0 = 0, W1 = 1).
 // ---------------------------------------------------------------------------
 // Each thread marches one (xi, eta) column through a zeta segment keeping
-// theta of planes k-3 .. k+4 in registers; the xi and eta windows are read
+// theta of planes k+W0 .. k+W1 in registers; the xi and eta windows are read
 // from the plane (cached).  Positions outside a bounded line count as 0
 // (theta >= 0, so the maximum is the one over the nodes that exist).
+template <int W0, int W1>
 __global__ __launch_bounds__(256) void k_plain_flags(const Geo g, const ZMarch zm, double theta1, double theta2,
                                                      int three_way, const double* __restrict__ theta,
                                                      uint8_t* __restrict__ flags) {
+  constexpr int WN = W1 - W0 + 1;
   int i, j, k0, k1;
   if (!zmarch_column(zm, g.n, &i, &j, &k0, &k1)) return;
   const int nz = g.n[2];
@@ -67,7 +72,7 @@ __global__ __launch_bounds__(256) void k_plain_flags(const Geo g, const ZMarch z
     const int n = g.n[d];
     double mx = 0.0;
 #pragma unroll
-    for (int o = -3; o <= 4; ++o) {
+    for (int o = W0; o <= W1; ++o) {
       int q = p + o;
       if (g.periodic[d]) {
         q = n >= 8 ? q + (q < 0 ? n : 0) - (q >= n ? n : 0) : wrapn(q, n);
@@ -78,28 +83,32 @@ __global__ __launch_bounds__(256) void k_plain_flags(const Geo g, const ZMarch z
     }
     return mx;
   };
-  double w[8];
+  double w[WN];
 #pragma unroll
-  for (int o = 0; o < 7; ++o) w[o] = zval(k0 - 3 + o);
+  for (int o = 0; o < WN - 1; ++o) w[o] = zval(k0 + W0 + o);
   for (int k = k0; k < k1; ++k) {
-    w[7] = zval(k + 4);
+    w[WN - 1] = zval(k + W1);
     const long long id = col + (long long)k * g.s[2];
     double mz = 0.0;
 #pragma unroll
-    for (int o = 0; o < 8; ++o) mz = fmax(mz, w[o]);
+    for (int o = 0; o < WN; ++o) mz = fmax(mz, w[o]);
     auto flag = [&](double mx) -> uint8_t { return mx <= theta1 ? 0 : ((three_way && mx > theta2) ? 2 : 1); };
     flags[id] = flag(inplane(id, 0, i));
     flags[g.N + id] = flag(inplane(id, 1, j));
     flags[2 * g.N + id] = flag(mz);
 #pragma unroll
-    for (int o = 0; o < 7; ++o) w[o] = w[o + 1];
+    for (int o = 0; o < WN - 1; ++o) w[o] = w[o + 1];
   }
 }
 
 hipError_t launch_plain_flags(const Geo& g, const Phys& ph, const double* theta, uint8_t* flags, hipStream_t st) {
   const ZMarch zm = make_zmarch(g.n);
-  hipLaunchKernelGGL(k_plain_flags, dim3(zm.blocks), dim3(256), 0, st, g, zm, ph.theta1, ph.theta2, ph.three_way,
-                     theta, flags);
+  if (ph.flag_window == 1)
+    hipLaunchKernelGGL((k_plain_flags<0, 1>), dim3(zm.blocks), dim3(256), 0, st, g, zm, ph.theta1, ph.theta2,
+                       ph.three_way, theta, flags);
+  else
+    hipLaunchKernelGGL((k_plain_flags<-3, 4>), dim3(zm.blocks), dim3(256), 0, st, g, zm, ph.theta1, ph.theta2,
+                       ph.three_way, theta, flags);
   return hipGetLastError();
 }
 

@@ -35,9 +35,11 @@ def test_header_and_binding_agree(ocfd):
 
 
 def test_params_struct_layout(ocfd):
-    # 3 + 3 + 6 int32, 3 + 3 + 10 double, 10 int32
-    assert ctypes.sizeof(ocfd.ocfd_params) == 216
+    # 3 + 3 + 6 int32, 3 + 3 + 10 double, 12 int32, 1 double
+    assert ctypes.sizeof(ocfd.ocfd_params) == 232
     assert ocfd.ocfd_params.characteristic.offset == 208
+    assert ocfd.ocfd_params.check_every.offset == 212 and ocfd.ocfd_params.flag_window.offset == 216
+    assert ocfd.ocfd_params.cfl_max.offset == 224
     assert ocfd.ocfd_params.bc.offset == 24 and ocfd.ocfd_params.period.offset == 48
     assert ocfd.ocfd_params.Tw.offset == 48 + 8 * 12 and ocfd.ocfd_params.viscous.offset == 48 + 8 * 16
 
@@ -57,7 +59,8 @@ def test_rejects_bad_parameters(ocfd):
     L = ocfd.lib()
     h = ctypes.c_void_p()
     for bad in (dict(nx=0), dict(gamma=1.0), dict(viscous=4), dict(scheme=7), dict(weno_eps=0.0), dict(Ma=-1.0),
-                dict(characteristic=2), dict(reserved0=1)):
+                dict(characteristic=2), dict(reserved0=1), dict(check_every=-1), dict(flag_window=2),
+                dict(cfl_max=-1.0), dict(cfl_max=float("inf"))):
         p = _params(ocfd, **bad)
         assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -1, bad
         assert L.ocfd_workspace_bytes(ctypes.byref(p)) == 0
@@ -84,6 +87,24 @@ def test_rejects_bad_parameters(ocfd):
     p.sensor = 1
     assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == 0
     L.ocfd_destroy(h)
+    # the network decides two ways: the three-way hybrid needs the plain sensor
+    p.scheme, p.three_way = 1, 1
+    assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -4
+    p.sensor = 0
+    assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == 0
+    L.ocfd_destroy(h)
+
+
+def test_substep_count_without_device_work(ocfd):
+    L = ocfd.lib()
+    assert L.ocfd_substeps_done(None) == -1
+    p = _params(ocfd, check_every=10, cfl_max=0.9, flag_window=1)
+    h = ctypes.c_void_p()
+    assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == 0
+    try:
+        assert L.ocfd_substeps_done(h) == 0
+    finally:
+        L.ocfd_destroy(h)
 
 
 def test_workspace_and_order_errors(ocfd):

@@ -55,6 +55,7 @@ class Case:
     lowdiss: str = "c8"                  # "ud7" | "c8"
     three_way: bool = False
     characteristic: bool = False         # reconstruct in characteristic variables (Sec. 2.2.2)
+    flag_window: int = 0                 # plain sensor window: 0 nodes j-3..j+4, 1 nodes j, j+1
     inflow: Optional[np.ndarray] = None
     precision: str = "fp64"              # "fp64" | "mixed" (GPU only)
     sensor: str = "plain"                # hybrid: "plain" (pressure sensor) | "learned" (GPU only)
@@ -406,3 +407,19 @@ def sensor_initial_weights(seed: int = 0) -> np.ndarray:
     W2 = rng.uniform(-1, 1, (32, 32)) * math.sqrt(6.0 / 32)
     w3 = rng.uniform(-1, 1, 32) * math.sqrt(6.0 / 32) * 0.1
     return np.concatenate([W1.ravel(), np.zeros(32), W2.ravel(), np.zeros(32), w3, np.zeros(1)])
+
+
+def projection_weights(n_nodes: int, count: int = 4, seed: int = 22096):
+    """`count` seeded standard-normal vectors over the nodes (PCG64(seed),
+    drawn in order), for comparing two whole fields through a few random
+    projections: for a difference d the projection r.d has the spread of the
+    L2 norm |d|, so the projections of two fields agree only if the fields
+    do."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return [rng.standard_normal(n_nodes) for _ in range(count)]
+
+
+def sample_nodes(n_nodes: int, count: int = 1024, seed: int = 22097) -> np.ndarray:
+    """`count` distinct node indices in increasing order (PCG64(seed))."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return np.sort(rng.choice(n_nodes, size=count, replace=False)).astype(np.int64)
