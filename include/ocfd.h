@@ -231,6 +231,26 @@ int ocfd_dudt(ocfd_solver* s, const double* U_dev, double* dudt_dev, int32_t par
    stream. */
 int ocfd_reduce(ocfd_solver* s, double dt, double* out_host);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the
+   reduction of ocfd_reduce without a solver, a workspace or a host copy.
+   Inputs: the grid and gas parameters *p (sizes, periodic, h, gamma are
+   read), the state U_dev [5][N] and the metrics met_dev [10][N] (layout of
+   ocfd_set_metrics).  Output: out_dev, a device buffer of OCFD_RED_COUNT
+   doubles; entries OCFD_RED_SUM0 .. OCFD_RED_NONFINITE as ocfd_reduce, the
+   WENO entries 0 (no flags are seen).  Enqueued on `stream` (a hipStream_t,
+   NULL: the default stream) on the current device, without synchronising.
+   Allocates nothing: its partial records live in a fixed array of
+   1024 x OCFD_RED_COUNT doubles (96 KiB) of device memory, one per GPU,
+   held until the process ends; every grid this library accepts needs at
+   most 1024 records (more would return BADSIZE).  Calls that overlap on one
+   GPU (two streams, two threads) share that array and race: serialise them.
+   Errors: BADARG (null pointer, dt not finite, invalid sizes, h or gamma),
+   BADSIZE, HIP (the array's address or the launch); the reason is printed
+   to stderr. */
+int ocfd_reduce_static(const ocfd_params* p, const double* U_dev, const double* met_dev, double dt,
+                       double* out_dev, void* stream);
+
 /* Per-interface scheme flags flags_dev [3][N] (byte: 0 low-dissipation,
    1 WENO7, 2 WENO5) used by the hybrid scheme instead of the sensor, or NULL
    to go back to the sensor.  The caller keeps the buffer alive while set.

@@ -91,6 +91,7 @@ def lib() -> ctypes.CDLL:
         L.ocfd_substeps_done.restype = ctypes.c_int64
         L.ocfd_dudt.argtypes = [vp, vp, vp, ctypes.c_int32]
         L.ocfd_reduce.argtypes = [vp, ctypes.c_double, dp]
+        L.ocfd_reduce_static.argtypes = [pp, vp, vp, ctypes.c_double, vp, vp]
         L.ocfd_profile.argtypes = [vp, ctypes.c_int32]
         L.ocfd_profile_read.argtypes = [vp, dp, ctypes.POINTER(ctypes.c_int64)]
         L.ocfd_kernel_name.argtypes = [ctypes.c_int32]
@@ -207,6 +208,17 @@ def ocfd_reduce(h, dt: float = 0.0):
     out = (ctypes.c_double * OCFD_RED_COUNT)()
     _check(h, lib().ocfd_reduce(h, dt, out), "ocfd_reduce")
     return list(out)
+
+
+def ocfd_reduce_static(p: ocfd_params, U: torch.Tensor, met: torch.Tensor, dt: float, out: torch.Tensor,
+                       stream: Optional[torch.cuda.Stream] = None):
+    """Enqueue the reduction of U into the device tensor out (OCFD_RED_COUNT
+    float64); no allocation, no synchronisation."""
+    if out.dtype != torch.float64 or out.numel() < OCFD_RED_COUNT:
+        raise OcfdError(f"out must hold {OCFD_RED_COUNT} float64 values")
+    st = (stream or torch.cuda.current_stream()).cuda_stream
+    _check(None, lib().ocfd_reduce_static(ctypes.byref(p), _ptr(U), _ptr(met), dt, _ptr(out), ctypes.c_void_p(st)),
+           "ocfd_reduce_static")
 
 
 def ocfd_set_flags(h, flags: Optional[torch.Tensor]):

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <random>
 #include <string>
@@ -183,19 +184,19 @@ long long decided_interfaces(const Geo& g) {
   return t;
 }
 
-void setup_geo_phys(ocfd_solver* s) {
-  const ocfd_params& p = s->p;
-  s->g.n[0] = p.nx;
-  s->g.n[1] = p.ny;
-  s->g.n[2] = p.nz;
-  s->g.s[0] = 1;
-  s->g.s[1] = p.nx;
-  s->g.s[2] = (long long)p.nx * p.ny;
-  s->g.N = (long long)p.nx * p.ny * p.nz;
-  for (int d = 0; d < 3; ++d) s->g.periodic[d] = p.periodic[d];
-  s->g.div[0] = make_fastdiv((uint32_t)p.nx);
-  s->g.div[1] = make_fastdiv((uint32_t)p.ny);
-  Phys& ph = s->ph;
+void geo_phys_of(const ocfd_params& p, Geo* geo, Phys* phys) {
+  Geo& g = *geo;
+  g.n[0] = p.nx;
+  g.n[1] = p.ny;
+  g.n[2] = p.nz;
+  g.s[0] = 1;
+  g.s[1] = p.nx;
+  g.s[2] = (long long)p.nx * p.ny;
+  g.N = (long long)p.nx * p.ny * p.nz;
+  for (int d = 0; d < 3; ++d) g.periodic[d] = p.periodic[d];
+  g.div[0] = make_fastdiv((uint32_t)p.nx);
+  g.div[1] = make_fastdiv((uint32_t)p.ny);
+  Phys& ph = *phys;
   ph.gamma = p.gamma;
   ph.gm1 = p.gamma - 1.0;
   ph.inv_gm1 = 1.0 / (p.gamma - 1.0);
@@ -216,6 +217,8 @@ void setup_geo_phys(ocfd_solver* s) {
     ph.period[d] = p.period[d];
   }
 }
+
+void setup_geo_phys(ocfd_solver* s) { geo_phys_of(s->p, &s->g, &s->ph); }
 
 size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver* s, char* base) {
   size_t off = 0;
@@ -474,6 +477,53 @@ int check_state(ocfd_solver* s, double dt) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Reduction without allocation (ocfd_reduce_static): the partial records live
+// in a fixed array in device memory, one copy per GPU, held until the process
+// ends.  Host code never passes the array's name to a kernel (in host code it
+// is only a stand-in for the symbol): the device address of each GPU's copy is
+// looked up once per device, with that device current, and kept here.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[RED_MAX_BLOCKS * OCFD_RED_COUNT];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_dev[MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch` (null on error).
+double* scratch_of_current_device(hipError_t* err) {
+  int dev = -1;
+  *err = hipGetDevice(&dev);
+  if (*err != hipSuccess) return nullptr;
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* ptr = nullptr;
+    *err = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (*err != hipSuccess) return nullptr;
+    scratch_dev[dev] = (double*)ptr;
+  }
+  return scratch_dev[dev];
+}
+
+// The parameters the reduction reads, checked without allocating.
+bool reduce_params_ok(const ocfd_params* p) {
+  if (p->nx < 1 || p->ny < 1 || p->nz < 1 || p->nx > 65535 || p->ny > 65535 || p->nz > 65535) return false;
+  if ((long long)p->nx * p->ny * p->nz >= (1ll << 31)) return false;
+  for (int d = 0; d < 3; ++d) {
+    if (!(p->h[d] > 0.0) || !std::isfinite(p->h[d])) return false;
+    if (p->periodic[d] != 0 && p->periodic[d] != 1) return false;
+  }
+  return p->gamma > 1.0 && std::isfinite(p->gamma);
+}
+
+}  // namespace
+
 extern "C" {
 
 int ocfd_params_default(ocfd_params* p) {
@@ -701,6 +751,38 @@ int ocfd_reduce(ocfd_solver* s, double dt, double* out) {
       f = NAN;
     else
       f = total > 0.0 ? f / total : 0.0;
+  }
+  return OCFD_OK;
+}
+
+int ocfd_reduce_static(const ocfd_params* p, const double* U, const double* met, double dt, double* out,
+                       void* stream) {
+  if (!p || !U || !met || !out || !std::isfinite(dt)) return OCFD_ERR_BADARG;
+  if (!reduce_params_ok(p)) {
+    fprintf(stderr, "ocfd_reduce_static: invalid grid or gas parameters\n");
+    return OCFD_ERR_BADARG;
+  }
+  Geo g;
+  Phys ph;
+  geo_phys_of(*p, &g, &ph);
+  const int nb = reduce_blocks(g);
+  if (nb > RED_MAX_BLOCKS) {
+    fprintf(stderr, "ocfd_reduce_static: %d partial records needed, the fixed array holds %d\n", nb,
+            RED_MAX_BLOCKS);
+    return OCFD_ERR_BADSIZE;
+  }
+  hipError_t e;
+  double* part = scratch_of_current_device(&e);
+  if (!part) {
+    fprintf(stderr, "ocfd_reduce_static: device address of the partial array: %s\n", hipGetErrorString(e));
+    return OCFD_ERR_HIP;
+  }
+  // every partial record the final pass reads is written by the first pass
+  // of this call, so nothing left by an earlier call is read
+  e = launch_reduce(g, ph, U, met, dt, nullptr, part, nb, out, (hipStream_t)stream);
+  if (e != hipSuccess) {
+    fprintf(stderr, "ocfd_reduce_static: launch: %s\n", hipGetErrorString(e));
+    return OCFD_ERR_HIP;
   }
   return OCFD_OK;
 }

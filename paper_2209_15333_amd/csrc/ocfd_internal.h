@@ -156,6 +156,9 @@ hipError_t launch_pressure(const Geo& g, const Phys& ph, const double* U, double
 hipError_t launch_metric_inner(const Geo& g, const Phys& ph, const double* xyz, double* inner, hipStream_t st);
 hipError_t launch_metric_outer(const Geo& g, const Phys& ph, const double* xyz, const double* inner, double* met,
                                hipStream_t st);
+// Most workgroups of the reduction (reduce_blocks never exceeds it): the
+// partial buffer holds RED_MAX_BLOCKS records of OCFD_RED_COUNT doubles.
+constexpr int RED_MAX_BLOCKS = 1024;
 hipError_t launch_reduce(const Geo& g, const Phys& ph, const double* U, const double* met, double dt,
                          const uint8_t* flags, double* partial, int nblocks, double* out, hipStream_t st);
 int reduce_blocks(const Geo& g);

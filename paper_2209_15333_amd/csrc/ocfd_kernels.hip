@@ -628,13 +628,12 @@ hipError_t launch_metric_outer(const Geo& g, const Phys& ph, const double* xyz, 
 // ---------------------------------------------------------------------------
 
 constexpr int RED_T = 256;
-constexpr int RED_MAXB = 1024;
 constexpr int NRED = OCFD_RED_COUNT;
 
 int reduce_blocks(const Geo& g) {
   long long b = (g.N + RED_T * 16 - 1) / (RED_T * 16);
   if (b < 1) b = 1;
-  if (b > RED_MAXB) b = RED_MAXB;
+  if (b > RED_MAX_BLOCKS) b = RED_MAX_BLOCKS;
   return (int)b;
 }
 
