@@ -66,15 +66,27 @@ extern "C" {
 /* Boundary kinds of the faces of a non-periodic direction (Sec. 2.4 names
    the kinds used by the compression-ramp case).  Applied after every
    Runge-Kutta stage, face by face in the order xi-, xi+, eta-, eta+, zeta-,
-   zeta+; a face node's dU/dt is zero, its value is set by its face:
+   zeta+; a face node's dU/dt is zero (except on NRBC faces), its value is
+   set by its face:
    INFLOW: the conserved state given by ocfd_set_inflow;
    EXTRAP: rho, velocity and p of the first interior node;
    WALL:   no slip, T = Tw, p of the first interior node, rho = gamma Ma^2 p / Tw;
-   NONE:   the face keeps its value. */
+   NONE:   the face keeps its value;
+   NRBC:   characteristic nonreflecting face (Sec. 6.1 names nonreflecting
+           conditions at the ramp's exit and upper boundary; the reading is
+           Thompson 1987 with the local one-dimensional relations of Poinsot &
+           Lele 1992): its nodes are advanced by the Runge-Kutta stage with
+           the fluxes of the directions they are interior to plus, along the
+           face normal, the time derivative carried by the outgoing
+           characteristic waves (one-sided second-order differences; incoming
+           wave amplitudes zero) and the metric-derivative part of the normal
+           flux derivative; no normal viscous term.  A node that also lies on
+           a face of another kind takes that face's value. */
 #define OCFD_BC_NONE 0
 #define OCFD_BC_INFLOW 1
 #define OCFD_BC_EXTRAP 2
 #define OCFD_BC_WALL 3
+#define OCFD_BC_NRBC 4
 
 /* Parts of the right-hand side for ocfd_dudt (bit mask). */
 #define OCFD_PART_XI 1

@@ -73,6 +73,8 @@ def lib():
                                  ctypes.c_double, dp]
         L.or_reduce.argtypes = [pp, dp, dp, ctypes.c_double, dp]
         L.or_apply_bc.argtypes = [pp, dp, dp]
+        L.or_nrbc_normal.argtypes = [pp, dp, dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                     ctypes.c_int32, dp]
         _lib = L
     return _lib
 
@@ -212,3 +214,13 @@ def apply_bc(P: Params, U: np.ndarray, inflow: Optional[np.ndarray] = None) -> n
     U = np.array(U, dtype=np.float64, order="C", copy=True)
     _check(lib().or_apply_bc(ctypes.byref(P), _dp(U), _dp(inflow)), "apply_bc")
     return U
+
+
+def nrbc_normal(P: Params, met: np.ndarray, U: np.ndarray, node, d: int, side: int) -> np.ndarray:
+    """Normal-direction part of dU/dt at node (i, j, k) of the nonreflecting
+    face (d, side)."""
+    out = np.zeros(5)
+    i, j, k = node
+    _check(lib().or_nrbc_normal(ctypes.byref(P), _dp(np.ascontiguousarray(met)), _dp(np.ascontiguousarray(U)),
+                                i, j, k, d, side, _dp(out)), "nrbc_normal")
+    return out

@@ -588,22 +588,131 @@ static void viscous_flux_at(const or_params* P, const double* met, const prim_t*
   }
 }
 
-/* Is node c on a face of a non-periodic direction? */
-static int on_boundary(const or_params* P, const int c[3]) {
-  for (int d = 0; d < 3; ++d)
-    if (!P->periodic[d] && (c[d] == 0 || c[d] == dim_n(P, d) - 1)) return 1;
+/* Is node c on a face whose kind sets its value after the stage (every kind
+   but the nonreflecting one)?  Such nodes have dU/dt = 0. */
+static int on_set_face(const or_params* P, const int c[3]) {
+  for (int d = 0; d < 3; ++d) {
+    if (P->periodic[d]) continue;
+    int n = dim_n(P, d);
+    if (c[d] == 0 && P->bc[2 * d] != OR_BC_NRBC) return 1;
+    if (c[d] == n - 1 && P->bc[2 * d + 1] != OR_BC_NRBC) return 1;
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Characteristic nonreflecting faces (Thompson 1987; Poinsot & Lele    */
+/* 1992).  The paper imposes nonreflecting conditions at the exit and  */
+/* the upper boundary of the ramp (Sec. 6.1) without formulas.          */
+/* ------------------------------------------------------------------ */
+
+/* Normal-direction part of dU/dt at a node of face (d, side).  Along the
+   grid line the Euler equations in primitive variables q = (rho, u, v, w, p)
+   read  dq/dt + s A_n dq/dxi = ...  with s = |grad xi_d| and A_n the Jacobian
+   along the unit normal n = grad xi_d / s (metric derivatives dropped).  Its
+   characteristic wave amplitudes, with dq/dxi the one-sided second-order
+   difference into the grid and u_n = u.n:
+     L1 = s (u_n - c) (dp - rho c du_n)        L5 = s (u_n + c) (dp + rho c du_n)
+     L2 = s u_n (c^2 drho - dp)                Lt = s u_n (du - n (n.du))
+   A wave entering the grid (speed < 0 on the upper face, > 0 on the lower)
+   has amplitude zero.  Then
+     drho/dt = -(L2 + (L5 + L1)/2) / c^2,   dp/dt = -(L5 + L1)/2,
+     du/dt = -(n (L5 - L1) / (2 rho c) + Lt),
+   carried to the conserved variables (eq 5, 8).  The part of the normal flux
+   derivative that the frozen normal leaves out, -J sum_a d(xi_a/J)/dxi F_a
+   (F_a the Cartesian inviscid flux of eq 6), is added as it stands (one-sided
+   second-order difference of the metrics): on a curved grid it balances the
+   metric derivatives of the transverse fluxes, so a uniform stream stays
+   uniform at the face. */
+static void nrbc_normal(const or_params* P, const double* met, const double* U, const int c[3], int d, int side,
+                        double out[5]) {
+  const long N = n_nodes(P);
+  const long id = lin(P, c);
+  const double h = P->h[d];
+  /* primitives of the node and of the next two nodes into the grid */
+  double q[3][5];
+  for (int t = 0; t < 3; ++t) {
+    int ct[3] = {c[0], c[1], c[2]};
+    ct[d] += side ? -t : t;
+    prim_t r = primitive(P, U, N, lin(P, ct));
+    q[t][0] = r.rho; q[t][1] = r.u; q[t][2] = r.v; q[t][3] = r.w; q[t][4] = r.p;
+  }
+  /* dq/dxi_d by the one-sided second-order difference */
+  double dq[5];
+  for (int m = 0; m < 5; ++m) {
+    double one = (-3.0 * q[0][m] + 4.0 * q[1][m] - q[2][m]) / (2.0 * h);
+    dq[m] = side ? -one : one;
+  }
+  const double Jinv = met[9 * N + id];
+  double gx[3];
+  for (int a = 0; a < 3; ++a) gx[a] = met[(long)(3 * d + a) * N + id] / Jinv;   /* grad xi_d */
+  const double sg = sqrt(gx[0] * gx[0] + gx[1] * gx[1] + gx[2] * gx[2]);
+  const double n[3] = {gx[0] / sg, gx[1] / sg, gx[2] / sg};
+  const double rho = q[0][0], u[3] = {q[0][1], q[0][2], q[0][3]}, p = q[0][4];
+  const double cs = sqrt(P->gamma * p / rho);
+  const double un = u[0] * n[0] + u[1] * n[1] + u[2] * n[2];
+  const double du[3] = {dq[1], dq[2], dq[3]};
+  const double dun = du[0] * n[0] + du[1] * n[1] + du[2] * n[2];
+  const double lam1 = sg * (un - cs), lam2 = sg * un, lam5 = sg * (un + cs);
+  /* a wave enters through the upper face when its speed is negative, through
+     the lower face when it is positive */
+  #define OUTGOING(l) (side ? (l) >= 0.0 : (l) <= 0.0)
+  const double L1 = OUTGOING(lam1) ? lam1 * (dq[4] - rho * cs * dun) : 0.0;
+  const double L5 = OUTGOING(lam5) ? lam5 * (dq[4] + rho * cs * dun) : 0.0;
+  const double L2 = OUTGOING(lam2) ? lam2 * (cs * cs * dq[0] - dq[4]) : 0.0;
+  double Lt[3];
+  for (int a = 0; a < 3; ++a) Lt[a] = OUTGOING(lam2) ? lam2 * (du[a] - n[a] * dun) : 0.0;
+  #undef OUTGOING
+  const double drho = -(L2 + 0.5 * (L5 + L1)) / (cs * cs);
+  const double dp = -0.5 * (L5 + L1);
+  double dvel[3];
+  for (int a = 0; a < 3; ++a) dvel[a] = -(n[a] * (L5 - L1) / (2.0 * rho * cs) + Lt[a]);
+  out[0] = drho;
+  for (int a = 0; a < 3; ++a) out[1 + a] = u[a] * drho + rho * dvel[a];
+  const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  out[4] = dp / (P->gamma - 1.0) + 0.5 * uu * drho + rho * (u[0] * dvel[0] + u[1] * dvel[1] + u[2] * dvel[2]);
+  /* metric-derivative part */
+  const double E = U[4 * N + id];
+  for (int a = 0; a < 3; ++a) {
+    double mt[3];
+    for (int t = 0; t < 3; ++t) {
+      int ct[3] = {c[0], c[1], c[2]};
+      ct[d] += side ? -t : t;
+      mt[t] = met[(long)(3 * d + a) * N + lin(P, ct)];
+    }
+    double dm = (-3.0 * mt[0] + 4.0 * mt[1] - mt[2]) / (2.0 * h);
+    if (side) dm = -dm;
+    const double Fa[5] = {rho * u[a], rho * u[0] * u[a] + (a == 0 ? p : 0.0), rho * u[1] * u[a] + (a == 1 ? p : 0.0),
+                          rho * u[2] * u[a] + (a == 2 ? p : 0.0), (E + p) * u[a]};
+    for (int m = 0; m < 5; ++m) out[m] -= dm * Fa[m] / Jinv;
+  }
+}
+
+int or_nrbc_normal(const or_params* P, const double* met, const double* U, int32_t i, int32_t j, int32_t k,
+                   int32_t d, int32_t side, double* out) {
+  int c[3] = {i, j, k};
+  if (d < 0 || d > 2 || P->periodic[d] || c[d] != (side ? dim_n(P, d) - 1 : 0)) return -1;
+  nrbc_normal(P, met, U, c, d, side, out);
   return 0;
 }
 
 /* dU/dt at node c from its interface fluxes and viscous fluxes:
    Fl[d] = flux at c-1/2, Fr[d] = flux at c+1/2 along d;
-   Fvn[d][m+4][s] = viscous flux component s of direction d at node c+m e_d. */
-static void assemble(const or_params* P, const double* met, const int c[3], int32_t parts,
+   Fvn[d][m+4][s] = viscous flux component s of direction d at node c+m e_d.
+   A node on a face whose kind sets it after the stage gets 0.  A node on
+   nonreflecting faces only takes the usual terms along the directions it is
+   interior to and, along each direction it is an end of, the characteristic
+   normal part of that face instead (no normal viscous term). */
+static void assemble(const or_params* P, const double* met, const double* U, const int c[3], int32_t parts,
                      const double Fl[3][5], const double Fr[3][5], const double Fvn[3][9][4], double out[5]) {
   const long N = n_nodes(P);
   double rhs[5] = {0, 0, 0, 0, 0};
-  if (on_boundary(P, c)) { for (int m = 0; m < 5; ++m) out[m] = 0.0; return; }
+  if (on_set_face(P, c)) { for (int m = 0; m < 5; ++m) out[m] = 0.0; return; }
+  int end[3] = {0, 0, 0};   /* end[d]: 1 lower end, 2 upper end of a bounded line */
+  for (int d = 0; d < 3; ++d)
+    if (!P->periodic[d]) end[d] = c[d] == 0 ? 1 : (c[d] == dim_n(P, d) - 1 ? 2 : 0);
   for (int d = 0; d < 3; ++d) {
+    if (end[d]) continue;
     if (parts & (1 << d))
       for (int m = 0; m < 5; ++m) rhs[m] -= (Fr[d][m] - Fl[d][m]) / P->h[d];
     if ((parts & OR_PART_VISC) && P->viscous)
@@ -615,6 +724,12 @@ static void assemble(const or_params* P, const double* met, const int c[3], int3
   }
   double Jinv = met[9 * N + lin(P, c)];
   for (int m = 0; m < 5; ++m) out[m] = rhs[m] / Jinv;   /* L(U) of eq 44 for U, not U/J */
+  for (int d = 0; d < 3; ++d) {
+    if (!end[d] || !(parts & (1 << d))) continue;
+    double nb[5];
+    nrbc_normal(P, met, U, c, d, end[d] == 2, nb);
+    for (int m = 0; m < 5; ++m) out[m] += nb[m];
+  }
 }
 
 static prim_t* all_primitives(const or_params* P, const double* U) {
@@ -710,7 +825,7 @@ int or_dudt(const or_params* P, const double* met, const double* U, const uint8_
       }
     }
     double o[5];
-    assemble(P, met, c, parts, Fl, Fr, Fvn, o);
+    assemble(P, met, U, c, parts, Fl, Fr, Fvn, o);
     for (int m = 0; m < 5; ++m) dudt[(long)m * N + id] = o[m];
   }
   free(q); free(F); free(fp); free(fm); free(Fv);
@@ -751,7 +866,7 @@ int or_dudt_points(const or_params* P, const double* met, const double* U, const
         for (int k = 0; k < 4; ++k) Fvn[d][t][k] = v[d][k];
       }
     }
-    assemble(P, met, c, parts, Fl, Fr, Fvn, out + 5 * s);
+    assemble(P, met, U, c, parts, Fl, Fr, Fvn, out + 5 * s);
   }
   free(q);
   if (owned) free(flags);
@@ -778,7 +893,7 @@ int or_apply_bc(const or_params* P, double* U, const double* inflow) {
     if (P->periodic[d]) continue;
     for (int side = 0; side < 2; ++side) {
       int kind = P->bc[2 * d + side];
-      if (kind == OR_BC_NONE) continue;
+      if (kind == OR_BC_NONE || kind == OR_BC_NRBC) continue;
       int n = dim_n(P, d);
       for (long id = 0; id < N; ++id) {
         int c[3]; unlin(P, id, c);

@@ -26,8 +26,13 @@ enum { OR_WENO7 = 0, OR_HYBRID = 1 };      /* inviscid scheme (Sec. 2.2.3) */
 enum { OR_UD7 = 0, OR_C8 = 1 };            /* low-dissipation stencil of the hybrid */
 /* Per-interface flag values (one byte per interface). */
 enum { OR_FLAG_LOW = 0, OR_FLAG_WENO7 = 1, OR_FLAG_WENO5 = 2 };
-/* Boundary kinds for the faces of non-periodic directions (ramp workloads). */
-enum { OR_BC_NONE = 0, OR_BC_INFLOW = 1, OR_BC_EXTRAP = 2, OR_BC_WALL = 3 };
+/* Boundary kinds for the faces of non-periodic directions (ramp workloads).
+   OR_BC_NRBC: characteristic nonreflecting face (Thompson 1987; the local
+   one-dimensional inviscid relations of Poinsot & Lele 1992): its nodes are
+   advanced in time like interior nodes, with the normal-direction terms
+   replaced by the outgoing characteristic wave amplitudes and the incoming
+   ones set to zero. */
+enum { OR_BC_NONE = 0, OR_BC_INFLOW = 1, OR_BC_EXTRAP = 2, OR_BC_WALL = 3, OR_BC_NRBC = 4 };
 
 typedef struct {
   int32_t nx, ny, nz;
@@ -95,10 +100,16 @@ int or_advance(const or_params* P, const double* met, double* U, double* Un, int
    out[7] = min rho; out[8] = count of non-finite values. */
 int or_reduce(const or_params* P, const double* met, const double* U, double dt, double* out);
 /* Apply the boundary conditions of the non-periodic faces to U in place, face
-   by face (xi-, xi+, eta-, eta+, zeta-, zeta+).  inflow: conserved variables
+   by face (xi-, xi+, eta-, eta+, zeta-, zeta+); NRBC faces are left as the
+   time step made them.  inflow: conserved variables
    [5][face] of the inflow face, the face indexed by its two other node
    indices with the lower direction fastest (NULL if there is none). */
 int or_apply_bc(const or_params* P, double* U, const double* inflow);
+/* Normal-direction part of dU/dt at node (i,j,k) on face (d, side) of a
+   nonreflecting face: out[5], the time derivative of the conserved variables
+   from the characteristic wave amplitudes (incoming ones zero). */
+int or_nrbc_normal(const or_params* P, const double* met, const double* U, int32_t i, int32_t j, int32_t k,
+                   int32_t d, int32_t side, double* out);
 
 #ifdef __cplusplus
 }

@@ -24,7 +24,7 @@ OCFD_SCHEME_WENO7, OCFD_SCHEME_HYBRID = 0, 1
 OCFD_LOWDISS_UD7, OCFD_LOWDISS_C8 = 0, 1
 OCFD_PREC_FP64, OCFD_PREC_MIXED = 0, 1
 OCFD_SENSOR_PLAIN, OCFD_SENSOR_LEARNED = 0, 1
-OCFD_BC_NONE, OCFD_BC_INFLOW, OCFD_BC_EXTRAP, OCFD_BC_WALL = 0, 1, 2, 3
+OCFD_BC_NONE, OCFD_BC_INFLOW, OCFD_BC_EXTRAP, OCFD_BC_WALL, OCFD_BC_NRBC = 0, 1, 2, 3, 4
 OCFD_PART_XI, OCFD_PART_ETA, OCFD_PART_ZETA, OCFD_PART_VISC, OCFD_PART_ALL = 1, 2, 4, 8, 15
 OCFD_RED_WENO0 = 9
 OCFD_RED_COUNT = 12

@@ -146,7 +146,7 @@ bool valid_params(const ocfd_params* p, std::string* why, int* code = nullptr) {
     }
     for (int side = 0; side < 2; ++side) {
       const int k = p->bc[2 * d + side];
-      if (k < OCFD_BC_NONE || k > OCFD_BC_WALL) { *why = "unknown boundary kind"; return false; }
+      if (k < OCFD_BC_NONE || k > OCFD_BC_NRBC) { *why = "unknown boundary kind"; return false; }
       if (k == OCFD_BC_INFLOW) ++ninflow;
       if (k == OCFD_BC_WALL && !(p->Tw > 0.0 && std::isfinite(p->Tw))) {
         *why = "a wall face needs Tw > 0";
@@ -194,6 +194,7 @@ void geo_phys_of(const ocfd_params& p, Geo* geo, Phys* phys) {
   g.s[2] = (long long)p.nx * p.ny;
   g.N = (long long)p.nx * p.ny * p.nz;
   for (int d = 0; d < 3; ++d) g.periodic[d] = p.periodic[d];
+  for (int f = 0; f < 6; ++f) g.setface[f] = !p.periodic[f / 2] && p.bc[f] != OCFD_BC_NRBC;
   g.div[0] = make_fastdiv((uint32_t)p.nx);
   g.div[1] = make_fastdiv((uint32_t)p.ny);
   Phys& ph = *phys;
@@ -439,6 +440,15 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
     e = launch_sweep(d, m, A, s->st);
     if (e != hipSuccess) return hip_fail(s, e, "sweep kernel");
   }
+  // normal-direction part of the nonreflecting faces, added to the stage
+  // (b dt) or to dU/dt
+  for (int f = 0; f < 6; ++f) {
+    const int d = f / 2;
+    if (s->p.periodic[d] || s->p.bc[f] != OCFD_BC_NRBC || !((parts >> d) & 1)) continue;
+    Timed tm(s, OCFD_K_OTHER);
+    e = launch_nrbc(s->g, s->ph, Ucur, s->met, out, d, f % 2, mode == MODE_RK ? b * dt : 1.0, s->st);
+    if (e != hipSuccess) return hip_fail(s, e, "nonreflecting face kernel");
+  }
   return OCFD_OK;
 }
 
@@ -447,7 +457,7 @@ int run_rhs(ocfd_solver* s, const double* Ucur, int mode, double* out, const dou
 int apply_bc(ocfd_solver* s, double* U) {
   for (int f = 0; f < 6; ++f) {
     const int d = f / 2;
-    if (s->p.periodic[d] || s->p.bc[f] == OCFD_BC_NONE) continue;
+    if (s->p.periodic[d] || s->p.bc[f] == OCFD_BC_NONE || s->p.bc[f] == OCFD_BC_NRBC) continue;
     Timed tm(s, OCFD_K_OTHER);
     hipError_t e = launch_bc(s->g, s->ph, U, d, f % 2, s->p.bc[f], s->p.Tw, s->inflow, s->st);
     if (e != hipSuccess) return hip_fail(s, e, "boundary kernel");

@@ -42,6 +42,7 @@ struct Geo {
   long long s[3];
   long long N;
   int periodic[3];
+  int setface[6];   // face f of a bounded direction whose kind sets its nodes after a stage (all but NRBC)
   FastDiv div[2];   // by n[0] and by n[1]
 };
 
@@ -149,6 +150,10 @@ hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* U, const
 // One face (d, side) of a bounded direction set by boundary kind `kind`.
 hipError_t launch_bc(const Geo& g, const Phys& ph, double* U, int d, int side, int kind, double Tw,
                      const double* inflow, hipStream_t st);
+// out [5][N] += coef * (normal-direction part of dU/dt) on the nodes of the
+// nonreflecting face (d, side), from the state U.
+hipError_t launch_nrbc(const Geo& g, const Phys& ph, const double* U, const double* met, double* out, int d, int side,
+                       double coef, hipStream_t st);
 // theta [N] of eq 42 from node pressures P [N].
 hipError_t launch_sensor(const Geo& g, const double* P, double* theta, hipStream_t st);
 // P [N] = pressure of U.

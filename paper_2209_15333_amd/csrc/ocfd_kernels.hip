@@ -281,8 +281,9 @@ hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* U, const
 // Divergence of the viscous fluxes (Sec. 2.3): rhs[0] = 0 and, for the
 // momentum and energy rows, rhs[1+q] = sum_d (d/d xi_d of Fv[4d+q]) / h_d,
 // each derivative of half width VH with the closures of line_deriv on
-// bounded lines (end nodes take the one-sided value; their dU/dt is zero
-// anyway).  Each flux is differentiated along its own direction only: the
+// bounded lines; at the end node of a bounded line the derivative along that
+// line is 0 (a face node either takes dU/dt = 0, or on a nonreflecting face
+// has no normal viscous term).  Each flux is differentiated along its own direction only: the
 // zeta fluxes through a register window of the zeta march, the xi fluxes from
 // an LDS row patch (the tile plus VH columns each side), the eta fluxes from
 // an LDS column patch (the tile plus VH rows above and below, read from memory
@@ -411,11 +412,13 @@ __global__ __launch_bounds__(256, 2) void k_visc_div(const Geo g, const Phys ph,
         const double* fx = pbuf + q * SX + ly * (VT_X + 2 * VH) + VH + lx;
         const double* fy = pbuf + 4 * SX + q * SY + (VH + ly) * VT_X + lx;
         const double dx = px ? central([&](int m) { return fx[m]; })
-                             : line_deriv([&](int m) { return fx[m]; }, i, nx, false, VH);
+                             : ((i == 0 || i == nx - 1) ? 0.0 : line_deriv([&](int m) { return fx[m]; }, i, nx, false, VH));
         const double dy = py ? central([&](int m) { return fy[m * VT_X]; })
-                             : line_deriv([&](int m) { return fy[m * VT_X]; }, j, ny, false, VH);
+                             : ((j == 0 || j == ny - 1) ? 0.0
+                                                        : line_deriv([&](int m) { return fy[m * VT_X]; }, j, ny, false, VH));
         const double dz = pz ? central([&](int m) { return zw[q][VH + m]; })
-                             : line_deriv([&](int m) { return zw[q][VH + m]; }, k, nz, false, VH);
+                             : ((k == 0 || k == nz - 1) ? 0.0
+                                                        : line_deriv([&](int m) { return zw[q][VH + m]; }, k, nz, false, VH));
         r[1 + q] = dx * ph.ih[0] + dy * ph.ih[1] + dz * ph.ih[2];
       }
 #pragma unroll
@@ -495,6 +498,115 @@ hipError_t launch_bc(const Geo& g, const Phys& ph, double* U, int d, int side, i
   const long long nf = (long long)g.n[d == 0 ? 1 : 0] * g.n[d == 2 ? 1 : 2];
   hipLaunchKernelGGL(k_bc, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, g, ph, U, d, side, kind, Tw,
                      inflow);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Characteristic nonreflecting faces (Thompson 1987, with the local
+// one-dimensional relations of Poinsot & Lele 1992; the paper imposes
+// nonreflecting conditions at the ramp's exit and upper boundary, Sec. 6.1,
+// without formulas).  A node of such a face is advanced like an interior
+// node: the sweeps give it the fluxes of the directions it is interior to,
+// and this kernel adds, for its normal direction d, the time derivative
+// carried by the characteristic waves that leave through the face (waves
+// entering have amplitude zero):
+//   s = |grad xi_d|, n = grad xi_d / s, q = (rho, u, v, w, p) and its
+//   one-sided second-order difference dq along xi_d into the grid, u_n = u.n;
+//   L1 = s (u_n - c)(dp - rho c du_n),  L5 = s (u_n + c)(dp + rho c du_n),
+//   L2 = s u_n (c^2 drho - dp),         Lt = s u_n (du - n (n.du));
+//   drho/dt = -(L2 + (L5 + L1)/2)/c^2, dp/dt = -(L5 + L1)/2,
+//   du/dt = -(n (L5 - L1)/(2 rho c) + Lt), in conserved variables,
+// plus the metric-derivative part of the normal flux derivative,
+// -J sum_a d(xi_a/J)/dxi F_a (one-sided difference of the metrics; F_a the
+// Cartesian inviscid flux), which keeps a uniform stream uniform on curved
+// grids.  The result times coef (b dt in a Runge-Kutta stage, 1 for dU/dt)
+// is added to out.  One thread per face node; nodes that also lie on a face
+// whose kind sets them after the stage are skipped.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_nrbc(const Geo g, const Phys ph, const double* __restrict__ U,
+                                              const double* __restrict__ met, double* __restrict__ out, int d,
+                                              int side, double coef) {
+  const int e0 = d == 0 ? 1 : 0, e1 = d == 2 ? 1 : 2;
+  const long long nf = (long long)g.n[e0] * g.n[e1];
+  const long long f = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (f >= nf) return;
+  int c[3];
+  c[e0] = (int)(f % g.n[e0]);
+  c[e1] = (int)(f / g.n[e0]);
+  c[d] = side ? g.n[d] - 1 : 0;
+  for (int a = 0; a < 3; ++a)
+    if ((c[a] == 0 && g.setface[2 * a]) || (c[a] == g.n[a] - 1 && g.setface[2 * a + 1])) return;
+  const long long N = g.N;
+  const long long id = c[0] + g.s[1] * c[1] + g.s[2] * c[2];
+  const long long step = side ? -g.s[d] : g.s[d];   // toward the interior
+  const double sgn = side ? -1.0 : 1.0;
+  const double ih = ph.ih[d];
+  double q[3][5], mt[3][3];
+#pragma unroll
+  for (int t = 0; t < 3; ++t) {
+    const long long it = id + t * step;
+    const double rho = U[it];
+    const double ir = 1.0 / rho;
+    const double u = U[N + it] * ir, v = U[2 * N + it] * ir, w = U[3 * N + it] * ir;
+    q[t][0] = rho;
+    q[t][1] = u;
+    q[t][2] = v;
+    q[t][3] = w;
+    q[t][4] = ph.gm1 * (U[4 * N + it] - 0.5 * rho * (u * u + v * v + w * w));
+#pragma unroll
+    for (int a = 0; a < 3; ++a) mt[t][a] = met[(3 * d + a) * N + it];
+  }
+  double dq[5];
+#pragma unroll
+  for (int m = 0; m < 5; ++m) dq[m] = sgn * 0.5 * (-3.0 * q[0][m] + 4.0 * q[1][m] - q[2][m]) * ih;
+  const double jinv = met[9 * N + id];
+  const double ij = 1.0 / jinv;
+  const double gx = mt[0][0] * ij, gy = mt[0][1] * ij, gz = mt[0][2] * ij;
+  const double sg = sqrt(gx * gx + gy * gy + gz * gz);
+  const double n[3] = {gx / sg, gy / sg, gz / sg};
+  const double rho = q[0][0], p = q[0][4];
+  const double uv[3] = {q[0][1], q[0][2], q[0][3]};
+  const double cs = sqrt(ph.gamma * p / rho);
+  const double un = uv[0] * n[0] + uv[1] * n[1] + uv[2] * n[2];
+  const double dun = dq[1] * n[0] + dq[2] * n[1] + dq[3] * n[2];
+  const double lam1 = sg * (un - cs), lam2 = sg * un, lam5 = sg * (un + cs);
+  auto outgoing = [&](double l) { return side ? l >= 0.0 : l <= 0.0; };
+  const double L1 = outgoing(lam1) ? lam1 * (dq[4] - rho * cs * dun) : 0.0;
+  const double L5 = outgoing(lam5) ? lam5 * (dq[4] + rho * cs * dun) : 0.0;
+  const bool o2 = outgoing(lam2);
+  const double L2 = o2 ? lam2 * (cs * cs * dq[0] - dq[4]) : 0.0;
+  const double drho = -(L2 + 0.5 * (L5 + L1)) / (cs * cs);
+  const double dp = -0.5 * (L5 + L1);
+  double dv[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double Lt = o2 ? lam2 * (dq[1 + a] - n[a] * dun) : 0.0;
+    dv[a] = -(n[a] * (L5 - L1) / (2.0 * rho * cs) + Lt);
+  }
+  double r[5];
+  r[0] = drho;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) r[1 + a] = uv[a] * drho + rho * dv[a];
+  const double uu = uv[0] * uv[0] + uv[1] * uv[1] + uv[2] * uv[2];
+  r[4] = dp / ph.gm1 + 0.5 * uu * drho + rho * (uv[0] * dv[0] + uv[1] * dv[1] + uv[2] * dv[2]);
+  const double E = U[4 * N + id];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double dm = sgn * 0.5 * (-3.0 * mt[0][a] + 4.0 * mt[1][a] - mt[2][a]) * ih;
+    const double Fa[5] = {rho * uv[a], rho * uv[0] * uv[a] + (a == 0 ? p : 0.0), rho * uv[1] * uv[a] + (a == 1 ? p : 0.0),
+                          rho * uv[2] * uv[a] + (a == 2 ? p : 0.0), (E + p) * uv[a]};
+#pragma unroll
+    for (int m = 0; m < 5; ++m) r[m] -= dm * Fa[m] * ij;
+  }
+#pragma unroll
+  for (int m = 0; m < 5; ++m) out[m * N + id] += coef * r[m];
+}
+
+hipError_t launch_nrbc(const Geo& g, const Phys& ph, const double* U, const double* met, double* out, int d, int side,
+                       double coef, hipStream_t st) {
+  const long long nf = (long long)g.n[d == 0 ? 1 : 0] * g.n[d == 2 ? 1 : 2];
+  hipLaunchKernelGGL(k_nrbc, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, st, g, ph, U, met, out, d, side, coef);
   return hipGetLastError();
 }
 

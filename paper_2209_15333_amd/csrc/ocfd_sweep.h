@@ -215,16 +215,18 @@ void k_sweep(const SweepArgs A) {
 #pragma unroll
       for (int q = 0; q < 5; ++q) __builtin_nontemporal_store(e.s[q] + r[q], A.rhs + q * N + id);
     } else {
-      // nodes on a face of a non-periodic direction take dU/dt = 0 (their
-      // value is set by the boundary condition after the stage)
+      // nodes on a face whose kind sets them after the stage take dU/dt = 0
+      // (every kind but the nonreflecting one, whose nodes keep the terms of
+      // the directions they are interior to; the normal part is added by
+      // k_nrbc)
       bool bnd = false;
       if (anyb) {
         int pq[3];
         node_position(A.g, id, pq);
         const int p0 = pq[0], p1 = pq[1], p2 = pq[2];
-        bnd = (!A.g.periodic[0] && (p0 == 0 || p0 == A.g.n[0] - 1)) ||
-              (!A.g.periodic[1] && (p1 == 0 || p1 == A.g.n[1] - 1)) ||
-              (!A.g.periodic[2] && (p2 == 0 || p2 == A.g.n[2] - 1));
+        bnd = (p0 == 0 && A.g.setface[0]) || (p0 == A.g.n[0] - 1 && A.g.setface[1]) ||
+              (p1 == 0 && A.g.setface[2]) || (p1 == A.g.n[1] - 1 && A.g.setface[3]) ||
+              (p2 == 0 && A.g.setface[4]) || (p2 == A.g.n[2] - 1 && A.g.setface[5]);
       }
       const double ij = 1.0 / e.ij;
 #pragma unroll

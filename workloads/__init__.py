@@ -237,6 +237,33 @@ def lax(n: int = 200, width: int = 2) -> Case:
                                nsteps=3 * int(round(0.13 / dt)))
 
 
+def acoustic_pulse(n: int = 201, width: int = 4, u0: float = 0.3, amplitude: float = 1e-3, sigma: float = 0.05,
+                   x0: float = 0.5, direction: int = 1, bc: int = 4) -> Case:
+    """A plane acoustic pulse in a uniform stream on x in [0, 1] (n nodes,
+    bounded, faces of kind `bc` at both ends) with `width` identical nodes in
+    the two periodic directions.  Free stream rho = 1, u = u0, Ma = 1 (sound
+    speed 1, p = 1/gamma); the pulse p' = amplitude p exp(-((x-x0)/sigma)^2)
+    with u' = direction p'/(rho c), rho' = p'/c^2 runs in +x (direction 1) or
+    -x (direction -1).  Euler; time step 0.4 h."""
+    nx, ny, nz = n, width, width
+    h = 1.0 / (n - 1)
+    Ls = (1.0, 0.1 * width, 0.1 * width)
+    X = np.arange(nx) * h
+    Y = np.arange(ny) * (Ls[1] / ny)
+    Z = np.arange(nz) * (Ls[2] / nz)
+    Zg, Yg, Xg = np.meshgrid(Z, Y, X, indexing="ij")
+    xyz = np.ascontiguousarray(np.stack([Xg, Yg, Zg]).astype(np.float64))
+    g = 1.4
+    p0 = 1.0 / g
+    pp = amplitude * p0 * np.exp(-((Xg - x0) / sigma) ** 2)
+    rho = 1.0 + pp
+    u = u0 + direction * pp
+    zero = np.zeros_like(rho)
+    return Case(name=f"pulse{n}", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=conserved(g, rho, u, zero, zero, p0 + pp),
+                period=(0.0, Ls[1], Ls[2]), h=(h, Ls[1] / ny, Ls[2] / nz), dt=0.4 * h, nsteps=0,
+                periodic=(0, 1, 1), bc=(bc, bc, 0, 0, 0, 0), gamma=g, Re=1.0, Ma=1.0, viscous=0)
+
+
 def isotropic_turbulence(n: int = 512, seed: int = 22093, k0: float = 4.0, Mt: float = 0.6,
                          Re_lambda: float = 100.0, dt: Optional[float] = None, nsteps: int = 500) -> Case:
     """Decaying compressible isotropic turbulence on [0, 2 pi)^3.
@@ -307,7 +334,7 @@ def _smooth_noise(rng, shape, sigma_cells: float = 2.0):
 
 def compression_ramp(shape: Tuple[int, int, int] = (1024, 160, 128), seed: int = 22094, Ma: float = 2.9,
                      angle_deg: float = 24.0, Re: float = 5e4, Tw: float = 2.84, dt: Optional[float] = None,
-                     nsteps: int = 100, noise: float = 0.05, viscous: int = 8) -> Case:
+                     nsteps: int = 100, noise: float = 0.05, viscous: int = 8, exit_bc: int = 4) -> Case:
     """Supersonic flow over a compression ramp on a body-fitted grid (lengths in
     units of the inflow boundary-layer thickness delta).
 
@@ -320,8 +347,10 @@ def compression_ramp(shape: Tuple[int, int, int] = (1024, 160, 128), seed: int =
     and recovery factor Pr^(1/2), uniform pressure 1/(gamma Ma^2), plus
     noise * u_bar * (Gaussian-smoothed white noise, 2 cells, unit rms) on u,
     v, w (PCG64(seed)).  Boundaries: inflow (the initial profile) at x = -20,
-    extrapolation at the outlet and the top, isothermal wall at y_w.  Viscous
-    terms of eighth order, as the paper's ramp runs (Sec. 5.1, 6.1)."""
+    isothermal wall at y_w, and at the outlet and the top faces of kind
+    exit_bc: 4 characteristic nonreflecting (the paper's Sec. 6.1), 2
+    extrapolation.  Viscous terms of eighth order, as the paper's ramp runs
+    (Sec. 5.1, 6.1)."""
     nx, ny, nz = shape
     g, Pr = 1.4, 0.72
     r, H, Lz = 0.25, 10.0, 4.0
@@ -359,7 +388,7 @@ def compression_ramp(shape: Tuple[int, int, int] = (1024, 160, 128), seed: int =
         dt = 8e-4   # set by the 0.002-high wall cell (acoustic CFL ~0.33)
     h = (32.0 / (nx - 1), H / (ny - 1), Lz / nz)
     return Case(name=f"ramp{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=U0, period=(0.0, 0.0, Lz), h=h,
-                dt=dt, nsteps=nsteps, periodic=(0, 0, 1), bc=(1, 2, 3, 2, 0, 0), gamma=g, Re=Re, Ma=Ma, Pr=Pr,
+                dt=dt, nsteps=nsteps, periodic=(0, 0, 1), bc=(1, exit_bc, 3, exit_bc, 0, 0), gamma=g, Re=Re, Ma=Ma, Pr=Pr,
                 Tref=108.1, Tw=Tw, inflow=inflow, viscous=viscous)
 
 
@@ -369,8 +398,10 @@ def bounded_box(shape: Tuple[int, int, int] = (36, 20, 18), seed: int = 22095, M
     nodes moved by amplitude * sin products (phases from PCG64(seed)); a smooth
     shear flow u = 1 + 0.3 tanh(2 (y - y_mid)), v = 0.1 sin(x/2), w = 0.05 cos(z/2)
     at Mach Ma with uniform pressure and temperature 1, plus relative noise on
-    the velocities.  Faces: inflow (the initial face) at xi-, extrapolation at
-    xi+, isothermal wall (Tw = 1) at eta-, extrapolation elsewhere."""
+    the velocities.  Faces: inflow (the initial face) at xi-, characteristic
+    nonreflecting at xi+ and zeta+ (their common edge takes both normal
+    parts), isothermal wall (Tw = 1) at eta-, extrapolation at eta+ and
+    zeta-."""
     nx, ny, nz = shape
     rng = np.random.Generator(np.random.PCG64(seed))
     ph = rng.uniform(0.0, 2.0 * math.pi, 9)
@@ -393,7 +424,7 @@ def bounded_box(shape: Tuple[int, int, int] = (36, 20, 18), seed: int = 22095, M
     U0 = conserved(g, rho, u, v, w, p)
     inflow = np.ascontiguousarray(U0[:, :, :, 0])
     return Case(name=f"box{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, xyz=xyz, U0=U0, period=(0.0, 0.0, 0.0),
-                h=(1.0, 1.0, 1.0), dt=0.05, nsteps=10, periodic=(0, 0, 0), bc=(1, 2, 3, 2, 2, 2), gamma=g, Re=Re,
+                h=(1.0, 1.0, 1.0), dt=0.05, nsteps=10, periodic=(0, 0, 0), bc=(1, 4, 3, 2, 2, 4), gamma=g, Re=Re,
                 Ma=Ma, Pr=0.72, Tw=1.0, inflow=inflow)
 
 
