@@ -108,8 +108,12 @@ def test_plain_flags_match_oracle(pk, torch_cuda, orc):
     assert diff.sum() == 0 or np.abs(theta - case.theta1).min() <= 1e-12
 
 
-def test_learned_flags_match_oracle(pk, torch_cuda, orc):
-    case = _developed(orc, _hit(24))
+# nx = 24: tiles of 16 consecutive nodes cross xi rows (general gather);
+# nx = 32: every tile is 16 nodes of one xi row (the path taken at the sizes
+# the benchmark times, where nx is a multiple of 16)
+@pytest.mark.parametrize("n", [24, 32])
+def test_learned_flags_match_oracle(pk, torch_cuda, orc, n):
+    case = _developed(orc, _hit(n))
     s = _solver(pk, torch_cuda, case)
     theta = mlp.init_params(5)
     theta[mlp.NPARAM - 33:mlp.NPARAM - 1] *= 20.0
@@ -136,10 +140,12 @@ def test_learned_flags_match_oracle(pk, torch_cuda, orc):
         assert np.all(np.abs(p[bad] - tau) < 1e-3)
 
 
-def test_learned_flags_bounded_match_oracle(pk, torch_cuda, orc):
+@pytest.mark.parametrize("shape", [(40, 24, 8), (48, 24, 8)])
+def test_learned_flags_bounded_match_oracle(pk, torch_cuda, orc, shape):
     """Reduced compression ramp (bounded xi, eta): one-sided features at the
-    ends, flag 1 wherever the interface window leaves the grid."""
-    case = workloads.compression_ramp(shape=(40, 24, 8))
+    ends, flag 1 wherever the interface window leaves the grid (nx = 48: the
+    row-tile path)."""
+    case = workloads.compression_ramp(shape=shape)
     case.scheme, case.sensor = "hybrid", "learned"
     s = _solver(pk, torch_cuda, case)
     theta = mlp.init_params(9)
