@@ -1,16 +1,21 @@
-"""Throughput of the FP64 path on one MI355X, in grid-point substeps per second.
+"""Throughput of the hot path on one MI355X, in grid-point substeps per second.
 
-Workload: the plain FP64 method on two 256^3 periodic grids distorted by a
-sinusoidal mapping (amplitude 0.1 h, seeded phases): the Taylor-Green vortex
-(Re 1600, M 0.1, WENO7 + sixth-order viscous terms) and the isentropic
-vortex (strength 5, advection (1,1,0), M 0.5, Euler).  One benchmark step is
-one Runge-Kutta substep of each of the two runs.  Inputs are synthetic and
-already resident in HBM when the timed region starts.
+Headline: the Mach 2.9 compression ramp on a 2048 x 256 x 256 body-fitted grid
+(134 M points), the plain FP64 hybrid (UD7 / WENO7 with the pressure sensor
+of eq 42-43) against the FP32 split/reconstruction form with the learned
+sensor trained in-run from the plain sensor's flags, on the identical seeded
+grid and inflow state.  `value` is the FP32 + learned form's throughput; the
+plain FP64 rate, the ratio and the learned form's per-field relative L2
+against the plain one after the timed substeps sit beside it.  Inputs are
+synthetic and resident in HBM when the timed region starts.
 
-Prints one JSON line.  The dominant kernel's duration comes from HIP events
-the library records around every launch on its stream during the timed
-region; the CPU baseline is the oracle on a bounded sample (one substep of
-each 256^3 run on the host cores).
+The dominant kernel's duration comes from HIP events the library records
+around every launch on its stream during the timed region.  The CPU baseline
+is the oracle on a bounded slab of the same workload.  Further comparisons
+(the 256^3 FP64 WENO7 runs, isotropic turbulence 512^3, the 1024 x 160 x 128
+ramp) follow under `forms`.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -31,8 +36,15 @@ FLOPS_PRIM = 15          # rho, u, v, w, p and c of a node
 FLOPS_SW = 92            # Steger-Warming split of a node, both signs
 FLOPS_WENO7 = 143        # one seventh-order WENO reconstruction
 FLOPS_IFACE = 10 * FLOPS_WENO7 + 5
+FLOPS_IFACE_LOW = 5 * 27 + 5   # one linear-stencil interface (UD7 of both signs), five components
 FLOPS_DIFF = 10          # flux difference of the five components
 FLOPS_MODE = {"set": 0, "add": 5, "rk": 30}
+# The paper-style manual count (its Table 6 convention): Steger-Warming split
+# of a node, one WENO7 and one linear-stencil reconstruction, the RK update.
+FLOPS_SURVEY_SW = 140
+FLOPS_SURVEY_WENO = 200
+FLOPS_SURVEY_LOW = 15
+FLOPS_SURVEY_RK = 21
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 HBM_PEAK_GBS = 8000.0
@@ -46,41 +58,9 @@ HBM_PEAK_GBS = 8000.0
 PMC_TRAFFIC = {"sweep_xi": {"fetch_kib": 1473148, "write_kib": 665600}}
 
 
-def sweep_flops(mode: str) -> int:
-    return FLOPS_PRIM + FLOPS_SW + FLOPS_IFACE + FLOPS_DIFF + FLOPS_MODE[mode]
-
-
 def make_cases(n: int):
     import workloads
     return [workloads.taylor_green(n, distorted=True), workloads.isentropic_vortex(n, distorted=True)]
-
-
-def cpu_baseline(cases, threads: int):
-    """The oracle, unchanged, on one substep of each run (metrics excluded)."""
-    import oracle
-    total_pts, total_t = 0, 0.0
-    for c in cases:
-        P = oracle.params_from_case(c, nthreads=threads)
-        met = oracle.metrics(P, c.xyz)
-        t0 = time.perf_counter()
-        oracle.advance(P, met, c.U0, 1, c.dt)
-        total_t += time.perf_counter() - t0
-        total_pts += c.N
-        del met
-    # the same oracle on one core, on a smaller sample of the same kind
-    import workloads
-    small = workloads.taylor_green(96, distorted=True)
-    P = oracle.params_from_case(small, nthreads=1)
-    met = oracle.metrics(P, small.xyz)
-    t0 = time.perf_counter()
-    oracle.advance(P, met, small.U0, 1, small.dt)
-    t1 = time.perf_counter() - t0
-    return {"value": total_pts / total_t / 1e9, "unit": "Gpt-substeps/s", "cores": threads, "kind": "oracle",
-            "sample": f"one substep of each of the {len(cases)} runs at full size ({total_pts} point-substeps), "
-                      f"{total_t:.1f} s",
-            "single_core": {"value": small.N / t1 / 1e9, "cores": 1,
-                            "sample": f"one substep of the distorted Taylor-Green vortex at 96^3 ({small.N} "
-                                      f"point-substeps), {t1:.1f} s"}}
 
 
 def _log(msg):
@@ -286,18 +266,73 @@ def form_ramp_mixed(torch, pk, shape, substeps):
             "forms": res}
 
 
-def form_ramp_full(torch, pk, shape, train, substeps, report):
-    """The ramp at scale with the full chosen form.  The plain FP64 hybrid
-    (UD7 / WENO7, plain sensor) runs `train` substeps from the inflow state
-    with the plain sensor's flags sampled every 50 substeps; the perceptron is
-    trained and calibrated on the GPU (an unbiased sample of every snapshot,
-    32 epochs).  Then, from the same inflow state, the plain FP64 hybrid and
-    the FP32 + learned-sensor hybrid (network every substep, and once per
-    Runge-Kutta step; audited every `report` substeps, union fallback) run
-    `substeps` substeps each in turns of `report`; after every turn the
-    per-field relative L2 of each learned form against the plain one and the
-    audit rates of the turn are recorded.  Each form's time is the sum of its
-    turns."""
+def _prof_avg_us(prof):
+    return {k: round(v[0] / v[1] * 1e3, 1) for k, v in prof.items() if v[1]}
+
+
+def _sweep_roofline(prof, N, weno_frac, mixed, hybrid=True, viscous=True, last_dir=0):
+    """Roofline entry of the sweep class with the largest time in `prof`
+    (ocfd_profile_read of a timed region).
+
+    Flops per node of a sweep launch by the paper-style manual count (its
+    Sec. 5.4, Table 6 convention: an FMA counts two): 140 for the
+    Steger-Warming split, 10 reconstructions of 200 (WENO7) or 15 (linear
+    stencil) flops, 21 for the Runge-Kutta update in the last sweep;
+    weno_frac[d] is the WENO fraction of direction d's interfaces.
+    Algorithmic bytes per node (each array once): U 40, the metric row 24,
+    the sum of the earlier sweeps 40 (accumulating and last sweeps), in the
+    last sweep U^n 40 x 2/3 (stages 2 and 3) and 1/J 8; hybrid sweeps read
+    their viscous-flux row 32 and one flag byte; every sweep writes 40.  The
+    binding roof is the one the algorithmic work reaches first: FP64 (or FP32)
+    vector flops or HBM bytes.  The design-count flop figure (every operation
+    as computed) is kept beside it."""
+    sweeps = [k for k in prof if k.startswith("sweep") and prof[k][1]]
+    dom = max(sweeps, key=lambda k: prof[k][0])
+    d = {"sweep_xi": 0, "sweep_eta": 1, "sweep_zeta": 2}[dom]
+    phi = float(weno_frac[d])
+    rk = d == last_dir
+    first = d == 2
+    flops = FLOPS_SURVEY_SW + 10 * (FLOPS_SURVEY_LOW + (FLOPS_SURVEY_WENO - FLOPS_SURVEY_LOW) * phi) + \
+        (FLOPS_SURVEY_RK if rk else 0)
+    design = FLOPS_PRIM + FLOPS_SW + phi * FLOPS_IFACE + (1.0 - phi) * FLOPS_IFACE_LOW + FLOPS_DIFF + \
+        FLOPS_MODE["rk" if rk else "add"]
+    vdiv = viscous and not hybrid and not mixed      # the first sweep adds onto the viscous divergence
+    nbytes = 40 + 24 + 40                             # U, metric row; output
+    nbytes += 40 if (not first or vdiv) else 0        # the sum of the earlier sweeps
+    nbytes += (40 * 2 / 3 + 8) if rk else 0           # U^n (stages 2, 3), 1/J
+    nbytes += 32 if (viscous and (hybrid or mixed)) else 0   # this direction's viscous-flux row
+    nbytes += 1 if hybrid else 0                      # interface flag
+    ms, cnt = prof[dom]
+    t = ms / cnt * 1e-3
+    peak = FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS
+    t_alu = flops * N / (peak * 1e12)
+    t_hbm = nbytes * N / (HBM_PEAK_GBS * 1e9)
+    out = {"kernel": dom, "avg_launch_us": round(t * 1e6, 1), "weno_frac": round(phi, 4),
+           "flops_per_node": round(flops, 1), "bytes_per_node": round(nbytes, 1),
+           "alu_frac": round(t_alu / t, 4), "hbm_frac": round(t_hbm / t, 4),
+           "frac_design_count": round(design * N / t / 1e12 / peak, 4),
+           "flops_per_node_design_count": round(design, 1), "traffic": None}
+    if t_hbm > t_alu:
+        out.update({"bound": "hbm", "achieved": round(nbytes * N / t / 1e9, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(t_hbm / t, 4)})
+    else:
+        out.update({"bound": "alu", "achieved": round(flops * N / t / 1e12, 3), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(t_alu / t, 4)})
+    return out
+
+
+def headline_ramp(torch, pk, shape, train, epochs, steps, warmup, report=100):
+    """The ramp at scale: plain FP64 hybrid (UD7 / WENO7, plain sensor) against
+    the FP32 + learned-sensor hybrid on the identical seeded grid and inflow
+    state.  The plain FP64 hybrid runs `train` substeps from the inflow state
+    with an unbiased sample of the plain sensor's flags every 50 substeps; the
+    perceptron is trained (`epochs` passes) and calibrated on the GPU.  Then
+    each form runs `warmup` substeps from the inflow state and is reset to
+    it, and both march `steps` substeps in turns of `report`, each turn timed
+    (kernel classes by the library's HIP events on the solver's stream).
+    After every turn: the learned form's per-field relative L2 against the
+    plain one, both forms' WENO fractions per direction and the learned
+    sensor's audit of that turn."""
     import dataclasses
     import workloads
     t_all = time.perf_counter()
@@ -324,117 +359,231 @@ def form_ramp_full(torch, pk, shape, train, substeps, report):
     for k in range(train // every):
         s.advance(every, case.dt)
         # the same keep rate for both classes: an unbiased sample of every
-        # snapshot, spread over the whole run (about 0.8 M per snapshot)
+        # snapshot, spread over the whole run
         total = pk.ocfd_sensor_collect(s.h, 9000 + k, 0.002, 0.002)
     torch.cuda.synchronize()
     t_dev = time.perf_counter() - t0
+    # WENO fraction of the developed state under both readings of the sensor window
+    win = {"stencil_j-3..j+4": [round(v, 5) for v in s.reduce(case.dt)[9:12]]}
+    alt = pk.Solver(pk.params_from(case, flag_window=1))
+    alt.set_grid(xyz)
+    fl = torch.empty((3,) + tuple(U0.shape[1:]), dtype=torch.uint8, device="cuda")
+    pk.ocfd_sensor_flags(alt.h, s.state(), pk.OCFD_SENSOR_PLAIN, fl)
+    win["nodes_j,j+1"] = [round(float(fl[d].float().mean()), 5) for d in range(3)]
+    alt.close()
+    del alt, fl
     pk.ocfd_sensor_set_params(s.h, workloads.sensor_initial_weights(13))
     t0 = time.perf_counter()
-    epochs = 32
     stats = pk.ocfd_sensor_train(s.h, epochs, 2048, 3e-3, 9, 0.1)
     cal = pk.ocfd_sensor_calibrate(s.h, 0.1, 0.5)
     t_train = time.perf_counter() - t0
     params = pk.ocfd_sensor_get_params(s.h)
     tau = cal[0]
-    _log(f"ramp{nx}x{ny}x{nz}: {train} plain substeps in {t_dev:.1f} s, {total} samples; trained in {t_train:.1f} s, "
-         f"tau {tau:.3g}, held-out recall {cal[1]}, false-positive rate {cal[2]:.4f}")
+    _log(f"ramp{nx}x{ny}x{nz}: {train} plain substeps in {t_dev:.1f} s, {total} samples; trained in "
+         f"{t_train:.1f} s, tau {tau:.3g}, held-out recall {cal[1]}, false-positive rate {cal[2]:.4f}; "
+         f"WENO fractions {win}")
     del buf
     s.close()
     del s
     torch.cuda.empty_cache()
-    plain = solver(case)
-    # the network every substep, and once per Runge-Kutta step (its flags
-    # then hold for the step's three stages)
-    learned = solver(dataclasses.replace(case, precision="mixed", sensor="learned", sensor_every=1,
-                                         audit_every=report))
-    learned3 = solver(dataclasses.replace(case, precision="mixed", sensor="learned", sensor_every=3,
-                                          audit_every=report))
-    for sv in (learned, learned3):
-        pk.ocfd_sensor_set_params(sv.h, params)
-        pk.ocfd_sensor_set_threshold(sv.h, tau)
-    elapsed = {"p": 0.0, "l": 0.0, "l3": 0.0}
+    learned_case = dataclasses.replace(case, precision="mixed", sensor="learned", sensor_every=3,
+                                       audit_every=report)
+    cases = {"plain_fp64": case, "learned_fp32": learned_case}
+    solvers = {}
+    for name, c in cases.items():
+        sv = solver(c)
+        if c.sensor == "learned":
+            pk.ocfd_sensor_set_params(sv.h, params)
+            pk.ocfd_sensor_set_threshold(sv.h, tau)
+        sv.advance(warmup, c.dt)
+        sv.set_state(U0)
+        solvers[name] = sv
+    torch.cuda.synchronize()
+    # both forms march in turns of `report` substeps; each turn is timed on its
+    # own (kernel classes by the library's HIP events), the comparisons
+    # between turns are not
+    elapsed = {name: 0.0 for name in cases}
+    fracs = {name: [] for name in cases}
     turns = []
-    prev = [0.0] * 6
-    prev3 = [0.0] * 6
-    for k in range(substeps // report):
-        for sv, which in ((plain, "p"), (learned, "l"), (learned3, "l3")):
+    prev = pk.ocfd_sensor_audit(solvers["learned_fp32"].h)
+    for sv in solvers.values():
+        pk.ocfd_profile(sv.h, True)
+    done = 0
+    while done < steps:
+        n = min(report, steps - done)
+        for name, sv in solvers.items():
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            sv.advance(report, case.dt)
+            sv.advance(n, case.dt)
             torch.cuda.synchronize()
-            elapsed[which] += time.perf_counter() - t0
-        a = pk.ocfd_sensor_audit(learned.h)
-        d = [a[i] - prev[i] for i in range(6)]
+            elapsed[name] += time.perf_counter() - t0
+        done += n
+        red = {name: sv.reduce(case.dt) for name, sv in solvers.items()}
+        for name in cases:
+            fracs[name].append(red[name][9:12])
+        a = pk.ocfd_sensor_audit(solvers["learned_fp32"].h)
+        dlt = [a[i] - prev[i] for i in range(6)]
         prev = a
-        a3 = pk.ocfd_sensor_audit(learned3.h)
-        d3 = [a3[i] - prev3[i] for i in range(6)]
-        prev3 = a3
-        red = plain.reduce(case.dt)
-        turns.append({"substeps": (k + 1) * report,
-                      "rel_l2_learned_fp32_vs_plain_fp64": [float(f"{e:.3e}") for e in
-                                                            _rel_l2(torch, learned.state(), plain.state())],
-                      "plain_weno_frac": round(d[2] / max(d[1], 1), 5),
-                      "learned_weno_frac": round(d[3] / max(d[1], 1), 5),
-                      "mismatch_rate": round(d[5] / max(d[1], 1), 6),
-                      "missed_frac_of_plain_weno": round(d[4] / max(d[2], 1), 6),
-                      "plain_weno_frac_by_direction": [round(v, 5) for v in red[9:12]],
-                      "rel_l2_learned_per_step_fp32_vs_plain_fp64": [float(f"{e:.3e}") for e in
-                                                                     _rel_l2(torch, learned3.state(), plain.state())],
-                      "learned_per_step_weno_frac": round(d3[3] / max(d3[1], 1), 5),
-                      "learned_per_step_missed_frac_of_plain_weno": round(d3[4] / max(d3[2], 1), 6)})
+        # the audit of a turn runs at its first substep (a multiple of `report`)
+        turns.append({"substeps": done,
+                      "rel_l2_learned_fp32_vs_plain_fp64": [float(f"{e:.3e}") for e in _rel_l2(
+                          torch, solvers["learned_fp32"].state(), solvers["plain_fp64"].state())],
+                      "plain_weno_frac_by_direction": [round(v, 5) for v in red["plain_fp64"][9:12]],
+                      "learned_weno_frac_by_direction": [round(v, 5) for v in red["learned_fp32"][9:12]],
+                      "audit_at_substep": done - n,
+                      "audit_plain_weno_frac": round(dlt[2] / max(dlt[1], 1), 5),
+                      "audit_learned_weno_frac": round(dlt[3] / max(dlt[1], 1), 5),
+                      "audit_mismatch_rate": round(dlt[5] / max(dlt[1], 1), 6),
+                      "audit_missed_frac_of_plain_weno": round(dlt[4] / max(dlt[2], 1), 6)})
         _log(f"ramp{nx}x{ny}x{nz}: {turns[-1]}")
-    rate_p = case.N * substeps / elapsed["p"] / 1e9
-    rate_l = case.N * substeps / elapsed["l"] / 1e9
-    rate_l3 = case.N * substeps / elapsed["l3"] / 1e9
-    plain.close()
-    learned.close()
-    learned3.close()
-    del plain, learned, learned3, xyz, inflow, U0
+    forms = {}
+    for name, sv in solvers.items():
+        c = cases[name]
+        prof = pk.ocfd_profile_read(sv.h)
+        pk.ocfd_profile(sv.h, False)
+        mean_frac = np.mean(np.array(fracs[name]), axis=0)
+        forms[name] = {"gpt_substeps_per_s": round(c.N * steps / elapsed[name] / 1e9, 4),
+                       "ms_per_substep": round(elapsed[name] / steps * 1e3, 3),
+                       "avg_launch_us": _prof_avg_us(prof),
+                       "weno_frac_mean_over_turns": [round(v, 5) for v in mean_frac],
+                       "roofline": _sweep_roofline(prof, c.N, mean_frac, c.precision == "mixed")}
+        _log(f"ramp{nx}x{ny}x{nz}: {name}: {forms[name]['gpt_substeps_per_s']} Gpt-substeps/s, "
+             f"{forms[name]['avg_launch_us']}")
+    a = pk.ocfd_sensor_audit(solvers["learned_fp32"].h)
+    forms["learned_fp32"]["audit"] = {"runs": int(a[0]), "plain_weno_frac": round(a[2] / max(a[1], 1), 5),
+                                      "learned_weno_frac": round(a[3] / max(a[1], 1), 5),
+                                      "missed_frac_of_plain_weno": round(a[4] / max(a[2], 1), 6),
+                                      "mismatch_rate": round(a[5] / max(a[1], 1), 6)}
+    drift100 = turns[0]["rel_l2_learned_fp32_vs_plain_fp64"] if turns and turns[0]["substeps"] == report else None
+    drift_end = turns[-1]["rel_l2_learned_fp32_vs_plain_fp64"] if turns else None
+    for sv in solvers.values():
+        sv.close()
+    del solvers, xyz, inflow, U0
     torch.cuda.empty_cache()
-    return {"workload": f"Mach 2.9 24-degree compression ramp {nx}x{ny}x{nz} ({case.N} points), C8 viscous, "
-                        f"hybrid UD7 / WENO7 from the inflow state; {substeps} substeps per form",
-            "training": {"plain_substeps": train, "samples": total, "epochs": epochs, "batch": 2048,
-                         "loss_first_last": [round(stats[0], 5), round(stats[1], 5)], "tau": tau,
-                         "heldout_recall": cal[1], "heldout_false_positive_rate": round(cal[2], 5),
-                         "train_s": round(t_train, 2)},
-            "forms": {"hybrid_plain_fp64": {"gpt_substeps_per_s": round(rate_p, 4)},
-                      "hybrid_learned_fp32": {"gpt_substeps_per_s": round(rate_l, 4),
-                                              "speedup_vs_hybrid_plain_fp64": round(rate_l / rate_p, 3)},
-                      "hybrid_learned_per_step_fp32": {"gpt_substeps_per_s": round(rate_l3, 4),
-                                                       "speedup_vs_hybrid_plain_fp64": round(rate_l3 / rate_p, 3)}},
-            "every_100_substeps": turns}
+    out = {"workload": f"Mach 2.9 24-degree compression ramp {nx}x{ny}x{nz} ({case.N} points), isothermal wall "
+                       f"Tw 2.84, nonreflecting exit and top, Re_delta 5e4, C8 viscous, hybrid UD7 / WENO7: plain "
+                       f"FP64 (pressure sensor) vs FP32 split/reconstruction + learned sensor once per RK step "
+                       f"(audited every {report} substeps); {steps} timed substeps each from the inflow state",
+           "points": case.N, "forms": forms,
+           "rel_l2_learned_vs_plain_after_100": drift100, "rel_l2_learned_vs_plain_at_end": drift_end,
+           "plain_weno_frac_after_training_run": win,
+           "training": {"plain_substeps": train, "samples": total, "epochs": epochs, "batch": 2048,
+                        "loss_first_last": [round(stats[0], 5), round(stats[1], 5)], "tau": tau,
+                        "heldout_recall": cal[1], "heldout_false_positive_rate": round(cal[2], 5),
+                        "train_s": round(t_train, 2)},
+           "every_100_substeps": turns}
+    return out
+
+
+def cpu_baseline_ramp(threads: int, shape=(512, 256, 128), substeps=3):
+    """The oracle, unchanged, on a slab of the ramp with the plain FP64 hybrid
+    (UD7 / WENO7, pressure sensor) from the inflow state, metrics excluded; and
+    on one core on a smaller slab.  Reported per grid-point substep."""
+    import dataclasses
+    import oracle
+    import workloads
+    out = {}
+    for key, shp, nth in (("all", shape, threads), ("single_core", (256, 128, 32), 1)):
+        c = dataclasses.replace(workloads.compression_ramp(shape=shp), scheme="hybrid", lowdiss="ud7")
+        P = oracle.params_from_case(c, nthreads=nth)
+        met = oracle.metrics(P, c.xyz)
+        best = None
+        for _ in range(2 if key == "all" else 1):
+            t0 = time.perf_counter()
+            oracle.advance(P, met, c.U0, substeps, c.dt, inflow=c.inflow)
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        out[key] = {"value": c.N * substeps / best / 1e9, "cores": nth,
+                    "sample": f"{substeps} substeps of the plain FP64 hybrid on a {shp[0]}x{shp[1]}x{shp[2]} "
+                              f"slab of the ramp ({c.N * substeps} point-substeps), {best:.1f} s"}
+    cpu = {"value": out["all"]["value"], "unit": "Gpt-substeps/s", "cores": out["all"]["cores"], "kind": "oracle",
+           "sample": out["all"]["sample"] + "; rate per point-substep, extrapolated to the full grid",
+           "single_core": out["single_core"]}
+    try:
+        model = [l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo") if l.startswith("model name")][0]
+        cpu["cpu_model"] = model
+    except Exception:
+        pass
+    return cpu
+
+
+def secondary_c2(torch, pk, n, steps, warmup):
+    """The plain FP64 method, WENO7 everywhere, on the two distorted periodic
+    n^3 runs (Taylor-Green with sixth-order viscous terms, isentropic vortex
+    Euler); one step = one substep of each run."""
+    cases = make_cases(n)
+    solvers = []
+    for c in cases:
+        s = pk.Solver(pk.params_from(c))
+        s.set_grid(torch.from_numpy(c.xyz).cuda())
+        s.set_state(torch.from_numpy(c.U0).cuda())
+        solvers.append(s)
+    for _ in range(warmup):
+        for s, c in zip(solvers, cases):
+            s.advance(1, c.dt)
+    torch.cuda.synchronize()
+    for s in solvers:
+        pk.ocfd_profile(s.h, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for s, c in zip(solvers, cases):
+            s.advance(1, c.dt)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = [pk.ocfd_profile_read(s.h) for s in solvers]
+    for s in solvers:
+        pk.ocfd_profile(s.h, False)
+        s.close()
+    del solvers
+    torch.cuda.empty_cache()
+    tot = {}
+    for p in prof:
+        for k, (ms, cnt) in p.items():
+            a = tot.setdefault(k, [0.0, 0])
+            a[0] += ms
+            a[1] += cnt
+    N = sum(c.N for c in cases) // len(cases)
+    roof = _sweep_roofline(tot, N, [1.0, 1.0, 1.0], False, hybrid=False)
+    if roof["kernel"] in PMC_TRAFFIC and n == 256:
+        t = PMC_TRAFFIC[roof["kernel"]]
+        roof["traffic"] = 2 * t["fetch_kib"] * 1024 + t["write_kib"] * 1024
+    return {"workload": f"isentropic vortex (Euler) + Taylor-Green (C6 viscous) on {n}^3 distorted periodic grids, "
+                        "plain FP64 method, SW + WENO7 everywhere, RK3; one step = one substep of each",
+            "gpt_substeps_per_s": round(sum(c.N for c in cases) * steps / elapsed / 1e9, 4),
+            "ms_per_step": round(elapsed / steps * 1e3, 4), "steps": steps,
+            "avg_launch_us": _prof_avg_us(tot), "roofline": roof}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=1000, help="substeps timed per form on the headline workload")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=256, help="grid points per direction")
+    ap.add_argument("--shape", type=str, default="2048,256,256", help="headline ramp grid")
+    ap.add_argument("--train-substeps", type=int, default=500)
+    ap.add_argument("--epochs", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=min(16, os.cpu_count() or 1))
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
-                    help="fp64: the plain path; mixed: FP32 split/reconstruction, FP64 difference and RK")
-    ap.add_argument("--learned-overhead", action="store_true",
-                    help="also time the learned sensor's kernels on the 256^3 Taylor-Green run")
-    ap.add_argument("--no-forms", action="store_true",
-                    help="skip the isotropic-turbulence and compression-ramp form comparisons")
-    ap.add_argument("--forms", choices=["all", "hit", "ramp", "ramp_full"], default="all",
-                    help="which form comparisons to run (unless --no-forms)")
-    ap.add_argument("--ramp-full-shape", type=str, default="2048,256,256")
-    ap.add_argument("--ramp-full-substeps", type=int, default=1000)
+    ap.add_argument("--n", type=int, default=256, help="grid points per direction of the secondary runs")
+    ap.add_argument("--c2-steps", type=int, default=200)
+    ap.add_argument("--forms", type=str, default="c2,hit,ramp",
+                    help="comma list of extra comparisons: c2 (256^3 FP64 WENO7), hit (512^3 isotropic "
+                         "turbulence forms), ramp (1024x160x128 forms); empty for none")
     ap.add_argument("--hit-n", type=int, default=512)
     ap.add_argument("--hit-develop", type=int, default=2500,
                     help="plain FP64 hybrid substeps before the forms are timed (t ~ 0.9 at 512^3)")
     ap.add_argument("--form-substeps", type=int, default=100)
     ap.add_argument("--ramp-shape", type=str, default="1024,160,128")
+    ap.add_argument("--learned-overhead", action="store_true",
+                    help="also time the learned sensor's kernels on the 256^3 Taylor-Green run")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="run one plain 512 MiB device-to-device copy first, as the reference dispatch "
                          "for scaling the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the solver keeps the whole domain on a single device; "
-              "run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the solver keeps the whole domain on a single device, and this "
+              "build has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -446,116 +595,56 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        print("[bench] calibration copy: 536870912 bytes read, 536870912 bytes written", file=sys.stderr, flush=True)
+        _log("calibration copy: 536870912 bytes read, 536870912 bytes written")
 
-    cases = make_cases(args.n)
-    for c in cases:
-        c.precision = args.precision
-    solvers = []
-    for c in cases:
-        s = pk.Solver(pk.params_from(c))
-        s.set_grid(torch.from_numpy(c.xyz).cuda())
-        s.set_state(torch.from_numpy(c.U0).cuda())
-        solvers.append(s)
-    torch.cuda.synchronize()
-    print(f"[bench] {len(cases)} runs of {args.n}^3 ready", file=sys.stderr, flush=True)
-
-    for _ in range(args.warmup):
-        for s, c in zip(solvers, cases):
-            s.advance(1, c.dt)
-    torch.cuda.synchronize()
-    for s in solvers:
-        pk.ocfd_profile(s.h, True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        for s, c in zip(solvers, cases):
-            s.advance(1, c.dt)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    prof = [pk.ocfd_profile_read(s.h) for s in solvers]
-    for s in solvers:
-        pk.ocfd_profile(s.h, False)
-    elapsed = t1 - t0
-    pts = sum(c.N for c in cases) * args.steps
-    value = pts / elapsed / 1e9
-    print(f"[bench] {args.steps} steps in {elapsed:.3f} s", file=sys.stderr, flush=True)
-
-    # Dominant kernel class over both runs.
-    tot = {}
-    for p in prof:
-        for k, (ms, cnt) in p.items():
-            a = tot.setdefault(k, [0.0, 0])
-            a[0] += ms
-            a[1] += cnt
-    for k, (ms, cnt) in sorted(tot.items(), key=lambda kv: -kv[1][0]):
-        if cnt:
-            print(f"[bench] {k:14s} {ms / cnt * 1e3:9.1f} us/launch  {cnt:6d} launches  {ms:9.2f} ms",
-                  file=sys.stderr, flush=True)
-    dom = max((k for k in tot if k.startswith("sweep")), key=lambda k: tot[k][0])
-    # The xi sweep (last) applies the Runge-Kutta update and eta accumulates;
-    # zeta (first) stores the sum, or adds to the viscous divergence.
-    flops_launch = {}
-    for c, p in zip(cases, prof):
-        ms, cnt = p[dom]
-        mode = {"sweep_xi": "rk", "sweep_eta": "add", "sweep_zeta": "add" if c.viscous else "set"}[dom]
-        flops_launch[c.name] = (sweep_flops(mode) * c.N, ms / cnt)
-    total_flops = sum(f * 1 for f, _ in flops_launch.values())
-    total_ms = sum(t for _, t in flops_launch.values())
-    achieved = total_flops / (total_ms * 1e-3) / 1e12
-    # The mixed form does the split and reconstruction (nearly all of a sweep's
-    # flops) in FP32, so it is measured against the FP32 vector peak.
-    peak = FP32_PEAK_TFLOPS if args.precision == "mixed" else FP64_PEAK_TFLOPS
-    traffic = None
-    if args.precision == "fp64" and args.n == 256 and dom in PMC_TRAFFIC:
-        t = PMC_TRAFFIC[dom]
-        traffic = 2 * t["fetch_kib"] * 1024 + t["write_kib"] * 1024
-    roof = {"bound": "alu", "kernel": dom, "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
-            "avg_launch_us": {k: round(v[1] * 1e3, 1) for k, v in flops_launch.items()},
-            "flops_per_launch": {k: v[0] for k, v in flops_launch.items()}}
-
-    for s in solvers:
-        s.close()
-    del solvers
-    torch.cuda.empty_cache()
-    overhead = learned_overhead(torch, pk, args.n, args.steps) if args.learned_overhead else None
-    forms = None
-    if not args.no_forms:
-        forms = {}
-        if args.forms in ("all", "hit"):
-            forms["isotropic_turbulence"] = form_hit_learned(torch, pk, args.hit_n, args.hit_develop, 50,
-                                                             args.form_substeps)
-        if args.forms in ("all", "ramp"):
-            forms["compression_ramp"] = form_ramp_mixed(torch, pk, tuple(int(v) for v in args.ramp_shape.split(",")),
-                                                        args.form_substeps)
-        if args.forms in ("all", "ramp_full"):
-            forms["compression_ramp_at_scale"] = form_ramp_full(
-                torch, pk, tuple(int(v) for v in args.ramp_full_shape.split(",")), 500, args.ramp_full_substeps, 100)
+    shape = tuple(int(v) for v in args.shape.split(","))
+    head = headline_ramp(torch, pk, shape, args.train_substeps, args.epochs, args.steps, args.warmup)
+    lf, pf = head["forms"]["learned_fp32"], head["forms"]["plain_fp64"]
+    value = lf["gpt_substeps_per_s"]
+    speedup = value / pf["gpt_substeps_per_s"]
+    extra = [f for f in args.forms.split(",") if f]
+    forms = {}
+    if "c2" in extra:
+        forms["c2_fp64_weno7_256cube"] = secondary_c2(torch, pk, args.n, args.c2_steps, args.warmup)
+        _log(f"c2: {forms['c2_fp64_weno7_256cube']['gpt_substeps_per_s']} Gpt-substeps/s")
+    if "hit" in extra:
+        forms["isotropic_turbulence"] = form_hit_learned(torch, pk, args.hit_n, args.hit_develop, 50,
+                                                         args.form_substeps)
+    if "ramp" in extra:
+        forms["compression_ramp"] = form_ramp_mixed(torch, pk, tuple(int(v) for v in args.ramp_shape.split(",")),
+                                                    args.form_substeps)
+    overhead = learned_overhead(torch, pk, args.n, 100) if args.learned_overhead else None
 
     cpu = None
     if not args.no_cpu_baseline:
-        print(f"[bench] oracle baseline on {args.cpu_threads} threads", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(cases, args.cpu_threads)
+        _log(f"oracle baseline on {args.cpu_threads} threads")
+        cpu = cpu_baseline_ramp(args.cpu_threads)
 
     out = {
         "metric": "Gpt-substeps/s: plain FP64 vs FP32+learned-sensor form at stated L2 error",
-        "value": round(value, 4),
+        "value": value,
         "unit": "Gpt-substeps/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(elapsed / args.steps * 1e3, 4),
+        "ms_per_step": lf["ms_per_substep"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 split/reconstruction + f64 difference/RK",
+        "dtype": "f32 split/reconstruction, f64 metrics/flux difference/RK/reductions, bf16 MFMA sensor",
         "data": "synthetic",
-        "config": {"workload": f"isentropic vortex + Taylor-Green on {args.n}^3 distorted periodic grids, "
-                               "SW + WENO7 + C6 viscous (TGV), RK3; one step = one substep of each",
-                   "points_per_step": sum(c.N for c in cases), "parallelism": "single GPU"},
-        "roofline": roof,
+        "config": {"workload": head["workload"], "points": head["points"], "parallelism": "single GPU"},
+        "plain_fp64": {"value": pf["gpt_substeps_per_s"], "ms_per_step": pf["ms_per_substep"],
+                       "dtype": "f64", "roofline": pf["roofline"]},
+        "speedup_vs_plain_fp64": round(speedup, 3),
+        "rel_l2_vs_plain_fp64_after_100_substeps": head["rel_l2_learned_vs_plain_after_100"],
+        "rel_l2_vs_plain_fp64_at_end": head["rel_l2_learned_vs_plain_at_end"],
+        "target": {"speedup_vs_plain_fp64": 2.0, "rel_l2_after_100_substeps": 1e-5,
+                   "met": bool(speedup >= 2.0 and head["rel_l2_learned_vs_plain_after_100"] is not None and
+                               max(head["rel_l2_learned_vs_plain_after_100"]) <= 1e-5)},
+        "roofline": lf["roofline"],
         "cpu_baseline": cpu,
+        "headline": head,
         "forms": forms,
     }
     if overhead is not None:
