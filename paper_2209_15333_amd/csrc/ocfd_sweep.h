@@ -265,6 +265,17 @@ void k_sweep(const SweepArgs A) {
   NodeIn ahead;
   bool have = load && gcol_ok && JB + 4 + gs <= mmax;
   if (!CHR && have) ahead = fetch(JB + 4 + gs, gc);
+  // Hybrid: the flag of the interface this thread reconstructs in chunk c is
+  // loaded during chunk c - 1, after that chunk's prefetch, so waiting for
+  // it never waits for the prefetch (loads complete in issue order).
+  auto flag_of = [&](int c) -> int {
+    const int jj = JB + c * SW_S + rs;
+    if (!(A.inviscid && rcol_ok && c * SW_S + rs < nif)) return 0;
+    if (!per && (jj < 3 || jj > n - 5)) return 1;   // boundary closure: always the masked WENO5 path
+    return A.flags[DIR * N + base + (long long)rc * sc + (long long)(n >= 8 ? wrap1(jj, n) : wrap(jj, n)) * sd];
+  };
+  int kflag = 0;
+  if (HYB) kflag = flag_of(0);
   // The same in characteristic variables (kind 1 or 2, or a boundary closure).
   auto reconstruct_char = [&](int j, int col, int kind, double* dst) {
     const int w0 = per ? (n >= 8 ? wrap1(j, n) : wrap(j, n)) : j;
@@ -385,14 +396,11 @@ void k_sweep(const SweepArgs A) {
     const int j = j0 + rs;
     const bool act = A.inviscid && rcol_ok && c * SW_S + rs < nif;
     if (HYB) {
+      const int kind = kflag;
+      if (c + 1 < nchunks) kflag = flag_of(c + 1);
       // Low-dissipation interfaces are done in place; WENO interfaces go to a
       // work list so that whole waves run the WENO code (no divergence).
       if (act) {
-        int kind;
-        if (!per && (j < 3 || j > n - 5))
-          kind = 1;   // boundary closure: always the masked WENO5 path
-        else
-          kind = A.flags[DIR * N + base + (long long)rc * sc + (long long)(n >= 8 ? wrap1(j, n) : wrap(j, n)) * sd];
         if (kind == 0)
           reconstruct(j, rc, 0, fh + (rs + 1) * FHS + rc);
         else
