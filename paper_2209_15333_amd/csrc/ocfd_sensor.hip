@@ -49,55 +49,87 @@ __device__ __forceinline__ v4f mfma16(const v4bf& a, const v4bf& b, const v4f& c
 // the interface's stencil, nodes j-3 .. j+4 (W0 = -3, W1 = 4), or its two
 // nodes j, j+1 (W0 = 0, W1 = 1).
 // ---------------------------------------------------------------------------
-// Each thread marches one (xi, eta) column through a zeta segment keeping
-// theta of planes k+W0 .. k+W1 in registers; the xi and eta windows are read
-// from the plane (cached).  Positions outside a bounded line count as 0
-// (theta >= 0, so the maximum is the one over the nodes that exist).
+// A workgroup owns a 64 x 4 tile of (xi, eta) columns (ZMarch numbering) and
+// marches it along zeta through one segment.  Per plane it stages an LDS patch
+// of theta covering the tile widened by the window along xi and eta
+// ((64 + W1 - W0) x (4 + W1 - W0) values, read one plane ahead into
+// registers), from which each thread takes the xi and eta window maxima of
+// its column; the zeta window is a register window of the column's own
+// theta.  Positions outside a bounded line count as 0 (theta >= 0, so the
+// maximum is the one over the nodes that exist).
 template <int W0, int W1>
 __global__ __launch_bounds__(256) void k_plain_flags(const Geo g, const ZMarch zm, double theta1, double theta2,
                                                      int three_way, const double* __restrict__ theta,
                                                      uint8_t* __restrict__ flags) {
   constexpr int WN = W1 - W0 + 1;
-  int i, j, k0, k1;
-  if (!zmarch_column(zm, g.n, &i, &j, &k0, &k1)) return;
-  const int nz = g.n[2];
-  const bool pz = g.periodic[2];
-  const long long col = i + g.s[1] * j;
-  auto zval = [&](int k) {
-    if (pz) return theta[col + (long long)(nz >= 8 ? k + (k < 0 ? nz : 0) - (k >= nz ? nz : 0) : wrapn(k, nz)) * g.s[2]];
-    return (k < 0 || k >= nz) ? 0.0 : theta[col + (long long)k * g.s[2]];
-  };
-  // in-plane window maximum along d (0: xi, 1: eta) at position p of n
-  auto inplane = [&](long long id, int d, int p) {
-    const int n = g.n[d];
-    double mx = 0.0;
+  constexpr int PX = 64 + WN - 1, PY = 4 + WN - 1, NP = PX * PY;
+  constexpr int NPT = (NP + 255) / 256;   // patch values per thread
+  __shared__ double patch[NP];
+  const int per = gridDim.x / 8;
+  const int L = (blockIdx.x % 8) * per + blockIdx.x / 8;
+  if (L >= zm.ntx * zm.nty * zm.nseg) return;   // uniform over the workgroup
+  const int tx = L % zm.ntx, ty = (L / zm.ntx) % zm.nty, zs = L / (zm.ntx * zm.nty);
+  const int lx = threadIdx.x & 63, ly = threadIdx.x >> 6;
+  const int i = tx * 64 + lx, j = ty * 4 + ly;
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const bool own = i < nx && j < ny;
+  const int k0 = zs * zm.zseg;
+  const int k1 = min(nz, k0 + zm.zseg);
+  const bool px_ = g.periodic[0], py_ = g.periodic[1], pz = g.periodic[2];
+  const long long sz = g.s[2];
+  // this thread's patch entries: their in-plane offsets (-1: outside a bounded line)
+  long long poff[NPT];
 #pragma unroll
-    for (int o = W0; o <= W1; ++o) {
-      int q = p + o;
-      if (g.periodic[d]) {
-        q = n >= 8 ? q + (q < 0 ? n : 0) - (q >= n ? n : 0) : wrapn(q, n);
-      } else if (q < 0 || q >= n) {
-        continue;
-      }
-      mx = fmax(mx, theta[id + (long long)(q - p) * g.s[d]]);
+  for (int q = 0; q < NPT; ++q) {
+    const int v = threadIdx.x + 256 * q;
+    poff[q] = -1;
+    if (v < NP) {
+      int gx = tx * 64 + W0 + v % PX, gy = ty * 4 + W0 + v / PX;
+      bool ok = true;
+      if (px_) gx = wrapn(gx, nx); else ok = ok && gx >= 0 && gx < nx;
+      if (py_) gy = wrapn(gy, ny); else ok = ok && gy >= 0 && gy < ny;
+      if (ok) poff[q] = gx + (long long)nx * gy;
     }
-    return mx;
+  }
+  auto patch_load = [&](double* r, int k) {
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) r[q] = poff[q] >= 0 ? theta[poff[q] + (long long)k * sz] : 0.0;
+  };
+  const long long col = own ? i + (long long)nx * j : 0;
+  auto zval = [&](int k) {
+    if (!own) return 0.0;
+    if (pz) return theta[col + (long long)(nz >= 8 ? k + (k < 0 ? nz : 0) - (k >= nz ? nz : 0) : wrapn(k, nz)) * sz];
+    return (k < 0 || k >= nz) ? 0.0 : theta[col + (long long)k * sz];
   };
   double w[WN];
 #pragma unroll
   for (int o = 0; o < WN - 1; ++o) w[o] = zval(k0 + W0 + o);
+  double nxt[NPT];
+  patch_load(nxt, k0);
+  auto flag = [&](double mx) -> uint8_t { return mx <= theta1 ? 0 : ((three_way && mx > theta2) ? 2 : 1); };
   for (int k = k0; k < k1; ++k) {
-    w[WN - 1] = zval(k + W1);
-    const long long id = col + (long long)k * g.s[2];
-    double mz = 0.0;
 #pragma unroll
-    for (int o = 0; o < WN; ++o) mz = fmax(mz, w[o]);
-    auto flag = [&](double mx) -> uint8_t { return mx <= theta1 ? 0 : ((three_way && mx > theta2) ? 2 : 1); };
-    flags[id] = flag(inplane(id, 0, i));
-    flags[g.N + id] = flag(inplane(id, 1, j));
-    flags[2 * g.N + id] = flag(mz);
+    for (int q = 0; q < NPT; ++q)
+      if (threadIdx.x + 256 * q < NP) patch[threadIdx.x + 256 * q] = nxt[q];
+    w[WN - 1] = zval(k + W1);
+    __syncthreads();
+    if (k + 1 < k1) patch_load(nxt, k + 1);
+    if (own) {
+      double mx = 0.0, my = 0.0, mz = 0.0;
+#pragma unroll
+      for (int o = 0; o < WN; ++o) {
+        mx = fmax(mx, patch[(ly - W0) * PX + lx + o]);
+        my = fmax(my, patch[(ly + o) * PX + lx - W0]);
+        mz = fmax(mz, w[o]);
+      }
+      const long long id = col + (long long)k * sz;
+      flags[id] = flag(mx);
+      flags[g.N + id] = flag(my);
+      flags[2 * g.N + id] = flag(mz);
+    }
 #pragma unroll
     for (int o = 0; o < WN - 1; ++o) w[o] = w[o + 1];
+    __syncthreads();
   }
 }
 
@@ -115,10 +147,13 @@ hipError_t launch_plain_flags(const Geo& g, const Phys& ph, const double* theta,
 // ---------------------------------------------------------------------------
 // Node features [4][N]: Delta div(u)/c and Delta |curl u|/c (Delta = (1/J)^(1/3),
 // the local cell size), and the pressure and density jumps: the normalised
-// second differences summed over the three directions,
-//   sum_d |q- - 2q + q+| / (q- + 2q + q+),
-// divided by the sensor threshold theta1 (so the pressure feature is the plain
-// sensor's node value in units of its threshold).  Velocity derivatives:
+// first differences across the node summed over the three directions,
+//   sum_d |q+ - q-| / (q+ + q-),
+// divided by the sensor threshold theta1 (a jump, not the plain sensor's
+// second difference: the label the network learns is not one of its
+// inputs); with the CURV inputs the normalised second differences
+//   sum_d |q- - 2q + q+| / (q- + 2q + q+) / theta1
+// instead (the plain sensor's own node value, eq 42).  Velocity derivatives:
 // second-order central differences (one-sided over one spacing at the end of
 // a bounded line), chain rule with the node metrics.  A bounded direction adds
 // no jump term at its end nodes.
@@ -186,7 +221,10 @@ __global__ __launch_bounds__(256) void k_features(const Geo g, const ZMarch zm, 
       dvd[a][1] = (yp[a + 1] - ym[a + 1]) * isy;
       dvd[a][2] = (zp1[a + 1] - zm1[a + 1]) * isz;
     }
-    auto jump = [](double m, double c, double pl) { return fabs(-m + 2.0 * c - pl) / (m + 2.0 * c + pl); };
+    const bool curv = ph.curv_inputs;
+    auto jump = [&](double m, double c, double pl) {
+      return curv ? fabs(-m + 2.0 * c - pl) / (m + 2.0 * c + pl) : fabs(pl - m) / (pl + m);
+    };
     double jp = 0.0, jr = 0.0;
     if (!endx) { jp += jump(xm[4], z0[4], xp[4]); jr += jump(xm[0], z0[0], xp[0]); }
     if (!endy) { jp += jump(ym[4], z0[4], yp[4]); jr += jump(ym[0], z0[0], yp[0]); }
@@ -301,7 +339,7 @@ __device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + __expf(
 // Learned flags of every interface: x of interface (d, node) = the four
 // features of the 8 nodes j-3 .. j+4 along d, node-major.
 __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const uint2* __restrict__ feat,
-                                                   const float* __restrict__ P, float tau,
+                                                   const float* __restrict__ P, const Tau3 tau,
                                                    uint8_t* __restrict__ flags) {
   MlpRegs R;
   load_mlp(P, R);
@@ -355,13 +393,13 @@ __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const uint2* __r
       __builtin_memcpy(&x, cur.xv, 16);
       Fwd F;
       mlp_forward(R, x, F);
-      if (cur.ok && gg == 0) flags[d * N + cur.id] = (!cur.inside || sigmoidf(F.z) >= tau) ? 1 : 0;
+      if (cur.ok && gg == 0) flags[d * N + cur.id] = (!cur.inside || sigmoidf(F.z) >= tau.t[d]) ? 1 : 0;
       cur = nxt;
     }
   }
 }
 
-hipError_t launch_mlp_flags(const Geo& g, const uint16_t* feat, const float* P, float tau, uint8_t* flags,
+hipError_t launch_mlp_flags(const Geo& g, const uint16_t* feat, const float* P, const Tau3& tau, uint8_t* flags,
                             hipStream_t st) {
   hipLaunchKernelGGL(k_mlp_flags, dim3(2048), dim3(256), 0, st, g, (const uint2*)feat, P, tau, flags);
   return hipGetLastError();
@@ -438,7 +476,7 @@ __global__ __launch_bounds__(GT) void k_mlp_grad(const uint16_t* __restrict__ X,
     Fwd F;
     mlp_forward(R, x, F);
     const float p = sigmoidf(F.z);
-    const float ys = (float)y[si];
+    const float ys = (float)(y[si] & 1);   // bit 0: label (bits 1-2 of collected samples: direction)
     const float ws = ok ? w[si] : 0.f;
     const float dz = ws * (p - ys) / Wsum;
     if (gg == 0) loss += -ws * (ys * __logf(p + 1e-12f) + (1.f - ys) * __logf(1.f - p + 1e-12f)) / Wsum;
@@ -664,7 +702,7 @@ __global__ __launch_bounds__(CT) void k_collect_write(const Geo g, const uint8_t
           xs[t] = feat[id + (long long)(wrapn(pos[d] + t - 3, g.n[d]) - pos[d]) * g.s[d]];  // window inside
         uint2* dst = (uint2*)(X + o * 32);
         for (int t = 0; t < 8; ++t) dst[t] = xs[t];
-        y[o] = flags[k] ? 1 : 0;
+        y[o] = (uint8_t)((flags[k] ? 1 : 0) | (d << 1));   // label, and the direction for calibration
         w[o] = 1.f;
       }
     }
