@@ -59,6 +59,10 @@ extern "C" {
 #define OCFD_PREC_FP64 0
 #define OCFD_PREC_MIXED 1
 
+/* Pressure and density features of the learned sensor (ocfd_params.sensor_inputs). */
+#define OCFD_INPUTS_JUMP 0
+#define OCFD_INPUTS_CURV 1
+
 /* Shock sensor of the hybrid scheme. */
 #define OCFD_SENSOR_PLAIN 0    /* modified Jameson pressure sensor, eq 42-43 */
 #define OCFD_SENSOR_LEARNED 1  /* perceptron on local flow features (ocfd_sensor_* below) */
@@ -158,7 +162,10 @@ typedef struct ocfd_params {
   int32_t flag_window;     /* plain sensor, how node values of theta decide interface j+1/2 (eq 43 applies
                               theta "at positions"): 0: the maximum over the nodes j-3 .. j+4 of its
                               stencil; 1: the maximum of theta_j and theta_j+1 */
-  int32_t reserved0;       /* must be 0 */
+  int32_t sensor_inputs;   /* learned sensor, the pressure and density features of a node:
+                              OCFD_INPUTS_JUMP: normalised first differences across the node;
+                              OCFD_INPUTS_CURV: the plain sensor's normalised second differences
+                              (eq 42), so its own value is among the inputs */
   double cfl_max;          /* > 0: CFL limit of the state check (the CFL number as OCFD_RED_CFL);
                               0: no CFL check */
 } ocfd_params;
@@ -282,9 +289,11 @@ const char* ocfd_kernel_name(int32_t kernel_class);
    A perceptron 32 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid) maps, for interface
    j+1/2 along a direction, four features of each of the 8 nodes j-3..j+4
    (Delta div u / c and Delta |curl u| / c with Delta = (1/J)^(1/3); the
-   pressure and the density jump, each the normalised second difference
-   |q- - 2q + q+| / (q- + 2q + q+) summed over the three directions and divided
-   by theta1) to the probability that the interface needs WENO.  It replaces
+   pressure and the density jump summed over the three directions and divided
+   by theta1, each the normalised first difference |q+ - q-| / (q+ + q-)
+   across the node, or with sensor_inputs = OCFD_INPUTS_CURV the normalised
+   second difference |q- - 2q + q+| / (q- + 2q + q+) of eq 42) to the
+   probability that the interface needs WENO.  It replaces
    the pressure sensor of eq 42-43 in the hybrid scheme: an interface takes
    WENO7 iff p >= tau.  Inference and training run on bf16 matrix cores with
    FP32 accumulation and FP32 master weights.  Parameters: one flat FP32 array
@@ -298,15 +307,22 @@ const char* ocfd_kernel_name(int32_t kernel_class);
 int32_t ocfd_sensor_nparams(void);
 int ocfd_sensor_set_params(ocfd_solver* s, const float* params_host);
 int ocfd_sensor_get_params(ocfd_solver* s, float* params_host);
-/* Decision threshold tau (default 0.5; ocfd_sensor_calibrate sets it). */
+/* Decision thresholds tau_d of the interfaces of direction d (default 0.5):
+   set_threshold gives all three directions the same value in [0, 1];
+   ocfd_sensor_calibrate sets them per direction; set_thresholds and
+   get_thresholds copy tau_host[3] in and out.  Errors: BADARG (null pointer,
+   a value outside [0, 1]). */
 int ocfd_sensor_set_threshold(ocfd_solver* s, double tau);
+int ocfd_sensor_set_thresholds(ocfd_solver* s, const double* tau_host);
+int ocfd_sensor_get_thresholds(ocfd_solver* s, double* tau_host);
 /* Flags [3][N] of the state U_dev by the plain sensor (0 low-dissipation,
    1 WENO7, 2 WENO5 when three_way) or by the network (0 / 1), written to
    flags_dev.  Errors: STATE (network not set). */
 int ocfd_sensor_flags(ocfd_solver* s, const double* U_dev, int32_t which, uint8_t* flags_dev);
 /* Caller-owned device buffer for training samples: each sample is 32 bf16
-   inputs, a label, a weight and bookkeeping, ocfd_sensor_sample_bytes(cap)
-   bytes for cap samples. */
+   inputs, a label byte (bit 0: WENO; bits 1-2: the interface's direction),
+   a weight and bookkeeping, ocfd_sensor_sample_bytes(cap) bytes for cap
+   samples. */
 size_t ocfd_sensor_sample_bytes(int64_t capacity);
 int ocfd_sensor_bind_samples(ocfd_solver* s, void* samples_dev, size_t bytes);
 /* Append samples from the current state labelled by the plain sensor: an
@@ -322,13 +338,15 @@ int ocfd_sensor_collect(ocfd_solver* s, uint64_t seed, double keep_weno, double 
    epoch, number of steps, training samples.  Synchronises. */
 int ocfd_sensor_train(ocfd_solver* s, int32_t epochs, int32_t batch, float lr, uint64_t seed, double holdout,
                       double* stats_host);
-/* Set tau from the held-out samples so that every held-out WENO interface is
-   kept: tau = margin * min probability over them.  out_host[4] = tau,
-   recall, false-positive rate, held-out samples.  Synchronises. */
+/* Set the thresholds from the held-out samples so that every held-out WENO
+   interface is kept: tau_d = margin * the least probability over the
+   held-out WENO samples of direction d (a direction with none takes the least
+   over all).  out_host[4] = the smallest tau_d, recall, false-positive rate,
+   held-out samples.  Synchronises. */
 int ocfd_sensor_calibrate(ocfd_solver* s, double holdout, double margin, double* out_host);
 /* Loss and gradient over n given samples with the current weights (no
    update): grad_host[nparams] then the loss.  X_dev: [n][32] bf16 bit
-   patterns.  Synchronises. */
+   patterns; y_dev: label bytes (bit 0 read); w_dev: weights.  Synchronises. */
 int ocfd_sensor_grad(ocfd_solver* s, const uint16_t* X_dev, const uint8_t* y_dev, const float* w_dev, int64_t n,
                      float* grad_host);
 /* Audit counters of the learned sensor since the solver started:

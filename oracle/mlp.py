@@ -6,10 +6,13 @@ stencil of flow features to the probability that an interface needs the
 WENO stencil.  This module holds, in plain numpy:
 
 * the node features: Delta * div(u) / c, Delta * |curl u| / c (Delta = (1/J)^(1/3),
-  the cell size), and the pressure and density jumps: normalised second
-  differences |q- - 2q + q+| / (q- + 2q + q+) summed over the three grid
-  directions, in units of the sensor threshold theta1; velocity derivatives
-  are second-order central differences mapped to x, y, z with the node metrics;
+  the cell size), and the pressure and density jumps: normalised first
+  differences |q+ - q-| / (q+ + q-) across the node, summed over the three
+  grid directions, in units of the sensor threshold theta1 (not the plain
+  sensor's second difference, so the label is not among the inputs), or
+  those second differences themselves (the "curv" inputs);
+  velocity derivatives are second-order central differences mapped to
+  x, y, z with the node metrics;
 * the interface input: the four features of the 8 nodes j-3 .. j+4 of the
   interface j+1/2, node-major;
 * the network 32 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid), its weighted
@@ -120,11 +123,14 @@ def adam_step(theta, m, v, g, t: int, lr: float, b1: float = 0.9, b2: float = 0.
 # ------------------------------------------------------------------ features
 
 def node_features(gamma: float, h, met: np.ndarray, U: np.ndarray, periodic=(1, 1, 1),
-                  theta1: float = 0.02) -> np.ndarray:
+                  theta1: float = 0.02, inputs: str = "jump") -> np.ndarray:
     """Node features [4, nz, ny, nx]: Delta div/c, Delta |curl|/c, and the
-    pressure and density jumps sum_d |q- - 2q + q+| / (q- + 2q + q+) divided
-    by theta1.  Along a bounded direction an end node takes a one-sided
-    velocity difference over one spacing and adds no jump term."""
+    pressure and density jumps sum_d |q+ - q-| / (q+ + q-) divided by theta1
+    (q+, q- the next and previous node along d); with inputs="curv" the
+    normalised second differences sum_d |q- - 2q + q+| / (q- + 2q + q+)
+    divided by theta1 instead (the plain sensor's node value, eq 42).  Along
+    a bounded direction an end node takes a one-sided velocity difference
+    over one spacing and adds no jump term."""
     rho = U[0]
     vel = [U[1] / rho, U[2] / rho, U[3] / rho]
     p = (gamma - 1.0) * (U[4] - 0.5 * rho * (vel[0] ** 2 + vel[1] ** 2 + vel[2] ** 2))
@@ -156,7 +162,10 @@ def node_features(gamma: float, h, met: np.ndarray, U: np.ndarray, periodic=(1, 
             dvd[a][d] = (vp - vm) / span
         for q, acc in ((p, jp), (rho, jr)):
             qp, qm, _, end = plus_minus(q, d)
-            acc += np.where(end, 0.0, np.abs(-qm + 2.0 * q - qp) / (qm + 2.0 * q + qp))
+            if inputs == "curv":
+                acc += np.where(end, 0.0, np.abs(-qm + 2.0 * q - qp) / (qm + 2.0 * q + qp))
+            else:
+                acc += np.where(end, 0.0, np.abs(qp - qm) / (qp + qm))
     grad = [[sum((met[3 * d + col] / jinv) * dvd[a][d] for d in range(3)) for col in range(3)] for a in range(3)]
     div = grad[0][0] + grad[1][1] + grad[2][2]
     wx = grad[2][1] - grad[1][2]

@@ -24,6 +24,7 @@ OCFD_SCHEME_WENO7, OCFD_SCHEME_HYBRID = 0, 1
 OCFD_LOWDISS_UD7, OCFD_LOWDISS_C8 = 0, 1
 OCFD_PREC_FP64, OCFD_PREC_MIXED = 0, 1
 OCFD_SENSOR_PLAIN, OCFD_SENSOR_LEARNED = 0, 1
+OCFD_INPUTS_JUMP, OCFD_INPUTS_CURV = 0, 1
 OCFD_BC_NONE, OCFD_BC_INFLOW, OCFD_BC_EXTRAP, OCFD_BC_WALL, OCFD_BC_NRBC = 0, 1, 2, 3, 4
 OCFD_PART_XI, OCFD_PART_ETA, OCFD_PART_ZETA, OCFD_PART_VISC, OCFD_PART_ALL = 1, 2, 4, 8, 15
 OCFD_RED_WENO0 = 9
@@ -49,7 +50,7 @@ class ocfd_params(ctypes.Structure):
         ("sensor", ctypes.c_int32), ("sensor_every", ctypes.c_int32), ("audit_every", ctypes.c_int32),
         ("three_way", ctypes.c_int32),
         ("characteristic", ctypes.c_int32), ("check_every", ctypes.c_int32),
-        ("flag_window", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("flag_window", ctypes.c_int32), ("sensor_inputs", ctypes.c_int32),
         ("cfl_max", ctypes.c_double),
     ]
 
@@ -106,6 +107,8 @@ def lib() -> ctypes.CDLL:
         L.ocfd_sensor_set_params.argtypes = [vp, fp]
         L.ocfd_sensor_get_params.argtypes = [vp, fp]
         L.ocfd_sensor_set_threshold.argtypes = [vp, ctypes.c_double]
+        L.ocfd_sensor_get_thresholds.argtypes = [vp, dp]
+        L.ocfd_sensor_set_thresholds.argtypes = [vp, dp]
         L.ocfd_sensor_flags.argtypes = [vp, vp, ctypes.c_int32, vp]
         L.ocfd_sensor_sample_bytes.argtypes = [ctypes.c_int64]
         L.ocfd_sensor_sample_bytes.restype = ctypes.c_size_t
@@ -268,6 +271,17 @@ def ocfd_sensor_set_threshold(h, tau: float):
     _check(h, lib().ocfd_sensor_set_threshold(h, tau), "ocfd_sensor_set_threshold")
 
 
+def ocfd_sensor_set_thresholds(h, tau):
+    arr = (ctypes.c_double * 3)(*[float(t) for t in tau])
+    _check(h, lib().ocfd_sensor_set_thresholds(h, arr), "ocfd_sensor_set_thresholds")
+
+
+def ocfd_sensor_get_thresholds(h):
+    out = (ctypes.c_double * 3)()
+    _check(h, lib().ocfd_sensor_get_thresholds(h, out), "ocfd_sensor_get_thresholds")
+    return list(out)
+
+
 def ocfd_sensor_flags(h, U: torch.Tensor, which: int, flags: torch.Tensor):
     if flags.dtype != torch.uint8:
         raise OcfdError("flags must be uint8")
@@ -344,6 +358,7 @@ def params_from(case, **overrides) -> ocfd_params:
     p.three_way = int(bool(getattr(case, "three_way", False)))
     p.characteristic = int(bool(getattr(case, "characteristic", False)))
     p.flag_window = int(getattr(case, "flag_window", 0))
+    p.sensor_inputs = OCFD_INPUTS_CURV if getattr(case, "sensor_inputs", "jump") == "curv" else OCFD_INPUTS_JUMP
     for k, v in overrides.items():
         setattr(p, k, v)
     return p

@@ -47,7 +47,7 @@ struct ocfd_solver {
   double* inflow = nullptr;       // [5][face] of the INFLOW face
   bool have_inflow = false;
   bool mlp_ready = false;
-  double tau = 0.5;
+  double tau[3] = {0.5, 0.5, 0.5};   // learned-sensor threshold per direction
   int adam_t = 0;
   long long substep = 0;
   double audit[6] = {0, 0, 0, 0, 0, 0};
@@ -126,7 +126,10 @@ bool valid_params(const ocfd_params* p, std::string* why, int* code = nullptr) {
   if (p->check_every < 0) { *why = "check_every must be >= 0"; return false; }
   if (p->flag_window != 0 && p->flag_window != 1) { *why = "flag_window must be 0 or 1"; return false; }
   if (!(p->cfl_max >= 0.0 && std::isfinite(p->cfl_max))) { *why = "cfl_max must be finite and >= 0"; return false; }
-  if (p->reserved0 != 0) { *why = "reserved0 must be 0"; return false; }
+  if (p->sensor_inputs != OCFD_INPUTS_JUMP && p->sensor_inputs != OCFD_INPUTS_CURV) {
+    *why = "unknown sensor_inputs";
+    return false;
+  }
   if (p->scheme == OCFD_SCHEME_HYBRID && p->sensor == OCFD_SENSOR_LEARNED && p->three_way) {
     // the network decides low-dissipation / WENO7 only; its audit fallback
     // could not tell the plain sensor's WENO5 tier apart
@@ -211,6 +214,7 @@ void geo_phys_of(const ocfd_params& p, Geo* geo, Phys* phys) {
   ph.theta2 = p.theta2;
   ph.three_way = p.three_way;
   ph.flag_window = p.flag_window;
+  ph.curv_inputs = p.sensor_inputs == OCFD_INPUTS_CURV;
   ph.vh = p.viscous == 8 ? 4 : 3;
   for (int d = 0; d < 3; ++d) {
     ph.h[d] = p.h[d];
@@ -311,6 +315,12 @@ bool ready(ocfd_solver* s, int* rc) {
   return true;
 }
 
+Tau3 tau3(const ocfd_solver* s) {
+  Tau3 t;
+  for (int d = 0; d < 3; ++d) t.t[d] = (float)s->tau[d];
+  return t;
+}
+
 // Node sensor theta of U into s->theta (the pressure of U into s->P first).
 int plain_theta(ocfd_solver* s, const double* U) {
   hipError_t e;
@@ -339,7 +349,7 @@ int learned_flags(ocfd_solver* s, const double* Ucur, bool count_substep) {
   if (!count_substep || k % every == 0) {
     Timed tm(s, OCFD_K_OTHER);
     e = launch_features(s->g, s->ph, Ucur, s->met, s->feat, s->st);
-    if (e == hipSuccess) e = launch_mlp_flags(s->g, s->feat, s->mlp, (float)s->tau, s->lflags, s->st);
+    if (e == hipSuccess) e = launch_mlp_flags(s->g, s->feat, s->mlp, tau3(s), s->lflags, s->st);
     if (e != hipSuccess) return hip_fail(s, e, "learned sensor kernels");
   }
   if (count_substep && s->p.audit_every > 0 && k % s->p.audit_every == 0) {
@@ -869,7 +879,24 @@ int ocfd_sensor_get_params(ocfd_solver* s, float* P) {
 int ocfd_sensor_set_threshold(ocfd_solver* s, double tau) {
   if (!s) return OCFD_ERR_BADARG;
   if (!(tau >= 0.0 && tau <= 1.0)) return fail(s, OCFD_ERR_BADARG, "threshold %g not in [0, 1]", tau);
-  s->tau = tau;
+  for (int d = 0; d < 3; ++d) s->tau[d] = tau;
+  return OCFD_OK;
+}
+
+int ocfd_sensor_set_thresholds(ocfd_solver* s, const double* tau_host) {
+  if (!s) return OCFD_ERR_BADARG;
+  if (!tau_host) return fail(s, OCFD_ERR_BADARG, "null thresholds");
+  for (int d = 0; d < 3; ++d)
+    if (!(tau_host[d] >= 0.0 && tau_host[d] <= 1.0))
+      return fail(s, OCFD_ERR_BADARG, "threshold %g of direction %d not in [0, 1]", tau_host[d], d);
+  for (int d = 0; d < 3; ++d) s->tau[d] = tau_host[d];
+  return OCFD_OK;
+}
+
+int ocfd_sensor_get_thresholds(ocfd_solver* s, double* tau_host) {
+  if (!s) return OCFD_ERR_BADARG;
+  if (!tau_host) return fail(s, OCFD_ERR_BADARG, "null output");
+  for (int d = 0; d < 3; ++d) tau_host[d] = s->tau[d];
   return OCFD_OK;
 }
 
@@ -886,7 +913,7 @@ int ocfd_sensor_flags(ocfd_solver* s, const double* U, int32_t which, uint8_t* f
   } else if (which == OCFD_SENSOR_LEARNED) {
     if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "no network parameters set");
     e = launch_features(s->g, s->ph, U, s->met, s->feat, s->st);
-    if (e == hipSuccess) e = launch_mlp_flags(s->g, s->feat, s->mlp, (float)s->tau, flags, s->st);
+    if (e == hipSuccess) e = launch_mlp_flags(s->g, s->feat, s->mlp, tau3(s), flags, s->st);
   } else {
     return fail(s, OCFD_ERR_BADARG, "unknown sensor %d", which);
   }
@@ -981,11 +1008,11 @@ int ocfd_sensor_train(ocfd_solver* s, int32_t epochs, int32_t batch, float lr, u
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
   if (e != hipSuccess) return hip_fail(s, e, "label download");
   long long npos = 0;
-  for (long long k = 0; k < ntrain; ++k) npos += hy[k] ? 1 : 0;
+  for (long long k = 0; k < ntrain; ++k) npos += hy[k] & 1;
   const long long nneg = ntrain - npos;
   const float wpos = (npos > 0 && nneg > 0) ? (float)std::min(1000.0, (double)nneg / (double)npos) : 1.f;
   std::vector<float> hw(ntrain);
-  for (long long k = 0; k < ntrain; ++k) hw[k] = hy[k] ? wpos : 1.f;
+  for (long long k = 0; k < ntrain; ++k) hw[k] = (hy[k] & 1) ? wpos : 1.f;
   e = hipMemcpyAsync(s->smp + smp_off_w(C), hw.data(), ntrain * sizeof(float), hipMemcpyHostToDevice, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
   if (e != hipSuccess) return hip_fail(s, e, "weight upload");
@@ -1047,18 +1074,30 @@ int ocfd_sensor_calibrate(ocfd_solver* s, double holdout, double margin, double*
   if (e == hipSuccess) e = hipMemcpyAsync(y.data(), s->smp + smp_off_y(C) + a, nh, hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
   if (e != hipSuccess) return hip_fail(s, e, "calibration");
-  double pmin = 1.0;
+  // per direction (bits 1-2 of the label byte): tau_d = margin * the least
+  // probability of a held-out WENO sample of direction d; a direction with
+  // none takes the least over all directions
+  double pmin[3] = {2.0, 2.0, 2.0}, pall = 2.0;
   long long npos = 0, nneg = 0;
-  for (long long k = 0; k < nh; ++k)
-    if (y[k]) { pmin = std::min(pmin, (double)p[k]); ++npos; } else { ++nneg; }
-  s->tau = npos ? margin * pmin : 0.5;
+  for (long long k = 0; k < nh; ++k) {
+    const int d = std::min(2, (int)(y[k] >> 1));
+    if (y[k] & 1) {
+      pmin[d] = std::min(pmin[d], (double)p[k]);
+      pall = std::min(pall, (double)p[k]);
+      ++npos;
+    } else {
+      ++nneg;
+    }
+  }
+  for (int d = 0; d < 3; ++d) s->tau[d] = npos ? margin * (pmin[d] <= 1.0 ? pmin[d] : pall) : 0.5;
   long long fp = 0, tp = 0;
   for (long long k = 0; k < nh; ++k) {
-    const bool on = p[k] >= (float)s->tau;
-    if (y[k] && on) ++tp;
-    if (!y[k] && on) ++fp;
+    const int d = std::min(2, (int)(y[k] >> 1));
+    const bool on = p[k] >= (float)s->tau[d];
+    if ((y[k] & 1) && on) ++tp;
+    if (!(y[k] & 1) && on) ++fp;
   }
-  out[0] = s->tau;
+  out[0] = std::min(s->tau[0], std::min(s->tau[1], s->tau[2]));
   out[1] = npos ? (double)tp / (double)npos : 1.0;
   out[2] = nneg ? (double)fp / (double)nneg : 0.0;
   out[3] = (double)nh;

@@ -104,6 +104,7 @@ struct Phys {
   double theta1, theta2;    // sensor thresholds (eq 43)
   int three_way;            // plain sensor marks max theta > theta2 with flag 2 (WENO5)
   int flag_window;          // plain sensor window of interface j+1/2: 0 nodes j-3 .. j+4; 1 nodes j, j+1
+  int curv_inputs;          // learned sensor: second differences (eq 42) as the jump features
   int vh;                   // half width of the interior viscous central stencil (3: sixth, 4: eighth order)
   double h[3], ih[3];       // computational spacing and its inverse
   double period[3];
@@ -175,7 +176,11 @@ int reduce_blocks(const Geo& g);
 hipError_t launch_plain_flags(const Geo& g, const Phys& ph, const double* theta, uint8_t* flags, hipStream_t st);
 hipError_t launch_features(const Geo& g, const Phys& ph, const double* U, const double* met, uint16_t* feat,
                            hipStream_t st);
-hipError_t launch_mlp_flags(const Geo& g, const uint16_t* feat, const float* P, float tau, uint8_t* flags,
+// Decision thresholds of the learned sensor, one per direction.
+struct Tau3 {
+  float t[3];
+};
+hipError_t launch_mlp_flags(const Geo& g, const uint16_t* feat, const float* P, const Tau3& tau, uint8_t* flags,
                             hipStream_t st);
 hipError_t launch_mlp_prob(const uint16_t* X, long long S, const float* P, float* prob, hipStream_t st);
 hipError_t launch_mlp_grad(const uint16_t* X, const uint8_t* y, const float* w, const int* idx, long long nb,

@@ -39,6 +39,7 @@ def test_params_struct_layout(ocfd):
     assert ctypes.sizeof(ocfd.ocfd_params) == 232
     assert ocfd.ocfd_params.characteristic.offset == 208
     assert ocfd.ocfd_params.check_every.offset == 212 and ocfd.ocfd_params.flag_window.offset == 216
+    assert ocfd.ocfd_params.sensor_inputs.offset == 220
     assert ocfd.ocfd_params.cfl_max.offset == 224
     assert ocfd.ocfd_params.bc.offset == 24 and ocfd.ocfd_params.period.offset == 48
     assert ocfd.ocfd_params.Tw.offset == 48 + 8 * 12 and ocfd.ocfd_params.viscous.offset == 48 + 8 * 16
@@ -59,7 +60,7 @@ def test_rejects_bad_parameters(ocfd):
     L = ocfd.lib()
     h = ctypes.c_void_p()
     for bad in (dict(nx=0), dict(gamma=1.0), dict(viscous=4), dict(scheme=7), dict(weno_eps=0.0), dict(Ma=-1.0),
-                dict(characteristic=2), dict(reserved0=1), dict(check_every=-1), dict(flag_window=2),
+                dict(characteristic=2), dict(sensor_inputs=2), dict(check_every=-1), dict(flag_window=2),
                 dict(cfl_max=-1.0), dict(cfl_max=float("inf"))):
         p = _params(ocfd, **bad)
         assert L.ocfd_create(ctypes.byref(p), None, ctypes.byref(h)) == -1, bad
@@ -136,6 +137,11 @@ def test_sensor_host_checks(ocfd):
     try:
         assert L.ocfd_sensor_set_threshold(h, ctypes.c_double(1.5)) == -1
         assert L.ocfd_sensor_set_threshold(h, ctypes.c_double(0.25)) == 0
+        t3 = (ctypes.c_double * 3)()
+        assert L.ocfd_sensor_get_thresholds(h, t3) == 0 and list(t3) == [0.25] * 3
+        assert L.ocfd_sensor_set_thresholds(h, (ctypes.c_double * 3)(0.1, 0.2, 1.5)) == -1
+        assert L.ocfd_sensor_set_thresholds(h, (ctypes.c_double * 3)(0.1, 0.2, 0.3)) == 0
+        assert L.ocfd_sensor_get_thresholds(h, t3) == 0 and list(t3) == [0.1, 0.2, 0.3]
         assert L.ocfd_sensor_bind_samples(h, ctypes.c_void_p(4096), 16 * 77 - 1) == -2
         assert L.ocfd_sensor_bind_samples(h, ctypes.c_void_p(4097), 10 ** 6) == -1
         out = (ctypes.c_double * 6)()

@@ -40,9 +40,10 @@ def test_bf16_rounding_definition():
 def test_features_closed_forms(orc):
     """Uniform flow: zero divergence, vorticity and jumps.  A shear u = a sin y:
     |curl| from the second-order difference of sin.  A density step along x:
-    the normalised second differences beside it.  The pressure feature times
-    theta1 is the plain sensor's node value (eq 42), computed independently by
-    the C oracle."""
+    the normalised first differences on both sides of it (and at the periodic
+    seam).  A pressure linear in x: the plain sensor (eq 42, computed by the
+    C oracle) is silent, the pressure jump is not: the feature is not the
+    label."""
     case = workloads.uniform_flow((12, 10, 8), amplitude_frac=0.0)
     P = orc.params_from_case(case)
     met = orc.metrics(P, case.xyz)
@@ -63,14 +64,25 @@ def test_features_closed_forms(orc):
     rho = np.where(np.arange(12)[None, None, :] >= 6, r, 1.0) * np.ones_like(x)
     U = workloads.conserved(1.4, rho, 0 * x, 0 * x, 0 * x, p)
     F = mlp.node_features(1.4, case.h, met, U, theta1=0.02)
-    assert F[3][0, 0, 5] == pytest.approx((r - 1) / (r + 3) / 0.02, rel=1e-14)
-    assert F[3][0, 0, 6] == pytest.approx((r - 1) / (3 * r + 1) / 0.02, rel=1e-14)
-    assert F[3][0, 0, 3] == 0.0 and np.all(F[2] == 0.0)
-    # pressure feature = plain sensor / theta1, on a noisy state
+    for node in (5, 6, 11, 0):
+        assert F[3][0, 0, node] == pytest.approx((r - 1) / (r + 1) / 0.02, rel=1e-14), node
+    assert F[3][0, 0, 3] == 0.0 and F[3][0, 0, 8] == 0.0 and np.all(F[2] == 0.0)
+    # linear pressure p = p0 (1 + e x) in the interior of x (away from the seam)
+    e = 0.01
+    pl = p * (1.0 + e * x)
+    U = workloads.conserved(1.4, np.ones_like(x), 0 * x, 0 * x, 0 * x, pl)
+    theta, _ = orc.sensor(P, U)
+    F = mlp.node_features(1.4, case.h, met, U, theta1=0.02)
+    hx = case.h[0]
+    xi = x[:, :, 1:-1]
+    assert np.allclose(F[2][:, :, 1:-1], e * hx / (1.0 + e * xi) / 0.02, rtol=1e-10)
+    assert np.abs(theta[:, :, 1:-1]).max() < 1e-13 and F[2][:, :, 1:-1].min() > 0.01
+    # the "curv" inputs: the pressure feature times theta1 is the plain
+    # sensor's node value, on a noisy state
     rng = np.random.default_rng(4)
     U = case.U0 * (1.0 + 0.05 * rng.standard_normal(case.U0.shape))
     theta, _ = orc.sensor(P, U)
-    F = mlp.node_features(1.4, case.h, met, U, theta1=case.theta1)
+    F = mlp.node_features(1.4, case.h, met, U, theta1=case.theta1, inputs="curv")
     assert np.allclose(F[2] * case.theta1, theta, rtol=1e-13, atol=1e-16)
 
 
@@ -78,9 +90,8 @@ def test_features_on_bounded_lines(orc):
     """Along a bounded direction the end nodes take a one-sided difference over
     one spacing (exact for linear fields) and add no jump term: u = a x,
     v = b x give div = a and |curl| = |b| at every node, ends included; a
-    density quadratic in y has a known normalised second difference inside
-    and none at the eta ends; the pressure feature still equals the plain
-    sensor of the C oracle."""
+    density quadratic in y has a known normalised first difference inside
+    and none at the eta ends."""
     nx, ny, nz = 12, 9, 4
     hh = (0.2, 0.3, 0.25)
     K, J, I = np.meshgrid(*[np.arange(n) * s for n, s in zip((nz, ny, nx), hh[::-1])], indexing="ij")
@@ -99,12 +110,14 @@ def test_features_on_bounded_lines(orc):
     assert np.allclose(F[0], delta * a / c, rtol=1e-12)
     assert np.allclose(F[1], delta * abs(b) / c, rtol=1e-12)
     y = J[:, 1:-1, :]
-    inner = 0.2 * hh[1] ** 2 / (4.0 * (1.0 + 0.1 * y * y) + 0.2 * hh[1] ** 2) / 0.02
+    # rho(y + h) - rho(y - h) = 0.4 y h;  rho(y + h) + rho(y - h) = 2 + 0.2 (y^2 + h^2)
+    inner = 0.4 * y * hh[1] / (2.0 + 0.2 * (y * y + hh[1] ** 2)) / 0.02
     assert np.allclose(F[3][:, 1:-1, :], inner, rtol=1e-10)
     assert np.all(F[3][:, 0, :] == 0.0) and np.all(F[3][:, -1, :] == 0.0)
+    assert np.abs(F[2]).max() < 1e-12   # uniform pressure, recovered from E with rounding
     rng = np.random.default_rng(6)
     U = U * (1.0 + 0.05 * rng.standard_normal(U.shape))
     theta, _ = orc.sensor(P, U)
-    F = mlp.node_features(1.4, hh, met, U, periodic=(0, 0, 1), theta1=case.theta1)
+    F = mlp.node_features(1.4, hh, met, U, periodic=(0, 0, 1), theta1=case.theta1, inputs="curv")
     assert np.allclose(F[2] * case.theta1, theta, rtol=1e-13, atol=1e-16)
     assert mlp.window_inside(nx, np.arange(nx), False).tolist() == [False] * 3 + [True] * (nx - 7) + [False] * 4

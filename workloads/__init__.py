@@ -61,6 +61,7 @@ class Case:
     sensor: str = "plain"                # hybrid: "plain" (pressure sensor) | "learned" (GPU only)
     sensor_every: int = 1
     audit_every: int = 0
+    sensor_inputs: str = "jump"          # learned sensor: "jump" (first differences) | "curv" (eq 42's)
 
     @property
     def N(self) -> int:
