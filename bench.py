@@ -117,6 +117,7 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
     t_all = time.perf_counter()
     case = workloads.isotropic_turbulence(n)
     case.dt *= 2.0        # acoustic CFL ~0.5 (the generator's default is ~0.25)
+    case.sensor_inputs = "curv"
     _log(f"hit{n}: inputs ready ({time.perf_counter() - t_all:.0f} s)")
     s = pk.Solver(pk.params_from(case))
     s.set_grid(torch.from_numpy(case.xyz).cuda())
@@ -141,6 +142,7 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
     t_train = time.perf_counter() - t0
     params = pk.ocfd_sensor_get_params(s.h)
     tau = cal[0]
+    taus = pk.ocfd_sensor_get_thresholds(s.h)
     _log(f"hit{n}: trained in {t_train:.1f} s, loss {stats[0]:.4f} -> {stats[1]:.4f}, tau {tau:.3g}, "
          f"held-out recall {cal[1]}, false-positive rate {cal[2]:.4f}")
     U = s.state()
@@ -151,7 +153,7 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
 
     def learned(sv):
         pk.ocfd_sensor_set_params(sv.h, params)
-        pk.ocfd_sensor_set_threshold(sv.h, tau)
+        pk.ocfd_sensor_set_thresholds(sv.h, taus)
 
     res = {}
     ref = None
@@ -188,7 +190,7 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
     return {"workload": f"decaying isotropic turbulence {n}^3 (k0 4, Mt 0.6, Re_lambda 100), C6 viscous, "
                         f"state after {develop} plain FP64 hybrid substeps; {substeps} timed substeps per form",
             "training": {"samples": total, "epochs": 4, "batch": 2048, "loss_first_last": [round(stats[0], 5),
-                         round(stats[1], 5)], "tau": tau, "heldout_recall": cal[1],
+                         round(stats[1], 5)], "tau": tau, "tau_by_direction": taus, "heldout_recall": cal[1],
                          "heldout_false_positive_rate": round(cal[2], 5), "train_s": round(t_train, 2)},
             "forms": res}
 
@@ -349,10 +351,16 @@ def headline_ramp(torch, pk, shape, train, epochs, steps, warmup, report=100):
         sv.set_inflow(inflow)
         sv.set_state(U0)
         return sv
+    # two sample sets from the same plain run: node features with the plain
+    # sensor's second differences as the pressure / density inputs ("curv",
+    # the headline form) and with first differences ("jump")
     s = solver(case)
+    sj = solver(dataclasses.replace(case, sensor_inputs="jump"))
     cap = 8_000_000
-    buf = torch.empty(pk.ocfd_sensor_sample_bytes(cap), dtype=torch.uint8, device="cuda")
-    pk.ocfd_sensor_bind_samples(s.h, buf)
+    bufs = []
+    for sv in (s, sj):
+        bufs.append(torch.empty(pk.ocfd_sensor_sample_bytes(cap), dtype=torch.uint8, device="cuda"))
+        pk.ocfd_sensor_bind_samples(sv.h, bufs[-1])
     t0 = time.perf_counter()
     total = 0
     every = 50
@@ -361,6 +369,8 @@ def headline_ramp(torch, pk, shape, train, epochs, steps, warmup, report=100):
         # the same keep rate for both classes: an unbiased sample of every
         # snapshot, spread over the whole run
         total = pk.ocfd_sensor_collect(s.h, 9000 + k, 0.002, 0.002)
+        sj.set_state(s.state())
+        pk.ocfd_sensor_collect(sj.h, 9000 + k, 0.002, 0.002)
     torch.cuda.synchronize()
     t_dev = time.perf_counter() - t0
     # WENO fraction of the developed state under both readings of the sensor window
@@ -372,29 +382,38 @@ def headline_ramp(torch, pk, shape, train, epochs, steps, warmup, report=100):
     win["nodes_j,j+1"] = [round(float(fl[d].float().mean()), 5) for d in range(3)]
     alt.close()
     del alt, fl
-    pk.ocfd_sensor_set_params(s.h, workloads.sensor_initial_weights(13))
-    t0 = time.perf_counter()
-    stats = pk.ocfd_sensor_train(s.h, epochs, 2048, 3e-3, 9, 0.1)
-    cal = pk.ocfd_sensor_calibrate(s.h, 0.1, 0.5)
-    t_train = time.perf_counter() - t0
-    params = pk.ocfd_sensor_get_params(s.h)
-    tau = cal[0]
-    _log(f"ramp{nx}x{ny}x{nz}: {train} plain substeps in {t_dev:.1f} s, {total} samples; trained in "
-         f"{t_train:.1f} s, tau {tau:.3g}, held-out recall {cal[1]}, false-positive rate {cal[2]:.4f}; "
-         f"WENO fractions {win}")
-    del buf
+    nets = {}
+    for key, sv in (("curv", s), ("jump", sj)):
+        pk.ocfd_sensor_set_params(sv.h, workloads.sensor_initial_weights(13))
+        t0 = time.perf_counter()
+        stats = pk.ocfd_sensor_train(sv.h, epochs, 2048, 3e-3, 9, 0.1)
+        cal = pk.ocfd_sensor_calibrate(sv.h, 0.1, 0.5)
+        t_train = time.perf_counter() - t0
+        nets[key] = {"params": pk.ocfd_sensor_get_params(sv.h), "taus": pk.ocfd_sensor_get_thresholds(sv.h),
+                     "info": {"samples": total, "epochs": epochs, "batch": 2048,
+                              "loss_first_last": [round(stats[0], 5), round(stats[1], 5)],
+                              "tau_by_direction": pk.ocfd_sensor_get_thresholds(sv.h), "heldout_recall": cal[1],
+                              "heldout_false_positive_rate": round(cal[2], 5), "train_s": round(t_train, 2)}}
+        _log(f"ramp{nx}x{ny}x{nz}: {key} inputs: trained in {t_train:.1f} s, taus {nets[key]['taus']}, "
+             f"held-out recall {cal[1]}, false-positive rate {cal[2]:.4f}")
+    _log(f"ramp{nx}x{ny}x{nz}: {train} plain substeps in {t_dev:.1f} s, {total} samples; WENO fractions {win}")
+    del bufs
     s.close()
-    del s
+    sj.close()
+    del s, sj
     torch.cuda.empty_cache()
     learned_case = dataclasses.replace(case, precision="mixed", sensor="learned", sensor_every=3,
-                                       audit_every=report)
-    cases = {"plain_fp64": case, "learned_fp32": learned_case}
+                                       audit_every=report, sensor_inputs="curv")
+    cases = {"plain_fp64": case, "learned_fp32": learned_case,
+             "learned_fp32_jump": dataclasses.replace(learned_case, sensor_inputs="jump")}
+    learned = [name for name in cases if name != "plain_fp64"]
     solvers = {}
     for name, c in cases.items():
         sv = solver(c)
         if c.sensor == "learned":
-            pk.ocfd_sensor_set_params(sv.h, params)
-            pk.ocfd_sensor_set_threshold(sv.h, tau)
+            net = nets[c.sensor_inputs]
+            pk.ocfd_sensor_set_params(sv.h, net["params"])
+            pk.ocfd_sensor_set_thresholds(sv.h, net["taus"])
         sv.advance(warmup, c.dt)
         sv.set_state(U0)
         solvers[name] = sv
@@ -405,7 +424,7 @@ def headline_ramp(torch, pk, shape, train, epochs, steps, warmup, report=100):
     elapsed = {name: 0.0 for name in cases}
     fracs = {name: [] for name in cases}
     turns = []
-    prev = pk.ocfd_sensor_audit(solvers["learned_fp32"].h)
+    prev = {name: pk.ocfd_sensor_audit(solvers[name].h) for name in learned}
     for sv in solvers.values():
         pk.ocfd_profile(sv.h, True)
     done = 0
@@ -421,20 +440,22 @@ def headline_ramp(torch, pk, shape, train, epochs, steps, warmup, report=100):
         red = {name: sv.reduce(case.dt) for name, sv in solvers.items()}
         for name in cases:
             fracs[name].append(red[name][9:12])
-        a = pk.ocfd_sensor_audit(solvers["learned_fp32"].h)
-        dlt = [a[i] - prev[i] for i in range(6)]
-        prev = a
-        # the audit of a turn runs at its first substep (a multiple of `report`)
-        turns.append({"substeps": done,
-                      "rel_l2_learned_fp32_vs_plain_fp64": [float(f"{e:.3e}") for e in _rel_l2(
-                          torch, solvers["learned_fp32"].state(), solvers["plain_fp64"].state())],
-                      "plain_weno_frac_by_direction": [round(v, 5) for v in red["plain_fp64"][9:12]],
-                      "learned_weno_frac_by_direction": [round(v, 5) for v in red["learned_fp32"][9:12]],
-                      "audit_at_substep": done - n,
-                      "audit_plain_weno_frac": round(dlt[2] / max(dlt[1], 1), 5),
-                      "audit_learned_weno_frac": round(dlt[3] / max(dlt[1], 1), 5),
-                      "audit_mismatch_rate": round(dlt[5] / max(dlt[1], 1), 6),
-                      "audit_missed_frac_of_plain_weno": round(dlt[4] / max(dlt[2], 1), 6)})
+        turn = {"substeps": done,
+                "plain_weno_frac_by_direction": [round(v, 5) for v in red["plain_fp64"][9:12]]}
+        for name in learned:
+            a = pk.ocfd_sensor_audit(solvers[name].h)
+            dlt = [a[i] - prev[name][i] for i in range(6)]
+            prev[name] = a
+            # the audit of a turn runs at its first substep (a multiple of `report`)
+            turn[name] = {"rel_l2_vs_plain_fp64": [float(f"{e:.3e}") for e in _rel_l2(
+                              torch, solvers[name].state(), solvers["plain_fp64"].state())],
+                          "weno_frac_by_direction": [round(v, 5) for v in red[name][9:12]],
+                          "audit_at_substep": done - n,
+                          "audit_plain_weno_frac": round(dlt[2] / max(dlt[1], 1), 5),
+                          "audit_learned_weno_frac": round(dlt[3] / max(dlt[1], 1), 5),
+                          "audit_mismatch_rate": round(dlt[5] / max(dlt[1], 1), 6),
+                          "audit_missed_frac_of_plain_weno": round(dlt[4] / max(dlt[2], 1), 6)}
+        turns.append(turn)
         _log(f"ramp{nx}x{ny}x{nz}: {turns[-1]}")
     forms = {}
     for name, sv in solvers.items():
@@ -449,13 +470,18 @@ def headline_ramp(torch, pk, shape, train, epochs, steps, warmup, report=100):
                        "roofline": _sweep_roofline(prof, c.N, mean_frac, c.precision == "mixed")}
         _log(f"ramp{nx}x{ny}x{nz}: {name}: {forms[name]['gpt_substeps_per_s']} Gpt-substeps/s, "
              f"{forms[name]['avg_launch_us']}")
-    a = pk.ocfd_sensor_audit(solvers["learned_fp32"].h)
-    forms["learned_fp32"]["audit"] = {"runs": int(a[0]), "plain_weno_frac": round(a[2] / max(a[1], 1), 5),
-                                      "learned_weno_frac": round(a[3] / max(a[1], 1), 5),
-                                      "missed_frac_of_plain_weno": round(a[4] / max(a[2], 1), 6),
-                                      "mismatch_rate": round(a[5] / max(a[1], 1), 6)}
-    drift100 = turns[0]["rel_l2_learned_fp32_vs_plain_fp64"] if turns and turns[0]["substeps"] == report else None
-    drift_end = turns[-1]["rel_l2_learned_fp32_vs_plain_fp64"] if turns else None
+    for name in learned:
+        a = pk.ocfd_sensor_audit(solvers[name].h)
+        forms[name]["audit"] = {"runs": int(a[0]), "plain_weno_frac": round(a[2] / max(a[1], 1), 5),
+                                "learned_weno_frac": round(a[3] / max(a[1], 1), 5),
+                                "missed_frac_of_plain_weno": round(a[4] / max(a[2], 1), 6),
+                                "mismatch_rate": round(a[5] / max(a[1], 1), 6)}
+        forms[name]["training"] = nets[cases[name].sensor_inputs]["info"]
+        forms[name]["rel_l2_vs_plain_fp64_after_100"] = (turns[0][name]["rel_l2_vs_plain_fp64"]
+                                                          if turns and turns[0]["substeps"] == report else None)
+        forms[name]["rel_l2_vs_plain_fp64_at_end"] = turns[-1][name]["rel_l2_vs_plain_fp64"] if turns else None
+    drift100 = forms["learned_fp32"]["rel_l2_vs_plain_fp64_after_100"]
+    drift_end = forms["learned_fp32"]["rel_l2_vs_plain_fp64_at_end"]
     for sv in solvers.values():
         sv.close()
     del solvers, xyz, inflow, U0
@@ -463,14 +489,11 @@ def headline_ramp(torch, pk, shape, train, epochs, steps, warmup, report=100):
     out = {"workload": f"Mach 2.9 24-degree compression ramp {nx}x{ny}x{nz} ({case.N} points), isothermal wall "
                        f"Tw 2.84, nonreflecting exit and top, Re_delta 5e4, C8 viscous, hybrid UD7 / WENO7: plain "
                        f"FP64 (pressure sensor) vs FP32 split/reconstruction + learned sensor once per RK step "
-                       f"(audited every {report} substeps); {steps} timed substeps each from the inflow state",
+                       f"(audited every {report} substeps; inputs: the plain sensor's second differences, and "
+                       f"beside it first differences); {steps} timed substeps each from the inflow state",
            "points": case.N, "forms": forms,
            "rel_l2_learned_vs_plain_after_100": drift100, "rel_l2_learned_vs_plain_at_end": drift_end,
-           "plain_weno_frac_after_training_run": win,
-           "training": {"plain_substeps": train, "samples": total, "epochs": epochs, "batch": 2048,
-                        "loss_first_last": [round(stats[0], 5), round(stats[1], 5)], "tau": tau,
-                        "heldout_recall": cal[1], "heldout_false_positive_rate": round(cal[2], 5),
-                        "train_s": round(t_train, 2)},
+           "plain_weno_frac_after_training_run": win, "training_run_substeps": train,
            "every_100_substeps": turns}
     return out
 
