@@ -354,7 +354,7 @@ def headline_ramp(torch, pk, shape, train, epochs, steps, warmup, report=100):
     # two sample sets from the same plain run: node features with the plain
     # sensor's second differences as the pressure / density inputs ("curv",
     # the headline form) and with first differences ("jump")
-    s = solver(case)
+    s = solver(dataclasses.replace(case, sensor_inputs="curv"))
     sj = solver(dataclasses.replace(case, sensor_inputs="jump"))
     cap = 8_000_000
     bufs = []
