@@ -286,7 +286,7 @@ int ocfd_profile_read(ocfd_solver* s, double* ms_host, int64_t* count_host);
 const char* ocfd_kernel_name(int32_t kernel_class);
 
 /* ---- Learned shock sensor ------------------------------------------------
-   A perceptron 32 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid) maps, for interface
+   A perceptron 32 -> 64 -> 64 -> 64 (ReLU each) -> 1 (sigmoid) maps, for interface
    j+1/2 along a direction, four features of each of the 8 nodes j-3..j+4
    (Delta div u / c and Delta |curl u| / c with Delta = (1/J)^(1/3); the
    pressure and the density jump summed over the three directions and divided
@@ -297,8 +297,8 @@ const char* ocfd_kernel_name(int32_t kernel_class);
    the pressure sensor of eq 42-43 in the hybrid scheme: an interface takes
    WENO7 iff p >= tau.  Inference and training run on bf16 matrix cores with
    FP32 accumulation and FP32 master weights.  Parameters: one flat FP32 array
-   of ocfd_sensor_nparams() values: W1 [32 inputs][32 units], b1 [32],
-   W2 [32][32], b2 [32], w3 [32], b3 [1].
+   of ocfd_sensor_nparams() = 10497 values: W1 [32 inputs][64 units],
+   b1 [64], W2 [64][64], b2 [64], W3 [64][64], b3 [64], w4 [64], b4 [1].
    On a bounded line the end nodes take a one-sided velocity difference over
    one spacing and add no jump term along that line; interfaces whose 8-node
    window leaves the grid (j < 3 or j > n-5) take the masked WENO5 closure
@@ -338,12 +338,16 @@ int ocfd_sensor_collect(ocfd_solver* s, uint64_t seed, double keep_weno, double 
    epoch, number of steps, training samples.  Synchronises. */
 int ocfd_sensor_train(ocfd_solver* s, int32_t epochs, int32_t batch, float lr, uint64_t seed, double holdout,
                       double* stats_host);
-/* Set the thresholds from the held-out samples so that every held-out WENO
-   interface is kept: tau_d = margin * the least probability over the
-   held-out WENO samples of direction d (a direction with none takes the least
-   over all).  out_host[4] = the smallest tau_d, recall, false-positive rate,
-   held-out samples.  Synchronises. */
-int ocfd_sensor_calibrate(ocfd_solver* s, double holdout, double margin, double* out_host);
+/* Set the thresholds from the held-out samples (the last `holdout` fraction
+   of the buffer): tau_d = margin * the k-th least probability over the
+   held-out WENO samples of direction d, k = floor(miss * their count) (a
+   direction with none takes the value over all directions).  miss = 0 keeps
+   every held-out WENO interface; miss > 0 lets that fraction of them fall
+   below the threshold before the margin is applied (the margin usually
+   keeps most of them).  0 < holdout < 1, 0 < margin <= 1, 0 <= miss < 0.5,
+   else OCFD_ERR_BADARG.  out_host[4] = the smallest tau_d, recall, false-
+   positive rate, held-out samples.  Synchronises. */
+int ocfd_sensor_calibrate(ocfd_solver* s, double holdout, double margin, double miss, double* out_host);
 /* Loss and gradient over n given samples with the current weights (no
    update): grad_host[nparams] then the loss.  X_dev: [n][32] bf16 bit
    patterns; y_dev: label bytes (bit 0 read); w_dev: weights.  Synchronises. */

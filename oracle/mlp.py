@@ -15,23 +15,26 @@ WENO stencil.  This module holds, in plain numpy:
   x, y, z with the node metrics;
 * the interface input: the four features of the 8 nodes j-3 .. j+4 of the
   interface j+1/2, node-major;
-* the network 32 -> 32 (ReLU) -> 32 (ReLU) -> 1 (sigmoid), its weighted
-  binary cross-entropy loss and the exact backward pass in FP64;
+* the network 32 -> 64 -> 64 -> 64 -> 1 (ReLU hidden layers, sigmoid
+  output), its weighted binary cross-entropy loss and the exact backward pass
+  in FP64;
 * the same forward/backward with values rounded to bfloat16 at the points
-  where the GPU kernels feed its matrix cores (inputs, weights of the two
-  hidden layers, hidden activations, back-propagated pre-activation
-  gradients), so the two can be compared on identical operands;
+  where the GPU kernels feed its matrix cores (inputs, weights of the three
+  hidden layers, the hidden activations entering layers 2 and 3, the
+  back-propagated pre-activation gradients), so the two can be compared on
+  identical operands;
 * the Adam update of the training loop.
 
-Parameters are one flat float array: W1 [32 in x 32 out] (row = input),
-b1 [32], W2 [32 x 32], b2 [32], w3 [32], b3 [1].
+Parameters are one flat float array: W1 [32 in x 64 out] (row = input),
+b1 [64], W2 [64 x 64], b2 [64], W3 [64 x 64], b3 [64], w4 [64], b4 [1].
 """
 from __future__ import annotations
 
 import numpy as np
 
-NIN, NH = 32, 32
-SIZES = [("W1", (NIN, NH)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)), ("w3", (NH,)), ("b3", (1,))]
+NIN, NH = 32, 64
+SIZES = [("W1", (NIN, NH)), ("b1", (NH,)), ("W2", (NH, NH)), ("b2", (NH,)), ("W3", (NH, NH)), ("b3", (NH,)),
+         ("w4", (NH,)), ("b4", (1,))]
 NPARAM = sum(int(np.prod(s)) for _, s in SIZES)
 
 
@@ -53,7 +56,8 @@ def init_params(seed: int = 0):
     rng = np.random.Generator(np.random.PCG64(seed))
     d = {"W1": rng.uniform(-1, 1, (NIN, NH)) * np.sqrt(6.0 / NIN), "b1": np.zeros(NH),
          "W2": rng.uniform(-1, 1, (NH, NH)) * np.sqrt(6.0 / NH), "b2": np.zeros(NH),
-         "w3": rng.uniform(-1, 1, NH) * np.sqrt(6.0 / NH) * 0.1, "b3": np.zeros(1)}
+         "W3": rng.uniform(-1, 1, (NH, NH)) * np.sqrt(6.0 / NH), "b3": np.zeros(NH),
+         "w4": rng.uniform(-1, 1, NH) * np.sqrt(6.0 / NH) * 0.1, "b4": np.zeros(1)}
     return pack(d)
 
 
@@ -78,9 +82,11 @@ def forward(theta, X, round_bf16: bool = False):
     a1 = x @ r(P["W1"]) + P["b1"]
     h1 = r(np.maximum(a1, 0.0))
     a2 = h1 @ r(P["W2"]) + P["b2"]
-    h2 = np.maximum(a2, 0.0)
-    z = h2 @ P["w3"] + P["b3"][0]
-    return _sigmoid(z), (x, a1, h1, a2, h2, z)
+    h2 = r(np.maximum(a2, 0.0))
+    a3 = h2 @ r(P["W3"]) + P["b3"]
+    h3 = np.maximum(a3, 0.0)
+    z = h3 @ P["w4"] + P["b4"][0]
+    return _sigmoid(z), (x, a1, h1, a2, h2, a3, h3, z)
 
 
 def loss_and_grad(theta, X, y, w, round_bf16: bool = False):
@@ -88,19 +94,21 @@ def loss_and_grad(theta, X, y, w, round_bf16: bool = False):
     and its gradient with respect to the flat parameters."""
     P = unpack(theta)
     r = bf16 if round_bf16 else (lambda v: np.asarray(v, dtype=np.float64))
-    p, (x, a1, h1, a2, h2, z) = forward(theta, X, round_bf16)
+    p, (x, a1, h1, a2, h2, a3, h3, z) = forward(theta, X, round_bf16)
     y = np.asarray(y, dtype=np.float64)
     w = np.asarray(w, dtype=np.float64)
     W = w.sum()
     eps = 1e-12
     L = -np.sum(w * (y * np.log(p + eps) + (1 - y) * np.log(1 - p + eps))) / W
     dz = w * (p - y) / W                          # dL/dz
-    g = {"w3": h2.T @ dz, "b3": np.array([dz.sum()])}
-    da2 = np.outer(dz, P["w3"]) * (a2 > 0)       # dL/da2
+    g = {"w4": h3.T @ dz, "b4": np.array([dz.sum()])}
+    da3 = np.outer(dz, P["w4"]) * (a3 > 0)       # dL/da3
+    g["W3"] = h2.T @ r(da3)
+    g["b3"] = da3.sum(axis=0)
+    da2 = (r(da3) @ r(P["W3"]).T) * (a2 > 0)
     g["W2"] = h1.T @ r(da2)
     g["b2"] = da2.sum(axis=0)
-    dh1 = r(da2) @ r(P["W2"]).T
-    da1 = dh1 * (a1 > 0)
+    da1 = (r(da2) @ r(P["W2"]).T) * (a1 > 0)
     g["W1"] = x.T @ r(da1)
     g["b1"] = da1.sum(axis=0)
     return L, pack(g)

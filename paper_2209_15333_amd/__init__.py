@@ -117,7 +117,7 @@ def lib() -> ctypes.CDLL:
                                           ctypes.POINTER(ctypes.c_int64)]
         L.ocfd_sensor_train.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_uint64,
                                         ctypes.c_double, dp]
-        L.ocfd_sensor_calibrate.argtypes = [vp, ctypes.c_double, ctypes.c_double, dp]
+        L.ocfd_sensor_calibrate.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_double, dp]
         L.ocfd_sensor_grad.argtypes = [vp, vp, vp, vp, ctypes.c_int64, fp]
         L.ocfd_sensor_audit.argtypes = [vp, dp]
         _lib = L
@@ -309,9 +309,9 @@ def ocfd_sensor_train(h, epochs: int, batch: int, lr: float, seed: int, holdout:
     return list(out)
 
 
-def ocfd_sensor_calibrate(h, holdout: float, margin: float):
+def ocfd_sensor_calibrate(h, holdout: float, margin: float, miss: float = 0.0):
     out = (ctypes.c_double * 4)()
-    _check(h, lib().ocfd_sensor_calibrate(h, holdout, margin, out), "ocfd_sensor_calibrate")
+    _check(h, lib().ocfd_sensor_calibrate(h, holdout, margin, miss, out), "ocfd_sensor_calibrate")
     return list(out)
 
 

@@ -1055,13 +1055,13 @@ int ocfd_sensor_train(ocfd_solver* s, int32_t epochs, int32_t batch, float lr, u
   return OCFD_OK;
 }
 
-int ocfd_sensor_calibrate(ocfd_solver* s, double holdout, double margin, double* out) {
+int ocfd_sensor_calibrate(ocfd_solver* s, double holdout, double margin, double miss, double* out) {
   int rc;
   if (!ready(s, &rc)) return rc;
   if (!out) return fail(s, OCFD_ERR_BADARG, "null output");
   if (!s->mlp_ready) return fail(s, OCFD_ERR_STATE, "no network parameters set");
-  if (!(holdout > 0.0 && holdout < 1.0) || !(margin > 0.0 && margin <= 1.0))
-    return fail(s, OCFD_ERR_BADARG, "holdout in (0,1) and margin in (0,1] required");
+  if (!(holdout > 0.0 && holdout < 1.0) || !(margin > 0.0 && margin <= 1.0) || !(miss >= 0.0 && miss < 0.5))
+    return fail(s, OCFD_ERR_BADARG, "holdout in (0,1), margin in (0,1] and miss in [0,0.5) required");
   const long long C = s->smp_cap;
   const long long a = (long long)((1.0 - holdout) * (double)s->smp_n);
   const long long nh = s->smp_n - a;
@@ -1074,22 +1074,29 @@ int ocfd_sensor_calibrate(ocfd_solver* s, double holdout, double margin, double*
   if (e == hipSuccess) e = hipMemcpyAsync(y.data(), s->smp + smp_off_y(C) + a, nh, hipMemcpyDeviceToHost, s->st);
   if (e == hipSuccess) e = hipStreamSynchronize(s->st);
   if (e != hipSuccess) return hip_fail(s, e, "calibration");
-  // per direction (bits 1-2 of the label byte): tau_d = margin * the least
-  // probability of a held-out WENO sample of direction d; a direction with
-  // none takes the least over all directions
-  double pmin[3] = {2.0, 2.0, 2.0}, pall = 2.0;
+  // per direction (bits 1-2 of the label byte): tau_d = margin * the k-th
+  // least probability of the held-out WENO samples of direction d,
+  // k = floor(miss * their count); a direction with none takes the value
+  // over all directions
+  std::vector<float> pw[4];
   long long npos = 0, nneg = 0;
   for (long long k = 0; k < nh; ++k) {
     const int d = std::min(2, (int)(y[k] >> 1));
     if (y[k] & 1) {
-      pmin[d] = std::min(pmin[d], (double)p[k]);
-      pall = std::min(pall, (double)p[k]);
+      pw[d].push_back(p[k]);
+      pw[3].push_back(p[k]);
       ++npos;
     } else {
       ++nneg;
     }
   }
-  for (int d = 0; d < 3; ++d) s->tau[d] = npos ? margin * (pmin[d] <= 1.0 ? pmin[d] : pall) : 0.5;
+  auto kth = [&](std::vector<float>& v) {
+    const size_t k = std::min(v.size() - 1, (size_t)(miss * (double)v.size()));
+    std::nth_element(v.begin(), v.begin() + k, v.end());
+    return (double)v[k];
+  };
+  const double pall = npos ? kth(pw[3]) : 0.0;
+  for (int d = 0; d < 3; ++d) s->tau[d] = npos ? margin * (pw[d].empty() ? pall : kth(pw[d])) : 0.5;
   long long fp = 0, tp = 0;
   for (long long k = 0; k < nh; ++k) {
     const int d = std::min(2, (int)(y[k] >> 1));

@@ -8,17 +8,20 @@
 
 namespace ocfd {
 
-// Learned-sensor perceptron 32 -> 32 -> 32 -> 1: offsets in the flat FP32
-// parameter array (W1 [input][unit], b1, W2 [input][unit], b2, w3, b3).
+// Learned-sensor perceptron 32 -> 64 -> 64 -> 64 -> 1: offsets in the flat
+// FP32 parameter array (W1 [input][unit], b1, W2 [input][unit], b2, W3, b3,
+// w4, b4).
 constexpr int MLP_IN = 32;
-constexpr int MLP_H = 32;
+constexpr int MLP_H = 64;
 constexpr int MLP_W1 = 0;
 constexpr int MLP_B1 = MLP_W1 + MLP_IN * MLP_H;
 constexpr int MLP_W2 = MLP_B1 + MLP_H;
 constexpr int MLP_B2 = MLP_W2 + MLP_H * MLP_H;
 constexpr int MLP_W3 = MLP_B2 + MLP_H;
-constexpr int MLP_B3 = MLP_W3 + MLP_H;
-constexpr int MLP_NPARAM = MLP_B3 + 1;
+constexpr int MLP_B3 = MLP_W3 + MLP_H * MLP_H;
+constexpr int MLP_W4 = MLP_B3 + MLP_H;
+constexpr int MLP_B4 = MLP_W4 + MLP_H;
+constexpr int MLP_NPARAM = MLP_B4 + 1;
 
 // Division of 32-bit unsigned integers by an invariant divisor d >= 1:
 // x / d = (umulhi(x, mul) + x) >> shift with shift = ceil(log2 d) and

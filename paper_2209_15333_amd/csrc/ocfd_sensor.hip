@@ -1,6 +1,6 @@
 // Shock sensors of the hybrid scheme (Sec. 2.2.3, eq 42-43) and the learned
 // sensor that can replace the pressure sensor: node features, per-interface
-// flags, a 32-32-32-1 perceptron evaluated and trained with bf16 matrix-core
+// flags, a 32-64-64-64-1 perceptron evaluated and trained with bf16 matrix-core
 // (MFMA) instructions, sample collection, calibration and audit.
 //
 // MFMA operand layout used throughout (v_mfma_f32_16x16x32_bf16, one wave):
@@ -10,8 +10,9 @@
 // and for v_mfma_f32_16x16x16bf16_1k the same with 4 values per lane.
 // Activations are kept transposed (hidden unit x sample), so a layer's C
 // registers are the next layer's B operand after a fixed relabelling of the
-// hidden units: k-slot 8g+q of lane group g holds unit 4g+q (q < 4) or
-// 16+4g+q-4 (q >= 4).  The relabelling is applied to the weights instead.
+// hidden units: in the K-chunk of units 32c .. 32c+31, k-slot 8g+q of lane
+// group g holds unit 32c + 4g+q (q < 4) or 32c + 16+4g+q-4 (q >= 4).  The
+// relabelling is applied to the weights instead.
 #include "ocfd_internal.h"
 
 namespace ocfd {
@@ -279,59 +280,90 @@ __device__ __forceinline__ int node_pos(const Geo& g, long long id, int d) {
 // The perceptron
 // ---------------------------------------------------------------------------
 
-// Per-lane weight registers of one wave.
+// Per-lane weight registers of one wave (forward pass).  Hidden unit u of a
+// layer with 64 units lives in C tile u / 16, row u % 16; a K-chunk c of 32
+// units (tiles 2c and 2c+1) feeds the next layer's B operand, k-slot 8g+q of
+// lane group g holding unit 32c + unit_of(g, q), which is the lane's own C
+// value of tile 2c (q < 4) or 2c+1 (q >= 4).
+// The biases and output weights (read once per tile each) sit in LDS, which
+// frees 64 registers per lane for the weights and the tile in flight.
 struct MlpRegs {
-  v8bf A1[2];   // W1^T tiles: row = hidden 16m + l%16, cols = inputs 8g..8g+7
-  v8bf A2[2];   // W2^T tiles, input hidden units relabelled by unit_of
-  float b1[2][4], b2[2][4], w3[2][4];
-  float b3;
+  v8bf A1[4];      // W1^T tiles: row = unit 16m + l%16, k = inputs 8g .. 8g+7
+  v8bf A2[4][2];   // W2^T: row = output unit 16m + l%16, k-chunk c: input unit 32c + unit_of(g, q)
+  v8bf A3[4][2];   // W3^T, the same
 };
+
+// LDS copy of b1, b2, b3, w4 (64 each) and b4.
+constexpr int LB_B1 = 0, LB_B2 = 64, LB_B3 = 128, LB_W4 = 192, LB_B4 = 256, LB_N = 260;
+
+// Every thread of the block takes part; a barrier follows before use.
+__device__ __forceinline__ void stage_bias(const float* __restrict__ P, float* lb) {
+  for (int k = threadIdx.x; k < 257; k += blockDim.x)
+    lb[k] = k < 64 ? P[MLP_B1 + k] : k < 128 ? P[MLP_B2 + k - 64] : k < 192 ? P[MLP_B3 + k - 128]
+          : k < 256 ? P[MLP_W4 + k - 192] : P[MLP_B4];
+}
+
+// Values of units 16m + 4g .. 16m + 4g + 3 of one 64-vector in LDS.
+__device__ __forceinline__ v4f lds4(const float* lb, int off, int m, int g) {
+  return *(const v4f*)(lb + off + 16 * m + 4 * g);
+}
+
+// A operand of W^T (W [input][unit] of a 64-unit layer, row 16m + i, k-chunk c).
+__device__ __forceinline__ void load_wt(const float* __restrict__ W, int m, int c, int g, int i, v8bf& A) {
+  for (int q = 0; q < 8; ++q) A[q] = (__bf16)W[(32 * c + unit_of(g, q)) * MLP_H + 16 * m + i];
+}
 
 __device__ __forceinline__ void load_mlp(const float* __restrict__ P, MlpRegs& R) {
   const int l = threadIdx.x & 63, i = l & 15, g = l >> 4;
-  for (int m = 0; m < 2; ++m) {
-    for (int q = 0; q < 8; ++q) {
-      R.A1[m][q] = (__bf16)P[MLP_W1 + (8 * g + q) * MLP_H + 16 * m + i];
-      R.A2[m][q] = (__bf16)P[MLP_W2 + unit_of(g, q) * MLP_H + 16 * m + i];
-    }
-    for (int r = 0; r < 4; ++r) {
-      R.b1[m][r] = P[MLP_B1 + 16 * m + 4 * g + r];
-      R.b2[m][r] = P[MLP_B2 + 16 * m + 4 * g + r];
-      R.w3[m][r] = P[MLP_W3 + 16 * m + 4 * g + r];
+  for (int m = 0; m < 4; ++m) {
+    for (int q = 0; q < 8; ++q) R.A1[m][q] = (__bf16)P[MLP_W1 + (8 * g + q) * MLP_H + 16 * m + i];
+    for (int c = 0; c < 2; ++c) {
+      load_wt(P + MLP_W2, m, c, g, i, R.A2[m][c]);
+      load_wt(P + MLP_W3, m, c, g, i, R.A3[m][c]);
     }
   }
-  R.b3 = P[MLP_B3];
 }
 
 struct Fwd {
-  v4f a1[2], a2[2];  // pre-activations, C layout (unit 16m + 4g + r, sample l%16)
-  v8bf h1;           // relu(a1) as the B operand of layer 2
-  float z;           // output logit of sample l%16 (same in the four lane groups)
+  v4f a1[4], a2[4], a3[4];  // pre-activations, C layout (unit 16m + 4g + r, sample l%16)
+  v8bf h1[2], h2[2];        // relu(a1), relu(a2) as the B operands of layers 2 and 3 (K-chunks)
+  float z;                  // output logit of sample l%16 (same in the four lane groups)
 };
 
-// Forward pass of 16 samples held as the B operand x (inputs 8g..8g+7 of sample l%16).
-__device__ __forceinline__ void mlp_forward(const MlpRegs& R, const v8bf& x, Fwd& F) {
-  const v4f zero = {0.f, 0.f, 0.f, 0.f};
-  for (int m = 0; m < 2; ++m) {
-    F.a1[m] = mfma32(R.A1[m], x, zero);
-    for (int r = 0; r < 4; ++r) F.a1[m][r] += R.b1[m][r];
-  }
+// B operand of K-chunk c from C tiles 2c, 2c+1 (the relabelling above), of
+// v (relu when relu is set).
+__device__ __forceinline__ v8bf chunk_b(const v4f* v, int c, bool relu) {
+  v8bf b;
   for (int q = 0; q < 8; ++q) {
-    const float a = q < 4 ? F.a1[0][q] : F.a1[1][q - 4];
-    F.h1[q] = (__bf16)fmaxf(a, 0.f);
+    const float a = q < 4 ? v[2 * c][q] : v[2 * c + 1][q - 4];
+    b[q] = (__bf16)(relu ? fmaxf(a, 0.f) : a);
   }
+  return b;
+}
+
+// One 64-unit layer: out[m] = sum_c A[m][c] B[c] + bias.
+__device__ __forceinline__ void layer64(const v8bf (*A)[2], const v8bf* B, const float* lb, int off, v4f* out) {
+  const int g = (threadIdx.x & 63) >> 4;
+  for (int m = 0; m < 4; ++m) out[m] = mfma32(A[m][1], B[1], mfma32(A[m][0], B[0], lds4(lb, off, m, g)));
+}
+
+// Forward pass of 16 samples held as the B operand x (inputs 8g..8g+7 of sample l%16).
+__device__ __forceinline__ void mlp_forward(const MlpRegs& R, const float* lb, const v8bf& x, Fwd& F) {
+  const int g = (threadIdx.x & 63) >> 4;
+  for (int m = 0; m < 4; ++m) F.a1[m] = mfma32(R.A1[m], x, lds4(lb, LB_B1, m, g));
+  for (int c = 0; c < 2; ++c) F.h1[c] = chunk_b(F.a1, c, true);
+  layer64(R.A2, F.h1, lb, LB_B2, F.a2);
+  for (int c = 0; c < 2; ++c) F.h2[c] = chunk_b(F.a2, c, true);
+  layer64(R.A3, F.h2, lb, LB_B3, F.a3);
   float z = 0.f;
-  for (int m = 0; m < 2; ++m) {
-    F.a2[m] = mfma32(R.A2[m], F.h1, zero);
-    for (int r = 0; r < 4; ++r) {
-      F.a2[m][r] += R.b2[m][r];
-      z += R.w3[m][r] * fmaxf(F.a2[m][r], 0.f);
-    }
+  for (int m = 0; m < 4; ++m) {
+    const v4f w4 = lds4(lb, LB_W4, m, g);
+    for (int r = 0; r < 4; ++r) z += w4[r] * fmaxf(F.a3[m][r], 0.f);
   }
   // sum over the four lane groups (hidden units) of each sample
   z += __shfl_xor(z, 16);
   z += __shfl_xor(z, 32);
-  F.z = z + R.b3;
+  F.z = z + lb[LB_B4];
 }
 
 __device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + __expf(-z)); }
@@ -341,8 +373,11 @@ __device__ __forceinline__ float sigmoidf(float z) { return 1.f / (1.f + __expf(
 __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const uint2* __restrict__ feat,
                                                    const float* __restrict__ P, const Tau3 tau,
                                                    uint8_t* __restrict__ flags) {
+  __shared__ __align__(16) float lb[LB_N];
+  stage_bias(P, lb);
   MlpRegs R;
   load_mlp(P, R);
+  __syncthreads();
   const int l = threadIdx.x & 63, j = l & 15, gg = l >> 4;
   const long long N = g.N;
   const long long tiles = (N + 15) / 16;
@@ -392,7 +427,7 @@ __global__ __launch_bounds__(256) void k_mlp_flags(const Geo g, const uint2* __r
       v8bf x;
       __builtin_memcpy(&x, cur.xv, 16);
       Fwd F;
-      mlp_forward(R, x, F);
+      mlp_forward(R, lb, x, F);
       if (cur.ok && gg == 0) flags[d * N + cur.id] = (!cur.inside || sigmoidf(F.z) >= tau.t[d]) ? 1 : 0;
       cur = nxt;
     }
@@ -408,8 +443,11 @@ hipError_t launch_mlp_flags(const Geo& g, const uint16_t* feat, const float* P, 
 // Probabilities of stored samples X [S][32] (bf16 bits), in order.
 __global__ __launch_bounds__(256) void k_mlp_prob(const uint16_t* __restrict__ X, long long S,
                                                   const float* __restrict__ P, float* __restrict__ prob) {
+  __shared__ __align__(16) float lb[LB_N];
+  stage_bias(P, lb);
   MlpRegs R;
   load_mlp(P, R);
+  __syncthreads();
   const int l = threadIdx.x & 63, j = l & 15, gg = l >> 4;
   const long long tiles = (S + 15) / 16;
   for (long long T = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); T < tiles; T += (long long)gridDim.x * 4) {
@@ -418,7 +456,7 @@ __global__ __launch_bounds__(256) void k_mlp_prob(const uint16_t* __restrict__ X
     v8bf x;
     __builtin_memcpy(&x, X + sc * 32 + 8 * gg, 16);
     Fwd F;
-    mlp_forward(R, x, F);
+    mlp_forward(R, lb, x, F);
     if (s < S && gg == 0) prob[s] = sigmoidf(F.z);
   }
 }
@@ -431,38 +469,59 @@ hipError_t launch_mlp_prob(const uint16_t* X, long long S, const float* P, float
 // ---------------------------------------------------------------------------
 // Training: gradient of the weighted binary cross-entropy over a batch
 //   L = -sum_i w_i [y_i log p_i + (1 - y_i) log(1 - p_i)] / Wsum
-// Each wave takes 16-sample tiles; weight gradients use 16x16x16 MFMAs with
-// the samples as the reduction dimension, after a transpose through LDS.
-// Every workgroup writes its partial gradient; k_mlp_reduce sums them in a
-// fixed order (deterministic).
+// A round takes 64 samples, 16 per wave.  Each wave runs the forward pass and
+// the backward pass of its samples through the layers (16x16x32 MFMAs with
+// the transposed weights) and stages its inputs, hidden activations and
+// pre-activation gradients as [unit][sample] bf16 rows in LDS.  Then the
+// weight gradients dW[in][out] = sum_s act[in][s] delta[out][s] are forty
+// 16x16 tiles (W1 8, W2 16, W3 16), ten per wave, each an MFMA chain over the
+// round's 64 samples (4 x 16x16x16).  Bias, output-layer and loss terms are
+// per-lane sums.  Every workgroup writes its partial gradient;
+// k_mlp_reduce_adam sums them in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
 constexpr int GT = 256;
+constexpr int SPAD = 64 + 8;   // row stride (bf16) of the [unit][sample] staging
+
+struct Stage {
+  __bf16 x[MLP_IN][SPAD];
+  __bf16 h1[MLP_H][SPAD];
+  __bf16 h2[MLP_H][SPAD];
+  __bf16 d1[MLP_H][SPAD];
+  __bf16 d2[MLP_H][SPAD];
+  __bf16 d3[MLP_H][SPAD];
+};
+
+// A operand of W (W [input][unit], 64 x 64) for the product W delta: row =
+// input unit 16m + i, k-chunk c: output unit 32c + unit_of(g, q).
+__device__ __forceinline__ void load_w(const float* __restrict__ W, int m, int c, int g, int i, v8bf& A) {
+  for (int q = 0; q < 8; ++q) A[q] = (__bf16)W[(16 * m + i) * MLP_H + 32 * c + unit_of(g, q)];
+}
 
 __global__ __launch_bounds__(GT) void k_mlp_grad(const uint16_t* __restrict__ X, const uint8_t* __restrict__ y,
                                                  const float* __restrict__ w, const int* __restrict__ idx,
                                                  long long nb, float Wsum, const float* __restrict__ P,
                                                  float* __restrict__ partial) {
-  __shared__ __bf16 lds_h[4][32][17];   // per wave: relu(a1) [unit][sample]
-  __shared__ __bf16 lds_d[4][32][17];   // per wave: back-propagated pre-activation gradient [unit][sample]
-  __shared__ __bf16 lds_x[4][32][17];   // per wave: inputs [input][sample]
-  __shared__ float red[MLP_NPARAM + 1];
+  __shared__ union {
+    Stage st;
+    float red[MLP_NPARAM + 1];
+  } sh;
+  __shared__ __align__(16) float lb[LB_N];
+  stage_bias(P, lb);
   MlpRegs R;
   load_mlp(P, R);
-  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, j = l & 15, gg = l >> 4;
-  for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += GT) red[k] = 0.f;
-  // W2 as the A operand of dh1 = W2 da2 (rows = input unit 16m + l%16, k-slots relabelled)
-  v8bf A2b[2];
-  for (int m = 0; m < 2; ++m)
-    for (int q = 0; q < 8; ++q) A2b[m][q] = (__bf16)P[MLP_W2 + (16 * m + j) * MLP_H + unit_of(gg, q)];
-  v4f gW1[2][2], gW2[2][2];   // [tile of output unit][tile of input] C layout: col = input, rows = output unit
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
-      gW1[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
-      gW2[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
-    }
-  float gb1[2][4] = {}, gb2[2][4] = {}, gw3[2][4] = {};
-  float gb3 = 0.f, loss = 0.f;
   __syncthreads();
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, j = l & 15, gg = l >> 4;
+  v8bf A2b[4][2], A3b[4][2];   // W2, W3 as the A operands of the back-propagation
+  for (int m = 0; m < 4; ++m)
+    for (int c = 0; c < 2; ++c) {
+      load_w(P + MLP_W2, m, c, gg, j, A2b[m][c]);
+      load_w(P + MLP_W3, m, c, gg, j, A3b[m][c]);
+    }
+  v4f acc[10];   // weight-gradient tiles t = wv + 4k (C layout: col = input unit, rows = output unit)
+  for (int k = 0; k < 10; ++k) acc[k] = (v4f){0.f, 0.f, 0.f, 0.f};
+  float gb1[4][4] = {}, gb2[4][4] = {}, gb3[4][4] = {}, gw4[4][4] = {};
+  float gb4 = 0.f, loss = 0.f;
+  const v4f zero = {0.f, 0.f, 0.f, 0.f};
   // Every wave runs the same number of rounds (barriers below are block-wide);
   // a wave past the last tile works on sample 0 with zero weight.
   const long long tiles = (nb + 15) / 16;
@@ -474,111 +533,121 @@ __global__ __launch_bounds__(GT) void k_mlp_grad(const uint16_t* __restrict__ X,
     v8bf x;
     __builtin_memcpy(&x, X + si * 32 + 8 * gg, 16);
     Fwd F;
-    mlp_forward(R, x, F);
+    mlp_forward(R, lb, x, F);
     const float p = sigmoidf(F.z);
     const float ys = (float)(y[si] & 1);   // bit 0: label (bits 1-2 of collected samples: direction)
     const float ws = ok ? w[si] : 0.f;
     const float dz = ws * (p - ys) / Wsum;
     if (gg == 0) loss += -ws * (ys * __logf(p + 1e-12f) + (1.f - ys) * __logf(1.f - p + 1e-12f)) / Wsum;
-    // output layer and da2
-    v4f da2[2];
-    for (int m = 0; m < 2; ++m)
+    if (gg == 0) gb4 += dz;
+    // output layer and da3
+    v4f da3[4], da2[4], da1[4];
+    for (int m = 0; m < 4; ++m)
       for (int r = 0; r < 4; ++r) {
-        const float h2 = fmaxf(F.a2[m][r], 0.f);
-        gw3[m][r] += dz * h2;
-        da2[m][r] = F.a2[m][r] > 0.f ? dz * R.w3[m][r] : 0.f;
+        gw4[m][r] += dz * fmaxf(F.a3[m][r], 0.f);
+        da3[m][r] = F.a3[m][r] > 0.f ? dz * lb[LB_W4 + 16 * m + 4 * gg + r] : 0.f;
+        gb3[m][r] += da3[m][r];
+      }
+    // da2 = (W3 da3) * (a2 > 0), da1 = (W2 da2) * (a1 > 0)
+    v8bf db[2];
+    for (int c = 0; c < 2; ++c) db[c] = chunk_b(da3, c, false);
+    for (int m = 0; m < 4; ++m) {
+      const v4f dh = mfma32(A3b[m][1], db[1], mfma32(A3b[m][0], db[0], zero));
+      for (int r = 0; r < 4; ++r) {
+        da2[m][r] = F.a2[m][r] > 0.f ? dh[r] : 0.f;
         gb2[m][r] += da2[m][r];
       }
-    if (gg == 0) gb3 += dz;
-    // dh1 = W2 da2 (B operand: da2 relabelled like h1)
-    v8bf db;
-    for (int q = 0; q < 8; ++q) db[q] = (__bf16)(q < 4 ? da2[0][q] : da2[1][q - 4]);
-    v4f da1[2];
-    const v4f zero = {0.f, 0.f, 0.f, 0.f};
-    for (int m = 0; m < 2; ++m) {
-      const v4f dh = mfma32(A2b[m], db, zero);
+    }
+    for (int c = 0; c < 2; ++c) db[c] = chunk_b(da2, c, false);
+    for (int m = 0; m < 4; ++m) {
+      const v4f dh = mfma32(A2b[m][1], db[1], mfma32(A2b[m][0], db[0], zero));
       for (int r = 0; r < 4; ++r) {
         da1[m][r] = F.a1[m][r] > 0.f ? dh[r] : 0.f;
         gb1[m][r] += da1[m][r];
       }
     }
-    // stage [unit][sample] tiles for the weight gradients
-    for (int m = 0; m < 2; ++m)
+    // stage [unit][sample] rows of this wave's 16 samples
+    const int col = 16 * wv + j;
+    for (int m = 0; m < 4; ++m)
       for (int r = 0; r < 4; ++r) {
         const int u = 16 * m + 4 * gg + r;
-        lds_h[wv][u][j] = (__bf16)fmaxf(F.a1[m][r], 0.f);
-        lds_d[wv][u][j] = (__bf16)da2[m][r];
+        sh.st.h1[u][col] = (__bf16)fmaxf(F.a1[m][r], 0.f);
+        sh.st.h2[u][col] = (__bf16)fmaxf(F.a2[m][r], 0.f);
+        sh.st.d1[u][col] = (__bf16)da1[m][r];
+        sh.st.d2[u][col] = (__bf16)da2[m][r];
+        sh.st.d3[u][col] = (__bf16)da3[m][r];
       }
-    for (int q = 0; q < 8; ++q) lds_x[wv][8 * gg + q][j] = x[q];
+    for (int q = 0; q < 8; ++q) sh.st.x[8 * gg + q][col] = x[q];
     __syncthreads();
-    // gW2[o][i] += sum_s da2[o][s] h1[i][s];  gW1[o][i] += sum_s da1[o][s] x[i][s]
-    for (int mo = 0; mo < 2; ++mo)
-      for (int mi = 0; mi < 2; ++mi) {
+    // weight-gradient tiles: t < 8 W1 (4 output x 2 input tiles), 8 <= t < 24
+    // W2, 24 <= t < 40 W3 (4 x 4); t is uniform within the wave
+    for (int k = 0; k < 10; ++k) {
+      const int t = wv + 4 * k;
+      const int mat = t < 8 ? 1 : (t < 24 ? 2 : 3);
+      const int tt = t < 8 ? t : (t < 24 ? t - 8 : t - 24);
+      const int mo = mat == 1 ? tt / 2 : tt / 4, mi = mat == 1 ? tt % 2 : tt % 4;
+      const __bf16(*act)[SPAD] = mat == 1 ? sh.st.x : (mat == 2 ? sh.st.h1 : sh.st.h2);
+      const __bf16(*del)[SPAD] = mat == 1 ? sh.st.d1 : (mat == 2 ? sh.st.d2 : sh.st.d3);
+      for (int kc = 0; kc < 4; ++kc) {
         v4bf a, b;
         for (int q = 0; q < 4; ++q) {
-          a[q] = lds_d[wv][16 * mo + j][4 * gg + q];
-          b[q] = lds_h[wv][16 * mi + j][4 * gg + q];
+          a[q] = del[16 * mo + j][16 * kc + 4 * gg + q];
+          b[q] = act[16 * mi + j][16 * kc + 4 * gg + q];
         }
-        gW2[mo][mi] = mfma16(a, b, gW2[mo][mi]);
+        acc[k] = mfma16(a, b, acc[k]);
       }
-    __syncthreads();
-    for (int m = 0; m < 2; ++m)
-      for (int r = 0; r < 4; ++r) lds_d[wv][16 * m + 4 * gg + r][j] = (__bf16)da1[m][r];
-    __syncthreads();
-    for (int mo = 0; mo < 2; ++mo)
-      for (int mi = 0; mi < 2; ++mi) {
-        v4bf a, b;
-        for (int q = 0; q < 4; ++q) {
-          a[q] = lds_d[wv][16 * mo + j][4 * gg + q];
-          b[q] = lds_x[wv][16 * mi + j][4 * gg + q];
-        }
-        gW1[mo][mi] = mfma16(a, b, gW1[mo][mi]);
-      }
+    }
     __syncthreads();
   }
   // Bias, output-layer and loss terms: lane (j, gg) holds the sums over its
   // samples for the units of lane group gg; add the 16 lanes of each group by
   // butterfly shuffles (every lane takes part; fixed order, so deterministic).
-  for (int m = 0; m < 2; ++m)
+  for (int m = 0; m < 4; ++m)
     for (int r = 0; r < 4; ++r)
       for (int o = 1; o < 16; o <<= 1) {
         gb1[m][r] += __shfl_xor(gb1[m][r], o);
         gb2[m][r] += __shfl_xor(gb2[m][r], o);
-        gw3[m][r] += __shfl_xor(gw3[m][r], o);
+        gb3[m][r] += __shfl_xor(gb3[m][r], o);
+        gw4[m][r] += __shfl_xor(gw4[m][r], o);
       }
   for (int o = 1; o < 16; o <<= 1) {
-    gb3 += __shfl_xor(gb3, o);
+    gb4 += __shfl_xor(gb4, o);
     loss += __shfl_xor(loss, o);
   }
-  // Into red[], wave by wave (block barrier between waves).  Within a wave
-  // every lane writes distinct entries: the weight tiles (o, in) differ per
-  // lane, and only lane j = 0 of each group writes that group's units.
+  // The staging is done with (barrier above); the same LDS now holds red[].
+  for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += GT) sh.red[k] = 0.f;
+  __syncthreads();
+  // Weight tiles: each entry belongs to one lane of one wave, so all waves
+  // write at once.
+  for (int k = 0; k < 10; ++k) {
+    const int t = wv + 4 * k;
+    const int mat = t < 8 ? 1 : (t < 24 ? 2 : 3);
+    const int tt = t < 8 ? t : (t < 24 ? t - 8 : t - 24);
+    const int mo = mat == 1 ? tt / 2 : tt / 4, mi = mat == 1 ? tt % 2 : tt % 4;
+    const int off = mat == 1 ? MLP_W1 : (mat == 2 ? MLP_W2 : MLP_W3);
+    for (int r = 0; r < 4; ++r) sh.red[off + (16 * mi + j) * MLP_H + 16 * mo + 4 * gg + r] = acc[k][r];
+  }
+  __syncthreads();
+  // Bias terms: the waves in turn (fixed order).
   for (int wave = 0; wave < 4; ++wave) {
-    if (wv == wave) {
-      for (int mo = 0; mo < 2; ++mo)
-        for (int mi = 0; mi < 2; ++mi)
-          for (int r = 0; r < 4; ++r) {
-            const int o = 16 * mo + 4 * gg + r, in = 16 * mi + j;
-            red[MLP_W1 + in * MLP_H + o] += gW1[mo][mi][r];
-            red[MLP_W2 + in * MLP_H + o] += gW2[mo][mi][r];
-          }
-      if (j == 0) {
-        for (int m = 0; m < 2; ++m)
-          for (int r = 0; r < 4; ++r) {
-            const int u = 16 * m + 4 * gg + r;
-            red[MLP_B1 + u] += gb1[m][r];
-            red[MLP_B2 + u] += gb2[m][r];
-            red[MLP_W3 + u] += gw3[m][r];
-          }
-        if (gg == 0) {
-          red[MLP_B3] += gb3;
-          red[MLP_NPARAM] += loss;
+    if (wv == wave && j == 0) {
+      for (int m = 0; m < 4; ++m)
+        for (int r = 0; r < 4; ++r) {
+          const int u = 16 * m + 4 * gg + r;
+          sh.red[MLP_B1 + u] += gb1[m][r];
+          sh.red[MLP_B2 + u] += gb2[m][r];
+          sh.red[MLP_B3 + u] += gb3[m][r];
+          sh.red[MLP_W4 + u] += gw4[m][r];
         }
+      if (gg == 0) {
+        sh.red[MLP_B4] += gb4;
+        sh.red[MLP_NPARAM] += loss;
       }
     }
     __syncthreads();
   }
-  for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += GT) partial[(long long)blockIdx.x * (MLP_NPARAM + 1) + k] = red[k];
+  for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += GT)
+    partial[(long long)blockIdx.x * (MLP_NPARAM + 1) + k] = sh.red[k];
 }
 
 // Sum the workgroups' partial gradients (fixed order) into grad[NPARAM + 1]

@@ -128,7 +128,7 @@ def test_workspace_and_order_errors(ocfd):
 def test_sensor_host_checks(ocfd):
     from oracle import mlp
     L = ocfd.lib()
-    assert L.ocfd_sensor_nparams() == mlp.NPARAM == 2145
+    assert L.ocfd_sensor_nparams() == mlp.NPARAM == 10497
     assert L.ocfd_sensor_sample_bytes(0) == 0
     assert L.ocfd_sensor_sample_bytes(1000) == 1000 * 77
     p = _params(ocfd)

@@ -430,15 +430,17 @@ def bounded_box(shape: Tuple[int, int, int] = (36, 20, 18), seed: int = 22095, M
 
 
 def sensor_initial_weights(seed: int = 0) -> np.ndarray:
-    """Initial weights of the 32-32-32-1 shock-sensor perceptron as one flat
-    array W1 [32 in][32 out], b1, W2 [32][32], b2, w3 [32], b3: He-uniform
-    hidden layers, an output layer ten times smaller, zero biases (PCG64(seed)
-    draws in that order)."""
+    """Initial weights of the 32-64-64-64-1 shock-sensor perceptron as one
+    flat array W1 [32 in][64 out], b1, W2 [64][64], b2, W3 [64][64], b3,
+    w4 [64], b4: He-uniform hidden layers, an output layer ten times smaller,
+    zero biases (PCG64(seed) draws in that order)."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    W1 = rng.uniform(-1, 1, (32, 32)) * math.sqrt(6.0 / 32)
-    W2 = rng.uniform(-1, 1, (32, 32)) * math.sqrt(6.0 / 32)
-    w3 = rng.uniform(-1, 1, 32) * math.sqrt(6.0 / 32) * 0.1
-    return np.concatenate([W1.ravel(), np.zeros(32), W2.ravel(), np.zeros(32), w3, np.zeros(1)])
+    W1 = rng.uniform(-1, 1, (32, 64)) * math.sqrt(6.0 / 32)
+    W2 = rng.uniform(-1, 1, (64, 64)) * math.sqrt(6.0 / 64)
+    W3 = rng.uniform(-1, 1, (64, 64)) * math.sqrt(6.0 / 64)
+    w4 = rng.uniform(-1, 1, 64) * math.sqrt(6.0 / 64) * 0.1
+    return np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), W3.ravel(), np.zeros(64), w4,
+                           np.zeros(1)])
 
 
 def projection_weights(n_nodes: int, count: int = 4, seed: int = 22096):
