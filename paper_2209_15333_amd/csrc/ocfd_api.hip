@@ -42,6 +42,7 @@ struct ocfd_solver {
   float* adam_m = nullptr;
   float* adam_v = nullptr;
   float* grad = nullptr;          // [NPARAM + 1]
+  double* eloss = nullptr;        // running sum of the batch losses of a training epoch
   float* gpartial = nullptr;      // [GRAD_BLOCKS][NPARAM + 1]
   unsigned long long* cnt = nullptr;   // [COUNT_BLOCKS * 4]
   double* inflow = nullptr;       // [5][face] of the INFLOW face
@@ -250,6 +251,7 @@ size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver
   float* am = (float*)take(MLP_NPARAM * sizeof(float));
   float* av = (float*)take(MLP_NPARAM * sizeof(float));
   float* grad = (float*)take((MLP_NPARAM + 1) * sizeof(float));
+  double* eloss = take(sizeof(double));
   float* gpart = (float*)take((size_t)GRAD_BLOCKS * (MLP_NPARAM + 1) * sizeof(float));
   unsigned long long* cnt = (unsigned long long*)take((size_t)COUNT_BLOCKS * 4 * sizeof(unsigned long long));
   const int fin = inflow_face(*p);
@@ -272,6 +274,7 @@ size_t workspace_layout(const ocfd_params* p, long long N, int nred, ocfd_solver
     s->adam_m = am;
     s->adam_v = av;
     s->grad = grad;
+    s->eloss = eloss;
     s->gpartial = gpart;
     s->cnt = cnt;
     s->inflow = inflow;
@@ -985,7 +988,7 @@ static int grad_step(ocfd_solver* s, const uint16_t* X, const uint8_t* y, const 
                      float Wsum, float lr) {
   if (lr > 0.f) s->adam_t += 1;
   hipError_t e = launch_mlp_grad(X, y, w, idx, nb, Wsum, s->mlp, s->gpartial, GRAD_BLOCKS, s->grad, s->mlp,
-                                 s->adam_m, s->adam_v, lr, s->adam_t, s->st);
+                                 s->adam_m, s->adam_v, lr, s->adam_t, s->eloss, s->st);
   return e == hipSuccess ? OCFD_OK : hip_fail(s, e, "training kernels");
 }
 
@@ -1028,22 +1031,22 @@ int ocfd_sensor_train(ocfd_solver* s, int32_t epochs, int32_t batch, float lr, u
     for (long long k = 0; k < ntrain; ++k) perm[k] = (int)k;
     std::shuffle(perm.begin(), perm.end(), rng);
     e = hipMemcpyAsync(didx, perm.data(), ntrain * sizeof(int), hipMemcpyHostToDevice, s->st);
+    // the batch losses are summed on the device and read once per epoch
+    if (e == hipSuccess) e = hipMemsetAsync(s->eloss, 0, sizeof(double), s->st);
     if (e != hipSuccess) return hip_fail(s, e, "index upload");
-    double eloss = 0.0;
     long long nbatch = 0;
     for (long long b0 = 0; b0 + batch <= ntrain; b0 += batch) {
       double W = 0.0;
       for (long long k = b0; k < b0 + batch; ++k) W += hw[perm[k]];
       rc = grad_step(s, X, y, w, didx + b0, batch, (float)W, lr);
       if (rc) return rc;
-      float L = 0.f;
-      e = hipMemcpyAsync(&L, s->grad + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToHost, s->st);
-      if (e == hipSuccess) e = hipStreamSynchronize(s->st);
-      if (e != hipSuccess) return hip_fail(s, e, "loss download");
-      eloss += L;
       nbatch += 1;
       steps += 1;
     }
+    double eloss = 0.0;
+    e = hipMemcpyAsync(&eloss, s->eloss, sizeof(double), hipMemcpyDeviceToHost, s->st);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->st);
+    if (e != hipSuccess) return hip_fail(s, e, "loss download");
     eloss /= (double)(nbatch > 0 ? nbatch : 1);
     if (ep == 0) first = eloss;
     last = eloss;

@@ -188,7 +188,7 @@ hipError_t launch_mlp_flags(const Geo& g, const uint16_t* feat, const float* P, 
 hipError_t launch_mlp_prob(const uint16_t* X, long long S, const float* P, float* prob, hipStream_t st);
 hipError_t launch_mlp_grad(const uint16_t* X, const uint8_t* y, const float* w, const int* idx, long long nb,
                            float Wsum, const float* P, float* partial, int nblocks, float* grad, float* Pmut,
-                           float* m, float* v, float lr, int t, hipStream_t st);
+                           float* m, float* v, float lr, int t, double* eloss, hipStream_t st);
 hipError_t launch_collect_count(const Geo& g, const uint8_t* flags, uint64_t seed, uint32_t thr_pos, uint32_t thr_neg,
                                 unsigned long long* counts, int nblocks, hipStream_t st);
 hipError_t launch_collect_write(const Geo& g, const uint8_t* flags, const uint16_t* feat, uint64_t seed, uint32_t thr_pos,

@@ -674,34 +674,40 @@ __global__ __launch_bounds__(GT) void k_mlp_grad(const uint16_t* __restrict__ X,
 }
 
 // Sum the workgroups' partial gradients (fixed order) into grad[NPARAM + 1]
-// (last entry: loss), then, if lr > 0, one Adam step on the FP32 master
-// parameters (moments m, v; step count t).
+// (last entry: loss, also added to the epoch's running sum *eloss), then, if
+// lr > 0, one Adam step on the FP32 master parameters (moments m, v; step
+// count t).  One thread per parameter.
 __global__ __launch_bounds__(256) void k_mlp_reduce_adam(const float* __restrict__ partial, int nblocks,
                                                          float* __restrict__ grad, float* __restrict__ P,
                                                          float* __restrict__ m, float* __restrict__ v, float lr,
-                                                         int t) {
+                                                         int t, double* __restrict__ eloss) {
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-  for (int k = threadIdx.x; k < MLP_NPARAM + 1; k += 256) {
-    float s = 0.f;
-    for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * (MLP_NPARAM + 1) + k];
-    grad[k] = s;
-    if (lr > 0.f && k < MLP_NPARAM) {
-      m[k] = b1 * m[k] + (1.f - b1) * s;
-      v[k] = b2 * v[k] + (1.f - b2) * s * s;
-      const float mh = m[k] / (1.f - powf(b1, (float)t));
-      const float vh = v[k] / (1.f - powf(b2, (float)t));
-      P[k] -= lr * mh / (sqrtf(vh) + eps);
-    }
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k > MLP_NPARAM) return;
+  float s = 0.f;
+  for (int b = 0; b < nblocks; ++b) s += partial[(long long)b * (MLP_NPARAM + 1) + k];
+  grad[k] = s;
+  if (k == MLP_NPARAM) {
+    *eloss += (double)s;
+  } else if (lr > 0.f) {
+    const float mk = b1 * m[k] + (1.f - b1) * s;
+    const float vk = b2 * v[k] + (1.f - b2) * s * s;
+    m[k] = mk;
+    v[k] = vk;
+    const float mh = mk / (1.f - powf(b1, (float)t));
+    const float vh = vk / (1.f - powf(b2, (float)t));
+    P[k] -= lr * mh / (sqrtf(vh) + eps);
   }
 }
 
 hipError_t launch_mlp_grad(const uint16_t* X, const uint8_t* y, const float* w, const int* idx, long long nb,
                            float Wsum, const float* P, float* partial, int nblocks, float* grad, float* Pmut,
-                           float* m, float* v, float lr, int t, hipStream_t st) {
+                           float* m, float* v, float lr, int t, double* eloss, hipStream_t st) {
   hipLaunchKernelGGL(k_mlp_grad, dim3(nblocks), dim3(GT), 0, st, X, y, w, idx, nb, Wsum, P, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_mlp_reduce_adam, dim3(1), dim3(256), 0, st, partial, nblocks, grad, Pmut, m, v, lr, t);
+  hipLaunchKernelGGL(k_mlp_reduce_adam, dim3((MLP_NPARAM + 1 + 255) / 256), dim3(256), 0, st, partial, nblocks, grad,
+                     Pmut, m, v, lr, t, eloss);
   return hipGetLastError();
 }
 
