@@ -56,6 +56,11 @@ HBM_PEAK_GBS = 8000.0
 # 2 x FETCH_SIZE.  Valid for the kernel as committed with that file; other
 # configurations report null.
 PMC_TRAFFIC = {"sweep_xi": {"fetch_kib": 1473148, "write_kib": 665600}}
+# The same for the xi Runge-Kutta hybrid sweeps of the ramp at 2048x256x256,
+# FP64 and FP32 split/reconstruction (profiles/ramp_headline_2048x256x256.md;
+# its 5.37 GB state copy gives the same factors).
+PMC_TRAFFIC_RAMP = {"fp64": {"fetch_kib": 16677702, "write_kib": 5242880},
+                    "mixed": {"fetch_kib": 17456205, "write_kib": 5242880}}
 
 
 def make_cases(n: int):
@@ -468,6 +473,9 @@ def headline_ramp(torch, pk, shape, train, epochs, steps, warmup, report=100):
                        "avg_launch_us": _prof_avg_us(prof),
                        "weno_frac_mean_over_turns": [round(v, 5) for v in mean_frac],
                        "roofline": _sweep_roofline(prof, c.N, mean_frac, c.precision == "mixed")}
+        if shape == (2048, 256, 256) and forms[name]["roofline"]["kernel"] == "sweep_xi":
+            t = PMC_TRAFFIC_RAMP["mixed" if c.precision == "mixed" else "fp64"]
+            forms[name]["roofline"]["traffic"] = 2 * t["fetch_kib"] * 1024 + t["write_kib"] * 1024
         _log(f"ramp{nx}x{ny}x{nz}: {name}: {forms[name]['gpt_substeps_per_s']} Gpt-substeps/s, "
              f"{forms[name]['avg_launch_us']}")
     for name in learned:
