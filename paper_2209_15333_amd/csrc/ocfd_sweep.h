@@ -65,7 +65,9 @@ void k_sweep(const SweepArgs A) {
   __shared__ double fh[(SW_S + 1) * FHS];  // fh[0]: carried flux; fh[s+1]: interface j0+s
   __shared__ double fh0[FHS];             // flux at 1/2, for node 0 of a periodic line
   __shared__ double cyb[FHS];             // carried flux of odd chunks (even chunks: fh[0])
-  __shared__ int wl_n;                    // hybrid: WENO work list of this chunk
+  // hybrid: this chunk's work list, WENO entries from the front (wl_n of them)
+  // and, in the FP32 xi sweeps, low-dissipation ones from the back (wl_l)
+  __shared__ int wl_n, wl_l;
   __shared__ short wl[SW_T];
   // the viscous flux of direction DIR of every ring node (FVR kernels in
   // viscous runs: [RING][4 * SW_W + 1] doubles, dynamic; zero bytes otherwise)
@@ -389,7 +391,10 @@ void k_sweep(const SweepArgs A) {
     EmitIn ein;
     if (!CHR && fin) ein = emit_load(jfin, gc);
     if (have) split_store(j0 + 4 + gs, gc, CHR ? fetch(j0 + 4 + gs, gc) : ahead);
-    if (HYB && t == 0) wl_n = 0;
+    if (HYB && t == 0) {
+      wl_n = 0;
+      wl_l = 0;
+    }
     __syncthreads();
     have = load && gcol_ok && c + 1 < nchunks && j0 + SW_S + 4 + gs <= mmax;
     if (!CHR && have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
@@ -398,19 +403,53 @@ void k_sweep(const SweepArgs A) {
     if (HYB) {
       const int kind = kflag;
       if (c + 1 < nchunks) kflag = flag_of(c + 1);
-      // Low-dissipation interfaces are done in place; WENO interfaces go to a
-      // work list so that whole waves run the WENO code (no divergence).
-      if (act) {
-        if (kind == 0)
-          reconstruct(j, rc, 0, fh + (rs + 1) * FHS + rc);
-        else
-          wl[atomicAdd(&wl_n, 1)] = (short)(t | (kind == 2 ? 512 : 0));
-      }
-      __syncthreads();
-      if (t < wl_n) {
-        const int tt = wl[t] & 511;
-        const int s2 = tt / SW_W, c2 = tt & (SW_W - 1);
-        reconstruct(j0 + s2, c2, (wl[t] & 512) ? 2 : 1, fh + (s2 + 1) * FHS + c2);
+      // The FP32 xi sweeps of bounded lines use one list for both kinds: the
+      // compiler then keeps that kernel at 136 registers (three waves per
+      // SIMD) instead of 195 (two), 9.5 -> 7.9 ms per Runge-Kutta sweep on the
+      // 2048 x 256 x 256 ramp at 0.63 WENO, 7.5 -> 7.0 ms at 0.003 (measured);
+      // the other sweeps are slower with it.
+      constexpr bool ONE_LIST = sizeof(R) == 4 && DIR == 0 && BND == 2;
+      if (!ONE_LIST) {
+        // Low-dissipation interfaces are done in place; WENO interfaces go to
+        // a work list so that whole waves run the WENO code (no divergence).
+        if (act) {
+          if (kind == 0)
+            reconstruct(j, rc, 0, fh + (rs + 1) * FHS + rc);
+          else
+            wl[atomicAdd(&wl_n, 1)] = (short)(t | (kind == 2 ? 512 : 0));
+        }
+        __syncthreads();
+        if (t < wl_n) {
+          const int tt = wl[t] & 511;
+          const int s2 = tt / SW_W, c2 = tt & (SW_W - 1);
+          reconstruct(j0 + s2, c2, (wl[t] & 512) ? 2 : 1, fh + (s2 + 1) * FHS + c2);
+        }
+      } else {
+        if (act) {
+          if (kind == 0)
+            wl[SW_T - 1 - atomicAdd(&wl_l, 1)] = (short)t;
+          else
+            wl[atomicAdd(&wl_n, 1)] = (short)(t | (kind == 2 ? 512 : 0));
+        }
+        __syncthreads();
+        if (wl_n < 64) {
+          // at most one wave of WENO interfaces: the low-dissipation ones in place
+          if (act && kind == 0) reconstruct(j, rc, 0, fh + (rs + 1) * FHS + rc);
+          if (t < wl_n) {
+            const int tt = wl[t] & 511;
+            const int s2 = tt / SW_W, c2 = tt & (SW_W - 1);
+            reconstruct(j0 + s2, c2, (wl[t] & 512) ? 2 : 1, fh + (s2 + 1) * FHS + c2);
+          }
+        } else {
+          // WENO entries from the front, low-dissipation ones from the back:
+          // whole waves run one kind (at most one wave holds both)
+          const bool weno = t < wl_n;
+          if (weno || t >= SW_T - wl_l) {
+            const int tt = wl[t] & 511;
+            const int s2 = tt / SW_W, c2 = tt & (SW_W - 1);
+            reconstruct(j0 + s2, c2, weno ? ((wl[t] & 512) ? 2 : 1) : 0, fh + (s2 + 1) * FHS + c2);
+          }
+        }
       }
     } else if (act) {
       reconstruct(j, rc, 1, fh + (rs + 1) * FHS + rc);

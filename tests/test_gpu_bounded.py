@@ -188,6 +188,33 @@ def test_bounded_mixed_precision_drift(pk, torch_cuda, orc):
     assert np.all(got[1:4, :, 0, :] == 0.0)
 
 
+@pytest.mark.parametrize("lowdiss", ["c8", "ud7"])
+def test_bounded_mixed_hybrid_drift(pk, torch_cuda, orc, lowdiss):
+    """FP32 split and reconstruction in the hybrid scheme on the ramp (the
+    bounded xi sweep takes its one-list path; its own pressure sensor marks a
+    ball of noise as WENO): 30 substeps stay within 1e-5 of the FP64 oracle."""
+    case = CASES["ramp"]()
+    case.scheme, case.lowdiss, case.precision = "hybrid", lowdiss, "mixed"
+    rng = np.random.default_rng(29)
+    k, j, i = np.meshgrid(*[np.arange(n) - n / 2 for n in (case.nz, case.ny, case.nx)], indexing="ij")
+    ball = np.exp(-(i * i + j * j) / (2.0 * 5.0 ** 2))
+    U0 = case.U0.copy()
+    U0[4] *= 1.0 + 0.05 * ball * rng.standard_normal(ball.shape)
+    case.U0 = U0
+    P = orc.params_from_case(case)
+    _, flags = orc.sensor(P, case.U0)
+    weno = (flags[0] != 0).mean()
+    print(f"ramp mixed hybrid {lowdiss}: xi WENO fraction of the first substep {weno:.3f}", flush=True)
+    assert 0.05 < weno < 0.95
+    s = _solver(pk, torch_cuda, case)
+    s.advance(30, case.dt)
+    got = s.state().cpu().numpy()
+    ref, _, _ = orc.advance(P, orc.metrics(P, case.xyz), case.U0, 30, case.dt, inflow=case.inflow)
+    l2, _ = rel_errors(got, ref)
+    print(f"ramp mixed hybrid {lowdiss} 30 substeps: rel L2 {l2}", flush=True)
+    assert np.all(l2 <= 1e-5)
+
+
 def test_bounded_call_order_errors(pk, torch_cuda):
     case = CASES["ramp"]()
     s = pk.Solver(pk.params_from(case))
