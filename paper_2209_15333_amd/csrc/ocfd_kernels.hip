@@ -60,10 +60,12 @@ hipError_t launch_pressure(const Geo& g, const Phys& ph, const double* U, double
 // Tile shapes (xi x eta columns of a workgroup of 256): 32 x 8 for the
 // viscous fluxes (their U ring is five values a node, so the smaller ring
 // pays) and for the eighth-order divergence; 64 x 4 for the sixth-order
-// divergence (measured on MI355X at 256^3 and on the ramp).
+// divergence (measured on MI355X at 256^3 and on the ramp).  At least three
+// waves per SIMD (168 registers, no spills): the eighth-order fluxes took
+// 8.09 ms at two waves and 7.44 ms at three on the 2048 x 256 x 256 ramp.
 
 template <int VH, int VT_X, int VT_Y>
-__global__ __launch_bounds__(256, 2) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ U,
+__global__ __launch_bounds__(256, 3) void k_visc_flux(const Geo g, const Phys ph, const double* __restrict__ U,
                                                    const double* __restrict__ met, double* __restrict__ Fv,
                                                    int ntx, int nty, int nseg, int zseg) {
   constexpr int ZW = 2 * VH + 1;          // planes of the zeta window
@@ -288,9 +290,9 @@ hipError_t launch_visc_flux(const Geo& g, const Phys& ph, const double* U, const
 // an LDS row patch (the tile plus VH columns each side), the eta fluxes from
 // an LDS column patch (the tile plus VH rows above and below, read from memory
 // one plane ahead into registers).  Same tile scheme and XCD numbering as
-// k_visc_flux.
+// k_visc_flux, and the same three waves per SIMD.
 template <int VH, int VT_X, int VT_Y>
-__global__ __launch_bounds__(256, 2) void k_visc_div(const Geo g, const Phys ph, const double* __restrict__ Fv,
+__global__ __launch_bounds__(256, 3) void k_visc_div(const Geo g, const Phys ph, const double* __restrict__ Fv,
                                                   double* __restrict__ rhs, int ntx, int nty, int nseg, int zseg) {
   constexpr int ZW = 2 * VH + 1;
   constexpr int SX = VT_Y * (VT_X + 2 * VH);   // one field of the xi patch
