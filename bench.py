@@ -168,6 +168,8 @@ def form_hit_learned(torch, pk, n, develop, every, substeps):
                      ("hybrid_learned_fp32", dict(precision="mixed", sensor="learned", sensor_every=1,
                                                   audit_every=50)),
                      ("hybrid_learned_fp32_every3", dict(precision="mixed", sensor="learned", sensor_every=3,
+                                                         audit_every=51)),
+                     ("hybrid_learned_fp32_every6", dict(precision="mixed", sensor="learned", sensor_every=6,
                                                          audit_every=51))):
         c = dataclasses.replace(case, **kw)
         rate, Uf, sv = _timed_run(torch, pk, c, U, substeps, setup=learned if c.sensor == "learned" else None)

@@ -50,9 +50,13 @@ constexpr int SW_S = 16;
 constexpr int SW_T = SW_W * SW_S;
 constexpr int RING = 32;
 
+// Occupancy floor: the FP64 characteristic kernels need it stated (two waves
+// per SIMD on bounded lines, three otherwise), or the compiler may go past
+// 256 registers and drop to one wave (measured: the bounded hybrid
+// Runge-Kutta one did, 10% slower).
 template <int DIR, int MODE, bool HYB, typename R, int BND, bool CHR>
 __global__ __launch_bounds__(SW_T) __attribute__((amdgpu_waves_per_eu(
-    (CHR && sizeof(R) == 8) ? (BND == 2 ? (HYB ? 1 : 2) : 3) : 1)))
+    (CHR && sizeof(R) == 8) ? (BND == 2 ? 2 : 3) : 1)))
 void k_sweep(const SweepArgs A) {
   constexpr int CD = (DIR == 0) ? 1 : 0;  // direction across the lines of the group
   constexpr int OD = (DIR == 2) ? 1 : 2;  // remaining direction
