@@ -595,7 +595,7 @@ def secondary_c2(torch, pk, n, steps, warmup):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1000, help="substeps timed per form on the headline workload")
+    ap.add_argument("--steps", type=int, default=500, help="substeps timed per form on the headline workload")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--shape", type=str, default="2048,256,256", help="headline ramp grid")
     ap.add_argument("--train-substeps", type=int, default=500)
