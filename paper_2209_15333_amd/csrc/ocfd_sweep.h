@@ -396,7 +396,7 @@ void k_sweep(const SweepArgs A) {
   // reading it again: 3-5% faster measured, where the FP64 sweeps lost more
   // to the ten extra registers than they gained.
   constexpr bool UROW = DIR == 0 && MODE == MODE_RK && !CHR && sizeof(R) == 4;
-  double uprev[5];
+  double uprev[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // read (and discarded) in the first chunk
   for (int c = 0; c < nchunks; ++c) {
     const int j0 = JB + c * SW_S;
     // the node this thread finishes in this chunk (periodic: node JB is
