@@ -41,10 +41,10 @@ FLOPS_DIFF = 10          # flux difference of the five components
 FLOPS_MODE = {"set": 0, "add": 5, "rk": 30}
 # The paper-style manual count (its Table 6 convention): Steger-Warming split
 # of a node, one WENO7 and one linear-stencil reconstruction, the RK update.
-FLOPS_SURVEY_SW = 140
-FLOPS_SURVEY_WENO = 200
-FLOPS_SURVEY_LOW = 15
-FLOPS_SURVEY_RK = 21
+FLOPS_COUNT_SW = 140
+FLOPS_COUNT_WENO = 200
+FLOPS_COUNT_LOW = 15
+FLOPS_COUNT_RK = 21
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3  # MI355X FP32 vector
 HBM_PEAK_GBS = 8000.0
@@ -301,8 +301,8 @@ def _sweep_roofline(prof, N, weno_frac, mixed, hybrid=True, viscous=True, last_d
     phi = float(weno_frac[d])
     rk = d == last_dir
     first = d == 2
-    flops = FLOPS_SURVEY_SW + 10 * (FLOPS_SURVEY_LOW + (FLOPS_SURVEY_WENO - FLOPS_SURVEY_LOW) * phi) + \
-        (FLOPS_SURVEY_RK if rk else 0)
+    flops = FLOPS_COUNT_SW + 10 * (FLOPS_COUNT_LOW + (FLOPS_COUNT_WENO - FLOPS_COUNT_LOW) * phi) + \
+        (FLOPS_COUNT_RK if rk else 0)
     design = FLOPS_PRIM + FLOPS_SW + phi * FLOPS_IFACE + (1.0 - phi) * FLOPS_IFACE_LOW + FLOPS_DIFF + \
         FLOPS_MODE["rk" if rk else "add"]
     vdiv = viscous and not hybrid and not mixed      # the first sweep adds onto the viscous divergence

@@ -436,7 +436,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
       }
     };
     // the next tile's inputs are loaded while the current one is evaluated;
-    // the last round of a wave reloads its own last tile (never past the end)
+    // the last iteration of a wave reloads its own last tile (never past the end)
     Tile cur, nxt;
     gather(wave, cur);
     for (long long T = wave; T < tiles; T += nwaves) {
@@ -492,13 +492,13 @@ hipError_t launch_mlp_prob(const uint16_t* X, long long S, const float* P, float
 // ---------------------------------------------------------------------------
 // Training: gradient of the weighted binary cross-entropy over a batch
 //   L = -sum_i w_i [y_i log p_i + (1 - y_i) log(1 - p_i)] / Wsum
-// A round takes 64 samples, 16 per wave.  Each wave runs the forward pass and
+// An iteration takes 64 samples, 16 per wave.  Each wave runs the forward pass and
 // the backward pass of its samples through the layers (16x16x32 MFMAs with
 // the transposed weights) and stages its inputs, hidden activations and
 // pre-activation gradients as [unit][sample] bf16 rows in LDS.  Then the
 // weight gradients dW[in][out] = sum_s act[in][s] delta[out][s] are forty
 // 16x16 tiles (W1 8, W2 16, W3 16), ten per wave, each an MFMA chain over the
-// round's 64 samples (4 x 16x16x16).  Bias, output-layer and loss terms are
+// iteration's 64 samples (4 x 16x16x16).  Bias, output-layer and loss terms are
 // per-lane sums.  Every workgroup writes its partial gradient;
 // k_mlp_reduce_adam sums them in a fixed order (deterministic).
 // ---------------------------------------------------------------------------
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(GT) void k_mlp_grad(const uint16_t* __restrict__ X,
   float gb1[4][4] = {}, gb2[4][4] = {}, gb3[4][4] = {}, gw4[4][4] = {};
   float gb4 = 0.f, loss = 0.f;
   const v4f zero = {0.f, 0.f, 0.f, 0.f};
-  // Every wave runs the same number of rounds (barriers below are block-wide);
+  // Every wave runs the same number of iterations (barriers below are block-wide);
   // a wave past the last tile works on sample 0 with zero weight.
   const long long tiles = (nb + 15) / 16;
   for (long long T0 = (long long)blockIdx.x * 4; T0 < tiles; T0 += (long long)gridDim.x * 4) {
@@ -780,7 +780,7 @@ __global__ __launch_bounds__(CT) void k_collect_write(const Geo g, const uint8_t
     const bool kp = in && keep_interface(g, seed, d, id, flags[in ? k : 0], thr_pos, thr_neg);
     sc[threadIdx.x] = kp ? 1 : 0;
     __syncthreads();
-    // exclusive prefix of this round (serial in one thread: 256 entries)
+    // exclusive prefix of this pass (serial in one thread: 256 entries)
     if (threadIdx.x == 0) {
       int s = 0;
       for (int i = 0; i < CT; ++i) {
