@@ -21,6 +21,9 @@ typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef __bf16 v4bf __attribute__((ext_vector_type(4)));
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v2s __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ int wrapn(int p, int n) {
   while (p < 0) p += n;
@@ -336,12 +339,25 @@ __device__ __forceinline__ float relu(float a) { return __int_as_float(max(__flo
 
 // B operand of K-chunk c from C tiles 2c, 2c+1 (the relabelling above), of
 // v (relu when relu is set).
+// The ReLU is taken after the rounding, on the packed bf16 values (a
+// negative bf16 is a negative int16): the same bits, half the instructions.
 __device__ __forceinline__ v8bf chunk_b(const v4f* v, int c, bool use_relu) {
-  v8bf b;
-  for (int q = 0; q < 8; ++q) {
-    const float a = q < 4 ? v[2 * c][q] : v[2 * c + 1][q - 4];
-    b[q] = (__bf16)(use_relu ? relu(a) : a);
+  unsigned w[4];
+  for (int k = 0; k < 4; ++k) {
+    const v4f& t = v[2 * c + k / 2];
+    const v2bf p = __builtin_convertvector((v2f){t[2 * (k & 1)], t[2 * (k & 1) + 1]}, v2bf);
+    __builtin_memcpy(&w[k], &p, 4);
   }
+  if (use_relu) {
+    for (int k = 0; k < 4; ++k) {
+      v2s h;
+      __builtin_memcpy(&h, &w[k], 4);
+      h = __builtin_elementwise_max(h, (v2s)0);
+      __builtin_memcpy(&w[k], &h, 4);
+    }
+  }
+  v8bf b;
+  __builtin_memcpy(&b, w, 16);
   return b;
 }
 
