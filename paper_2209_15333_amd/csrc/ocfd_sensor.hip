@@ -395,11 +395,11 @@ __device__ __forceinline__ float sigmoidf(float z) { return __builtin_amdgcn_rcp
 // index, a periodic wrap is one conditional add, and the gather has no
 // branch: the next tile's loads stay in flight while the current tile is
 // evaluated (a load behind a branch makes the compiler wait for every load
-// before the first MFMA).  Three waves per SIMD (168 registers, a few
-// spilled outside the loop): 1.27 ms against 1.59 ms at two waves for
-// 50.3 M interfaces, measured.
+// before the first MFMA).  The fast path runs three waves per SIMD (no
+// spills): 1.27 ms against 1.59 ms at two waves for 50.3 M interfaces,
+// measured; the general one two.
 template <bool FAST>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_mlp_flags(const Geo g, const uint2* __restrict__ feat,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FAST ? 3 : 2))) void k_mlp_flags(const Geo g, const uint2* __restrict__ feat,
                                                    const float* __restrict__ P, const Tau3 tau,
                                                    uint8_t* __restrict__ flags) {
   __shared__ __align__(16) float lb[LB_N];
