@@ -38,13 +38,6 @@ namespace ocfd {
 // back by S^-1.  A linear stencil commutes with the fixed S, so the hybrid's
 // low-dissipation interfaces skip the two products (an exact identity).
 
-// Lane i of each row of 16 lanes takes the value of lane (i - 4) mod 16.
-__device__ __forceinline__ double row_ror4(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x124, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x124, 0xf, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-
 constexpr int SW_W = 16;
 constexpr int SW_S = 16;
 constexpr int SW_T = SW_W * SW_S;
@@ -275,9 +268,30 @@ void k_sweep(const SweepArgs A) {
   }
   // Characteristic kernels fetch each chunk's nodes when they split them
   // instead of one chunk ahead: the registers go to the longer reconstruction.
-  NodeIn ahead;
-  bool have = load && gcol_ok && JB + 4 + gs <= mmax;
-  if (!CHR && have) ahead = fetch(JB + 4 + gs, gc);
+  // The xi sweeps with JB = 0 split nodes 16c + 4 .. 16c + 19 in chunk c,
+  // which straddle two 128-byte lines of every array; loaded that way, the
+  // second half of each line is evicted from L2 before the next chunk reads
+  // it and is fetched again.  The FP32 ones, and the FP64 hybrid ones of
+  // periodic lines, load whole aligned 16-node blocks instead: blk holds
+  // block c (node 16c + gs of this lane), ahead block c + 1; lanes 4..15
+  // split their node of block c, lanes 0..3 theirs of block c + 1.  Measured
+  // per Runge-Kutta xi sweep: FP32 hybrid 7.68 -> 7.16 ms on the developed
+  // 2048 x 256 x 256 ramp, 825 -> 759 us on 256^3 turbulence, FP64 hybrid
+  // there 866 -> 838 us; the other FP64 kernels lost to the 24 extra
+  // registers (the bounded hybrid one 9.70 -> 9.96 ms, the periodic WENO7
+  // one 798 -> 891 us, down to two waves per SIMD).
+  constexpr bool ALN = DIR == 0 && !CHR && (BND == 2 || JBP == 0) && (sizeof(R) == 4 || (HYB && BND != 2));
+  NodeIn ahead, blk;
+  bool have, have_blk = false;
+  if (ALN) {
+    have_blk = load && gcol_ok && gs <= mmax;
+    if (have_blk) blk = fetch(gs, gc);
+    have = load && gcol_ok && SW_S + gs <= mmax;
+    if (have) ahead = fetch(SW_S + gs, gc);
+  } else {
+    have = load && gcol_ok && JB + 4 + gs <= mmax;
+    if (!CHR && have) ahead = fetch(JB + 4 + gs, gc);
+  }
   // Hybrid: the flag of the interface this thread reconstructs in chunk c is
   // loaded during chunk c - 1, after that chunk's prefetch, so waiting for
   // it never waits for the prefetch (loads complete in issue order).
@@ -390,13 +404,10 @@ void k_sweep(const SweepArgs A) {
     }
   };
 
-  // The FP32 xi Runge-Kutta sweeps take U of the node they finish from the
-  // lane that loaded it for the split (four lanes back in the same row of 16,
-  // in this chunk or, for the first four nodes, the previous one) instead of
-  // reading it again: 3-5% faster measured, where the FP64 sweeps lost more
-  // to the ten extra registers than they gained.
-  constexpr bool UROW = DIR == 0 && MODE == MODE_RK && !CHR && sizeof(R) == 4;
-  double uprev[5] = {0.0, 0.0, 0.0, 0.0, 0.0};   // read (and discarded) in the first chunk
+  // The xi Runge-Kutta sweeps with aligned blocks take U of the node they
+  // finish (node 16c + gs) from the block this lane loaded for the split
+  // instead of reading it again.
+  constexpr bool UROW = ALN && MODE == MODE_RK;
   for (int c = 0; c < nchunks; ++c) {
     const int j0 = JB + c * SW_S;
     // the node this thread finishes in this chunk (periodic: node JB is
@@ -406,27 +417,34 @@ void k_sweep(const SweepArgs A) {
     const int jfin = per ? (n >= 8 ? wrap1(jraw, n) : wrap(jraw, n)) : jraw;
     // characteristic kernels load the finishing step's inputs just before it,
     // which keeps 32 registers free through the longer reconstruction
-    const bool urow = UROW && load && c > 0;
+    const bool urow = UROW && load;
     EmitIn ein;
     if (!CHR && fin) ein = emit_load(jfin, gc, !urow);
-    if (UROW && load) {
-      double ucur[5];
+    if (ALN) {
+      // a finished node is loaded (j0 + gs <= mmax) wherever fin holds
+      if (urow) {
 #pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        ucur[q] = ahead.U[q];   // node j0 + 4 + gs (valid wherever a finished node needs it)
-        const double from_cur = row_ror4(ucur[q]), from_prev = row_ror4(uprev[q]);
-        if (urow) ein.u[q] = gs >= 4 ? from_cur : from_prev;
-        uprev[q] = ucur[q];
+        for (int q = 0; q < 5; ++q) ein.u[q] = blk.U[q];
       }
+      const bool lo = gs < 4;
+      if (lo ? have : have_blk) split_store(j0 + gs + (lo ? SW_S : 0), gc, lo ? ahead : blk);
+    } else if (have) {
+      split_store(j0 + 4 + gs, gc, CHR ? fetch(j0 + 4 + gs, gc) : ahead);
     }
-    if (have) split_store(j0 + 4 + gs, gc, CHR ? fetch(j0 + 4 + gs, gc) : ahead);
     if (HYB && t == 0) {
       wl_n = 0;
       wl_l = 0;
     }
     __syncthreads();
-    have = load && gcol_ok && c + 1 < nchunks && j0 + SW_S + 4 + gs <= mmax;
-    if (!CHR && have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
+    if (ALN) {
+      blk = ahead;
+      have_blk = have;
+      have = load && gcol_ok && j0 + 2 * SW_S + gs <= mmax;
+      if (have) ahead = fetch(j0 + 2 * SW_S + gs, gc);
+    } else {
+      have = load && gcol_ok && c + 1 < nchunks && j0 + SW_S + 4 + gs <= mmax;
+      if (!CHR && have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
+    }
     const int j = j0 + rs;
     const bool act = A.inviscid && rcol_ok && c * SW_S + rs < nif;
     if (HYB) {
