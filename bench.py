@@ -59,8 +59,8 @@ PMC_TRAFFIC = {"sweep_xi": {"fetch_kib": 1473148, "write_kib": 665600}}
 # The same for the xi Runge-Kutta hybrid sweeps of the ramp at 2048x256x256,
 # FP64 and FP32 split/reconstruction (profiles/ramp_headline_2048x256x256.md;
 # its 5.37 GB state copy gives the same factors).
-PMC_TRAFFIC_RAMP = {"fp64": {"fetch_kib": 16390997, "write_kib": 5242880},
-                    "mixed": {"fetch_kib": 16541963, "write_kib": 5242880}}
+PMC_TRAFFIC_RAMP = {"fp64": {"fetch_kib": 15979708, "write_kib": 5242880},
+                    "mixed": {"fetch_kib": 11954710, "write_kib": 5242880}}
 
 
 def make_cases(n: int):
