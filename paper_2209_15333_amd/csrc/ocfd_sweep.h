@@ -42,14 +42,29 @@ constexpr int SW_W = 16;
 constexpr int SW_S = 16;
 constexpr int SW_T = SW_W * SW_S;
 constexpr int RING = 32;
+// Ring slots of a kernel: the FP32 eta and zeta sweeps of lines that are
+// not bounded keep 24 (a chunk reads the 23 nodes j0 - 3 .. j0 + 19 and
+// finishes with the viscous fluxes of j0 - 4 .. j0 + 19), which with their
+// 24-slot viscous-flux ring brings a workgroup under 40 KB of LDS: four
+// workgroups per CU instead of three, within 128 registers without spills.
+// Measured: zeta sweep of the developed 2048 x 256 x 256 ramp 6.06 -> 5.44
+// ms, eta and zeta at 256^3 2-4% faster.  The bounded ones need 137
+// registers: forced to 128 they spill (eta of the ramp 6.19 -> 6.52 ms), at
+// three waves the slot arithmetic costs 1.6%, so they keep 32 slots, and so
+// do the WENO7 Runge-Kutta ones (they too would spill).
+template <int DIR, int MODE, bool HYB, typename R, int BND, bool CHR>
+constexpr int ring_slots() {
+  return (sizeof(R) == 4 && DIR != 0 && !CHR && BND != 2 && (HYB || MODE != MODE_RK)) ? 24 : RING;
+}
 
 // Occupancy floor: the FP64 characteristic kernels need it stated (two waves
 // per SIMD on bounded lines, three otherwise), or the compiler may go past
 // 256 registers and drop to one wave (measured: the bounded hybrid
-// Runge-Kutta one did, 10% slower).
+// Runge-Kutta one did, 10% slower); the 24-slot sweeps ask for the four
+// waves their LDS allows.
 template <int DIR, int MODE, bool HYB, typename R, int BND, bool CHR>
 __global__ __launch_bounds__(SW_T) __attribute__((amdgpu_waves_per_eu(
-    (CHR && sizeof(R) == 8) ? (BND == 2 ? 2 : 3) : 1)))
+    (CHR && sizeof(R) == 8) ? (BND == 2 ? 2 : 3) : (ring_slots<DIR, MODE, HYB, R, BND, CHR>() == 24 ? 4 : 1))))
 void k_sweep(const SweepArgs A) {
   constexpr int CD = (DIR == 0) ? 1 : 0;  // direction across the lines of the group
   constexpr int OD = (DIR == 2) ? 1 : 2;  // remaining direction
@@ -59,13 +74,23 @@ void k_sweep(const SweepArgs A) {
   constexpr int SLOT = NVAL * SW_W + 1;   // padded against bank conflicts
   constexpr int FHS = 5 * SW_W + 1;
   constexpr int FVS = 4 * SW_W + 1;
-  // Viscous-flux neighbours staged in an LDS ring (16.6 KB per workgroup):
+  // Viscous-flux neighbours staged in an LDS ring (16.6 KB per workgroup, 12.5
+  // KB with 24 slots):
   // the FP32 and hybrid sweeps add the derivative of the viscous fluxes of
   // their direction in the finishing step; the FP64 WENO7 sweep keeps three
   // workgroups per CU instead and has no viscous code (a separate kernel
   // writes the viscous divergence it accumulates onto).
   constexpr bool FVR = HYB || sizeof(R) == 4;
-  __shared__ R ring[RING * SLOT];
+  constexpr int NR = ring_slots<DIR, MODE, HYB, R, BND, CHR>();
+  // slot of node m (m >= -8: the prologue and the viscous neighbours of a
+  // periodic line reach 8 nodes before its first)
+  auto slot = [](int m) -> int {
+    if constexpr (NR == 32)
+      return m & 31;
+    else
+      return (int)((unsigned)(m + 48) % 24u);
+  };
+  __shared__ R ring[NR * SLOT];
   __shared__ double fh[(SW_S + 1) * FHS];  // fh[0]: carried flux; fh[s+1]: interface j0+s
   __shared__ double fh0[FHS];             // flux at 1/2, for node 0 of a periodic line
   __shared__ double cyb[FHS];             // carried flux of odd chunks (even chunks: fh[0])
@@ -74,7 +99,7 @@ void k_sweep(const SweepArgs A) {
   __shared__ int wl_n, wl_l;
   __shared__ short wl[SW_T];
   // the viscous flux of direction DIR of every ring node (FVR kernels in
-  // viscous runs: [RING][4 * SW_W + 1] doubles, dynamic; zero bytes otherwise)
+  // viscous runs: [ring slots][4 * SW_W + 1] doubles, dynamic; zero bytes otherwise)
   extern __shared__ double fvr[];
 
   const int n = A.g.n[DIR];
@@ -129,15 +154,15 @@ void k_sweep(const SweepArgs A) {
       const double p = A.ph.gm1 * (in.U[4] - 0.5 * rho * (u * u + v * v + w * w));
       R fp[5], fm[5];
       sw_split<R>(A.ph, (R)rho, (R)ir, (R)u, (R)v, (R)w, (R)p, (R)in.a[0], (R)in.a[1], (R)in.a[2], fp, fm);
-      R* slot = ring + (m & (RING - 1)) * SLOT + col;
+      R* sl = ring + slot(m) * SLOT + col;
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        slot[q * SW_W] = fp[q];
-        slot[(5 + q) * SW_W] = fm[q];
+        sl[q * SW_W] = fp[q];
+        sl[(5 + q) * SW_W] = fm[q];
       }
     }
     if (FVR && A.viscous) {
-      double* fs = fvr + (m & (RING - 1)) * FVS + col;
+      double* fs = fvr + slot(m) * FVS + col;
 #pragma unroll
       for (int q = 0; q < 4; ++q) fs[q * SW_W] = in.fv[q];
     }
@@ -189,7 +214,7 @@ void k_sweep(const SweepArgs A) {
     if (FVR && A.viscous && inv) {
       // F(q, k): component q of the viscous flux at node jr + k
       auto F = [&](int q, int k) {
-        if (ringfv) return fvr[((jr + k) & (RING - 1)) * FVS + q * SW_W + col];
+        if (ringfv) return fvr[slot(jr + k) * FVS + q * SW_W + col];
         const int p = j + k;
         const int w = per ? (n >= 8 ? wrap1(p, n) : wrap(p, n)) : p;
         return A.Fv[(long long)(4 * DIR + q) * N + id + (long long)(w - j) * sd];
@@ -318,7 +343,7 @@ void k_sweep(const SweepArgs A) {
     fr.init(A.ph, Ua, a);
     // characteristic values of node j + o of the f+ (sg 0) or f- (sg 1) ring
     auto proj = [&](int sg, int o, R* w) {
-      const R* B = ring + col + sg * 5 * SW_W + ((j + o) & (RING - 1)) * SLOT;
+      const R* B = ring + col + sg * 5 * SW_W + slot(j + o) * SLOT;
       R f[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) f[q] = B[q * SW_W];
@@ -372,8 +397,8 @@ void k_sweep(const SweepArgs A) {
     for (int q = 0; q < 5; ++q) {
       const R* P = ring + col + q * SW_W;
       const R* M = ring + col + (5 + q) * SW_W;
-#define RP(o) P[((j + (o)) & (RING - 1)) * SLOT]
-#define RM(o) M[((j + (o)) & (RING - 1)) * SLOT]
+#define RP(o) P[slot(j + (o)) * SLOT]
+#define RM(o) M[slot(j + (o)) * SLOT]
       double F;
       if (!per && (j < 3 || j > n - 5)) {
         // stencil leaves the domain: masked WENO5 (out-of-domain values
@@ -529,19 +554,25 @@ void k_sweep(const SweepArgs A) {
 }
 
 // Dynamic LDS: the viscous-flux ring of the FP32 and hybrid kernels.
+template <int DIR, int MODE, bool HYB, typename R, int BND, bool CHR>
+static void launch_sweep_k(const SweepArgs& a, dim3 grid, hipStream_t st) {
+  const size_t lds = (a.viscous && (a.mixed || a.hybrid))
+                         ? (size_t)ring_slots<DIR, MODE, HYB, R, BND, CHR>() * (4 * SW_W + 1) * sizeof(double)
+                         : 0;
+  hipLaunchKernelGGL((k_sweep<DIR, MODE, HYB, R, BND, CHR>), grid, dim3(SW_T), lds, st, a);
+}
 template <int DIR, int MODE, int BND, bool CHR>
 static void launch_sweep_b(const SweepArgs& a, dim3 grid, hipStream_t st) {
-  const size_t lds = (a.viscous && (a.mixed || a.hybrid)) ? (size_t)RING * (4 * SW_W + 1) * sizeof(double) : 0;
   if (a.mixed) {
     if (a.hybrid)
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, float, BND, CHR>), grid, dim3(SW_T), lds, st, a);
+      launch_sweep_k<DIR, MODE, true, float, BND, CHR>(a, grid, st);
     else
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, float, BND, CHR>), grid, dim3(SW_T), lds, st, a);
+      launch_sweep_k<DIR, MODE, false, float, BND, CHR>(a, grid, st);
   } else {
     if (a.hybrid)
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, true, double, BND, CHR>), grid, dim3(SW_T), lds, st, a);
+      launch_sweep_k<DIR, MODE, true, double, BND, CHR>(a, grid, st);
     else
-      hipLaunchKernelGGL((k_sweep<DIR, MODE, false, double, BND, CHR>), grid, dim3(SW_T), lds, st, a);
+      launch_sweep_k<DIR, MODE, false, double, BND, CHR>(a, grid, st);
   }
 }
 
