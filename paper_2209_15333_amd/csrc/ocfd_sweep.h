@@ -476,8 +476,9 @@ void k_sweep(const SweepArgs A) {
       const int kind = kflag;
       if (c + 1 < nchunks) kflag = flag_of(c + 1);
       // The FP32 xi sweeps of bounded lines use one list for both kinds: the
-      // compiler then keeps that kernel at 136 registers (three waves per
-      // SIMD) instead of 195 (two), 9.5 -> 7.9 ms per Runge-Kutta sweep on the
+      // compiler then keeps that kernel within three waves per SIMD (136
+      // registers then, 162 with the aligned block loads) instead of 195
+      // registers and two, 9.5 -> 7.9 ms per Runge-Kutta sweep on the
       // 2048 x 256 x 256 ramp at 0.63 WENO, 7.5 -> 7.0 ms at 0.003 (measured);
       // the other sweeps are slower with it.
       constexpr bool ONE_LIST = sizeof(R) == 4 && DIR == 0 && BND == 2;
