@@ -34,14 +34,20 @@ def _run(pk, case, n):
     return s.state().cpu().numpy(), r0, r1
 
 
-@pytest.mark.parametrize("which", ["tgv32", "vortex", "tgv-hybrid"])
+# tgv-hybrid-ragged: every line length leaves a partial last chunk of 16
+# nodes (36 = 2 x 16 + 4 along xi, whose Runge-Kutta sweep loads whole
+# aligned blocks); tgv-narrow: fewer xi nodes than one chunk
+@pytest.mark.parametrize("which", ["tgv32", "vortex", "tgv-hybrid", "tgv-hybrid-ragged", "tgv-narrow"])
 def test_mixed_drift_vs_fp64_oracle(pk, orc, which):
     if which == "tgv32":
         case = workloads.taylor_green(32)
     elif which == "vortex":
         case = workloads.isentropic_vortex(shape=(48, 40, 8), distorted=True, dt=0.02)
+    elif which == "tgv-narrow":
+        case = workloads.taylor_green(shape=(12, 24, 20), distorted=True, dt=1e-3)
     else:
-        case = workloads.taylor_green(shape=(32, 24, 20), distorted=True, dt=1e-3)
+        shape = (32, 24, 20) if which == "tgv-hybrid" else (36, 20, 12)
+        case = workloads.taylor_green(shape=shape, distorted=True, dt=1e-3)
         case.scheme = "hybrid"
     P = orc.params_from_case(case)
     met = orc.metrics(P, case.xyz)
