@@ -42,19 +42,22 @@ constexpr int SW_W = 16;
 constexpr int SW_S = 16;
 constexpr int SW_T = SW_W * SW_S;
 constexpr int RING = 32;
-// Ring slots of a kernel: the FP32 eta and zeta sweeps of lines that are
-// not bounded keep 24 (a chunk reads the 23 nodes j0 - 3 .. j0 + 19 and
-// finishes with the viscous fluxes of j0 - 4 .. j0 + 19), which with their
-// 24-slot viscous-flux ring brings a workgroup under 40 KB of LDS: four
-// workgroups per CU instead of three, within 128 registers without spills.
-// Measured: zeta sweep of the developed 2048 x 256 x 256 ramp 6.06 -> 5.44
-// ms, eta and zeta at 256^3 2-4% faster.  The bounded ones need 137
-// registers: forced to 128 they spill (eta of the ramp 6.19 -> 6.52 ms), at
-// three waves the slot arithmetic costs 1.6%, so they keep 32 slots, and so
-// do the WENO7 Runge-Kutta ones (they too would spill).
+// Ring slots of a kernel: the FP32 eta and zeta sweeps keep 24 (a chunk
+// reads the 23 nodes j0 - 3 .. j0 + 19 and finishes with the viscous fluxes
+// of j0 - 4 .. j0 + 19), which with their 24-slot viscous-flux ring brings a
+// workgroup under 40 KB of LDS: four workgroups per CU instead of three,
+// within 128 registers without spills.  On bounded lines that needs the
+// loads of each chunk's nodes issued when they are split rather than one
+// chunk ahead (with the prefetch they took 137 registers and spilled at
+// 128), and holds for the first and summing sweeps only.  Measured on the
+// developed 2048 x 256 x 256 ramp: zeta (periodic span) 6.06 -> 5.44 ms, eta
+// (bounded) 6.01 -> 5.41 ms; eta and zeta at 256^3 2-4% faster.  The WENO7
+// Runge-Kutta ones of periodic lines, and the Runge-Kutta and dU/dt ones of
+// bounded lines, would spill too: they keep 32 slots and three workgroups.
 template <int DIR, int MODE, bool HYB, typename R, int BND, bool CHR>
 constexpr int ring_slots() {
-  return (sizeof(R) == 4 && DIR != 0 && !CHR && BND != 2 && (HYB || MODE != MODE_RK)) ? 24 : RING;
+  return (sizeof(R) == 4 && DIR != 0 && !CHR &&
+          (BND != 2 ? (HYB || MODE != MODE_RK) : (MODE == MODE_SET || MODE == MODE_ADD))) ? 24 : RING;
 }
 
 // Occupancy floor: the FP64 characteristic kernels need it stated (two waves
@@ -291,8 +294,9 @@ void k_sweep(const SweepArgs A) {
     const int m = JB + pm - 3;
     if (col0 + pc < ncol && (per || (m >= 0 && m < n))) split_store(m, pc, fetch(m, pc));
   }
-  // Characteristic kernels fetch each chunk's nodes when they split them
-  // instead of one chunk ahead: the registers go to the longer reconstruction.
+  // Characteristic kernels, and the 24-slot sweeps of bounded lines, fetch
+  // each chunk's nodes when they split them instead of one chunk ahead: the
+  // registers go to the longer reconstruction, or to the fourth wave.
   // The xi sweeps with JB = 0 split nodes 16c + 4 .. 16c + 19 in chunk c,
   // which straddle two 128-byte lines of every array; loaded that way, the
   // second half of each line is evicted from L2 before the next chunk reads
@@ -305,6 +309,7 @@ void k_sweep(const SweepArgs A) {
   // there 866 -> 838 us; the other FP64 kernels lost to the 24 extra
   // registers (the bounded hybrid one 9.70 -> 9.96 ms, the periodic WENO7
   // one 798 -> 891 us, down to two waves per SIMD).
+  constexpr bool NOPF = CHR || (NR == 24 && BND == 2);
   constexpr bool ALN = DIR == 0 && !CHR && (BND == 2 || JBP == 0) && (sizeof(R) == 4 || (HYB && BND != 2));
   NodeIn ahead, blk;
   bool have, have_blk = false;
@@ -315,7 +320,7 @@ void k_sweep(const SweepArgs A) {
     if (have) ahead = fetch(SW_S + gs, gc);
   } else {
     have = load && gcol_ok && JB + 4 + gs <= mmax;
-    if (!CHR && have) ahead = fetch(JB + 4 + gs, gc);
+    if (!NOPF && have) ahead = fetch(JB + 4 + gs, gc);
   }
   // Hybrid: the flag of the interface this thread reconstructs in chunk c is
   // loaded during chunk c - 1, after that chunk's prefetch, so waiting for
@@ -454,7 +459,7 @@ void k_sweep(const SweepArgs A) {
       const bool lo = gs < 4;
       if (lo ? have : have_blk) split_store(j0 + gs + (lo ? SW_S : 0), gc, lo ? ahead : blk);
     } else if (have) {
-      split_store(j0 + 4 + gs, gc, CHR ? fetch(j0 + 4 + gs, gc) : ahead);
+      split_store(j0 + 4 + gs, gc, NOPF ? fetch(j0 + 4 + gs, gc) : ahead);
     }
     if (HYB && t == 0) {
       wl_n = 0;
@@ -468,7 +473,7 @@ void k_sweep(const SweepArgs A) {
       if (have) ahead = fetch(j0 + 2 * SW_S + gs, gc);
     } else {
       have = load && gcol_ok && c + 1 < nchunks && j0 + SW_S + 4 + gs <= mmax;
-      if (!CHR && have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
+      if (!NOPF && have) ahead = fetch(j0 + SW_S + 4 + gs, gc);
     }
     const int j = j0 + rs;
     const bool act = A.inviscid && rcol_ok && c * SW_S + rs < nif;
